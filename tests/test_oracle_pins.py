@@ -1,0 +1,345 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+Nothing here re-types the oracle's formulas: the expected values come from the
+paper's printed examples (``tests/golden/``), from closed forms, from a
+set-based brute force that never uses the digit arithmetic of rho, and from
+invariants of the prime-implicant set.
+"""
+import itertools
+import math
+import os
+import random
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2302_10083_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def both_oracles(n, tt):
+    """(M, O) as sets from the definitional enumerator and from brute force;
+    asserts they agree."""
+    M2, O2, _ = oracle.primes(n, tt)
+    M1, O1 = oracle.bruteforce(n, tt)
+    assert np.array_equal(M1, M2), "brute force and enumerator disagree on M"
+    assert np.array_equal(O1, O2), "brute force and enumerator disagree on O"
+    return oracle.bitmap_to_set(n, M2), oracle.bitmap_to_set(n, O2)
+
+
+def strings(n, rhos):
+    return sorted(oracle.string_of(n, r) for r in rhos)
+
+
+# ----------------------------------------------------------------------------
+# paper's printed examples
+
+
+def _read_golden(name):
+    rows = []
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                rows.append(line.split())
+    return rows
+
+
+def test_majority_example():
+    rows = _read_golden("maj3.txt")
+    n = int(rows[0][1])
+    expected = sorted(r[1] for r in rows if r[0] == "prime")
+    tt = inputs.interval(n, 2, n)  # majority of 3: at least two ones
+    M, O = both_oracles(n, tt)
+    assert strings(n, O) == expected
+    # the minterms of Maj plus the three primes are all the implicants
+    minterms = {"110", "101", "011", "111"}
+    assert set(strings(n, M)) == minterms | set(expected)
+
+
+def test_string_examples():
+    rows = _read_golden("string_examples.txt")
+    # x_1 x_3' for n = 5
+    n = int(rows[0][1])
+    prod = rows[1][1]
+    care = sum(1 << i for i, c in enumerate(prod) if c != "*")
+    val = sum(1 << i for i, c in enumerate(prod) if c == "1")
+    assert care == 0b00101 and val == 0b00001  # literals on x_1 (positive), x_3 (negated)
+    tt = inputs.from_terms(n, [(care, val)])
+    _, O = both_oracles(n, tt)
+    assert strings(n, O) == [prod]
+    # 0011* + 0111* = 0*11*
+    n = int(rows[2][1])
+    a, b = rows[3][1], rows[3][2]
+    merged = rows[4][1]
+    terms = []
+    for s in (a, b):
+        terms.append((sum(1 << i for i, c in enumerate(s) if c != "*"),
+                      sum(1 << i for i, c in enumerate(s) if c == "1")))
+    tt = inputs.from_terms(n, terms)
+    M, O = both_oracles(n, tt)
+    assert strings(n, O) == [merged]
+    assert oracle.rho_of(a) in M and oracle.rho_of(b) in M
+
+
+@pytest.mark.parametrize("n", list(range(0, 9)))
+def test_constant_one_only_allstar_prime(n):
+    rows = _read_golden("constant_one.txt")
+    assert rows[1][1] == "all-star"
+    M, O = both_oracles(n, inputs.constant(n, 1))
+    assert M == set(range(3**n))
+    assert O == {3**n - 1}
+    assert strings(n, O) == ["*" * n]
+
+
+@pytest.mark.parametrize("n", [10, 12])
+def test_constant_one_enum_larger(n):
+    M, O, lst = oracle.primes(n, inputs.constant(n, 1))
+    assert int(np.bitwise_count(M).sum()) == 3**n
+    assert lst.tolist() == [3**n - 1]
+
+
+@pytest.mark.parametrize("n", list(range(0, 9)))
+def test_constant_zero_no_primes(n):
+    M, O = both_oracles(n, inputs.constant(n, 0))
+    assert M == set() and O == set()
+
+
+# ----------------------------------------------------------------------------
+# set-based brute force: cubes as sets of minterms, no rho digit arithmetic
+
+
+def _cube_minterm_sets(n):
+    """For every string s in {0,1,*}^n (s_1 first), the frozenset of the x it
+    covers, where x_i = bit i-1 of x."""
+    out = {}
+    for s in itertools.product("01*", repeat=n):
+        choices = [(0,) if c == "0" else (1,) if c == "1" else (0, 1) for c in s]
+        xs = frozenset(sum(b << i for i, b in enumerate(bits)) for bits in itertools.product(*choices))
+        out["".join(s)] = xs
+    return out
+
+
+def _setwise_primes(n, support, cubes):
+    impl = {s for s, xs in cubes.items() if xs <= support}
+    primes = {s for s in impl if not any(cubes[s] < cubes[t] for t in impl)}
+    return impl, primes
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 3])
+def test_all_functions_small_n_vs_setwise(n):
+    cubes = _cube_minterm_sets(n)
+    for f in range(1 << (1 << n)):
+        support = frozenset(x for x in range(1 << n) if (f >> x) & 1)
+        bits = np.array([(f >> x) & 1 for x in range(1 << n)], dtype=bool)
+        tt = inputs.from_bits(n, bits)
+        impl, primes = _setwise_primes(n, support, cubes)
+        M, O = both_oracles(n, tt)
+        assert strings(n, M) == sorted(impl), f
+        assert strings(n, O) == sorted(primes), f
+
+
+def test_random_functions_n4_n5_vs_setwise():
+    rng = random.Random(4)
+    for n, count in ((4, 120), (5, 25)):
+        cubes = _cube_minterm_sets(n)
+        for _ in range(count):
+            bits = np.array([rng.random() < rng.choice([0.3, 0.6, 0.85]) for _ in range(1 << n)])
+            support = frozenset(int(x) for x in np.nonzero(bits)[0])
+            tt = inputs.from_bits(n, bits)
+            impl, primes = _setwise_primes(n, support, cubes)
+            M, O = both_oracles(n, tt)
+            assert strings(n, M) == sorted(impl)
+            assert strings(n, O) == sorted(primes)
+
+
+# ----------------------------------------------------------------------------
+# closed forms
+
+
+@pytest.mark.parametrize("n", list(range(1, 11)))
+def test_parity_primes_are_odd_minterms(n):
+    # no two true minterms of parity are adjacent, so no merge ever happens
+    M2, O2, lst = oracle.primes(n, inputs.parity(n))
+    odd = sorted(sum(((x >> i) & 1) * 3**i for i in range(n)) for x in range(1 << n) if bin(x).count("1") % 2)
+    assert lst.tolist() == odd
+    assert np.array_equal(M2, O2)
+    if n <= 8:
+        M1, O1 = oracle.bruteforce(n, inputs.parity(n))
+        assert np.array_equal(O1, O2)
+
+
+def _interval_expected(n, a, b):
+    """Symmetric f = [a <= |x| <= b].  A cube with o ones and k stars covers
+    weights o..o+k: it is an implicant iff a <= o and o + k <= b, and prime iff
+    moreover no literal can be dropped, i.e. o = a and o + k = b."""
+    M, O = set(), set()
+    for s in itertools.product("01*", repeat=n):
+        o, k = s.count("1"), s.count("*")
+        r = oracle.rho_of("".join(s))
+        if a <= o and o + k <= b:
+            M.add(r)
+            if o == a and o + k == b:
+                O.add(r)
+    return M, O
+
+
+@pytest.mark.parametrize("n,a,b", [(3, 2, 3), (4, 1, 2), (5, 0, 3), (5, 2, 2), (6, 1, 4), (6, 3, 6), (7, 2, 5), (8, 0, 8)])
+def test_interval_symmetric_closed_form(n, a, b):
+    M_exp, O_exp = _interval_expected(n, a, b)
+    M, O = both_oracles(n, inputs.interval(n, a, b))
+    assert M == M_exp
+    assert O == O_exp
+    assert len(O) == math.comb(n, a) * math.comb(n - a, b - a)
+
+
+@pytest.mark.parametrize("n,a,b", [(12, 4, 9), (13, 6, 7), (14, 2, 12)])
+def test_interval_symmetric_counts_larger(n, a, b):
+    _, O, lst = oracle.primes(n, inputs.interval(n, a, b))
+    assert len(lst) == math.comb(n, a) * math.comb(n - a, b - a)
+    for r in lst[:: max(1, len(lst) // 200)]:
+        s = oracle.string_of(n, int(r))
+        assert s.count("1") == a and s.count("*") == b - a
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_single_product_term(seed):
+    rng = random.Random(seed)
+    n = rng.randint(1, 9)
+    care = rng.getrandbits(n)
+    val = rng.getrandbits(n) & care
+    tt = inputs.from_terms(n, [(care, val)])
+    M, O = both_oracles(n, tt)
+    term = "".join(("1" if (val >> i) & 1 else "0") if (care >> i) & 1 else "*" for i in range(n))
+    assert strings(n, O) == [term]
+    # implicants: agree with the term on its literals, anything elsewhere
+    assert len(M) == 3 ** (n - bin(care).count("1"))
+
+
+def _unate_expected(n, terms):
+    """Prime implicants of a unate DNF: the terms left after absorption (a term
+    whose literal set contains another term's literal set is dropped)."""
+    ts = sorted(set(terms))
+    keep = [t for t in ts if not any(u != t and (u[0] & t[0]) == u[0] for u in ts)]
+    out = set()
+    for care, val in keep:
+        s = "".join(("1" if (val >> i) & 1 else "0") if (care >> i) & 1 else "*" for i in range(n))
+        out.add(oracle.rho_of(s))
+    return out
+
+
+@pytest.mark.parametrize("n,T,wlo,whi,seed", [(6, 5, 1, 4, 1), (8, 12, 2, 5, 2), (10, 30, 2, 6, 3), (12, 60, 3, 8, 4), (14, 80, 4, 9, 5)])
+def test_unate_dnf_primes_are_absorbed_terms(n, T, wlo, whi, seed):
+    terms = inputs.unate_terms(n, T, wlo, whi, seed)
+    tt = inputs.from_terms(n, terms)
+    _, O, lst = oracle.primes(n, tt)
+    assert set(int(x) for x in lst) == _unate_expected(n, terms)
+    if n <= 8:
+        M1, O1 = oracle.bruteforce(n, tt)
+        assert np.array_equal(O1, O)
+
+
+# ----------------------------------------------------------------------------
+# invariants and cross-checks on random functions
+
+
+def _covers(n, big, small):
+    """True iff cube `big` contains cube `small` (string-wise)."""
+    sb, ss = oracle.string_of(n, big), oracle.string_of(n, small)
+    return all(a == "*" or a == b for a, b in zip(sb, ss))
+
+
+@pytest.mark.parametrize("n,p,seed", [(6, 0.5, 1), (7, 0.8, 2), (8, 0.9, 3), (8, 0.3, 4)])
+def test_invariants_random(n, p, seed):
+    tt = inputs.bernoulli(n, p, seed)
+    M, O = both_oracles(n, tt)
+    bits = inputs.to_bits(n, tt)
+    # M restricted to minterms is the truth table
+    binary = {sum(((x >> i) & 1) * 3**i for i in range(n)) for x in range(1 << n)}
+    assert {r for r in M if r in binary} == {sum(((x >> i) & 1) * 3**i for i in range(n)) for x in range(1 << n) if bits[x]}
+    assert O <= M
+    # antichain: no prime strictly contains another
+    Ol = sorted(O)
+    for a in Ol:
+        for b in Ol:
+            if a != b:
+                assert not _covers(n, a, b)
+    # down-closure of the primes is exactly the implicant set
+    for r in M:
+        assert any(_covers(n, p_, r) for p_ in Ol)
+    # every true minterm is covered by a prime (covering invariant)
+    for x in np.nonzero(bits)[0]:
+        r = sum(((int(x) >> i) & 1) * 3**i for i in range(n))
+        assert any(_covers(n, p_, r) for p_ in Ol)
+
+
+@pytest.mark.parametrize("n,p,seed", [(9, 0.5, 11), (10, 0.9, 12), (11, 0.7, 13), (12, 0.95, 14), (12, 0.5, 15)])
+def test_bruteforce_vs_enumerator_random(n, p, seed):
+    tt = inputs.bernoulli(n, p, seed)
+    both_oracles(n, tt)
+
+
+@pytest.mark.parametrize("n,seed", [(4, 21), (5, 22), (6, 23)])
+def test_one_step_prime_equals_all_divisor_prime(n, seed):
+    tt = inputs.bernoulli(n, 0.75, seed)
+    _, O1 = oracle.bruteforce(n, tt, all_divisors=False)
+    _, Oa = oracle.bruteforce(n, tt, all_divisors=True)
+    assert np.array_equal(O1, Oa)
+
+
+def _permute_tt(n, tt, perm):
+    """g(x) = f(y) where y_{perm[i]} = x_i."""
+    bits = inputs.to_bits(n, tt)
+    out = np.zeros(1 << n, dtype=bool)
+    for x in range(1 << n):
+        y = 0
+        for i in range(n):
+            if (x >> i) & 1:
+                y |= 1 << perm[i]
+        out[x] = bits[y]
+    return inputs.from_bits(n, out)
+
+
+@pytest.mark.parametrize("n,seed", [(6, 31), (8, 32), (9, 33)])
+def test_equivariance_permutation_and_negation(n, seed):
+    rng = random.Random(seed)
+    tt = inputs.bernoulli(n, 0.8, seed)
+    _, _, lst = oracle.primes(n, tt)
+    base = set(strings(n, [int(r) for r in lst]))
+    perm = list(range(n))
+    rng.shuffle(perm)
+    _, _, lst_p = oracle.primes(n, _permute_tt(n, tt, perm))
+    # digit i of a prime of g is digit perm[i] of a prime of f
+    mapped = {"".join(s[perm[i]] for i in range(n)) for s in base}
+    assert set(strings(n, [int(r) for r in lst_p])) == mapped
+    # negating x_j swaps digits 0 and 1 at position j
+    j = rng.randrange(n)
+    bits = inputs.to_bits(n, tt)
+    neg = inputs.from_bits(n, bits[np.arange(1 << n) ^ (1 << j)])
+    _, _, lst_n = oracle.primes(n, neg)
+    sw = {"0": "1", "1": "0", "*": "*"}
+    mapped_n = {s[:j] + sw[s[j]] + s[j + 1:] for s in base}
+    assert set(strings(n, [int(r) for r in lst_n])) == mapped_n
+
+
+def test_extract_ascending_and_capped():
+    n = 7
+    tt = inputs.bernoulli(n, 0.85, 7)
+    _, O, lst = oracle.primes(n, tt)
+    assert np.all(np.diff(lst.astype(np.int64)) > 0)
+    part, cnt = oracle.extract(n, O, cap=5)
+    assert cnt == len(lst) and part.tolist() == lst[:5].tolist()
+
+
+def test_per_cube_definitions_match_bitmaps():
+    n = 9
+    tt = inputs.dnf(n, 12, 2, 5, 99)
+    M, O, _ = oracle.primes(n, tt)
+    Ms, Os = oracle.bitmap_to_set(n, M), oracle.bitmap_to_set(n, O)
+    rng = random.Random(5)
+    for _ in range(400):
+        r = rng.randrange(3**n)
+        assert oracle.is_implicant(n, tt, r) == (r in Ms)
+        assert oracle.is_prime(n, tt, r) == (r in Os)
