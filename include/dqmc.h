@@ -1,0 +1,140 @@
+/*
+ * dqmc.h - C ABI of libdqmc: all prime implicants of a Boolean function from
+ * its full truth table, on an AMD Instinct MI355X (gfx950).
+ *
+ * Method: the dense bit-slice Quine-McCluskey algorithm of Udovenko,
+ * "DenseQMC: an efficient bit-slice implementation of the Quine-McCluskey
+ * algorithm" (arXiv 2302.10083): the implicant indicator M over all 3^n
+ * ternary cubes (MergeAll), the prime indicator O (ReduceAll), then the list
+ * of primes (Sec. 4, Alg. 3 and Alg. 4).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  n         number of variables, 0 <= n <= DQMC_MAX_N.
+ *  cube      a string s in {0,1,*}^n (Sec. 2); its index is
+ *            rho(s) = sum_{i=1..n} 3^(i-1) rho(s_i), rho(0)=0, rho(1)=1,
+ *            rho(*)=2 (Sec. 4.2).  Digit i of a cube carries the literal on
+ *            variable x_i.
+ *  truth     little-endian uint32 words, dqmc_tt_words(n) of them; bit x
+ *  table     (word x/32, bit x%32) is f(x), where variable x_i is bit i-1 of
+ *            x.  Bits at x >= 2^n (only when n < 5) are ignored.
+ *  state     the 3^n-bit cube bitmap in the "T27" layout: dqmc_state_words(n)
+ *            uint32 words; cube rho lives in word rho/27, bit rho%27 (n >= 3).
+ *            For n < 3 there is one word and cube rho is bit rho.  Bits 27..31
+ *            of every word (bits >= 3^n for n < 3) are always 0.  The order of
+ *            the words is increasing rho.
+ *  list      uint64 cube indices rho, strictly increasing.
+ *  stream    a hipStream_t passed as void* (NULL = the null stream).
+ *
+ *  Ownership: the caller owns and allocates every buffer argument (device
+ *  memory unless stated otherwise); the context owns only small scratch
+ *  memory allocated when it is created (no entry point allocates).
+ *  Asynchrony: compute entry points only enqueue work on `stream` and return;
+ *  results are valid after the stream is synchronised.  Argument errors are
+ *  found on the host before anything is enqueued and return DQMC_EINVAL;
+ *  dqmc_last_error() then describes the problem.
+ *  Concurrency: a context's scratch serves one call at a time; calls that use
+ *  one context must be ordered (same stream, or synchronised in between).
+ *  Use one context per concurrently used stream.
+ */
+#ifndef DQMC_H
+#define DQMC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DQMC_MAX_N 25
+
+typedef enum {
+    DQMC_OK = 0,
+    DQMC_EINVAL = -1,  /* bad argument (n out of range, NULL, bad size) */
+    DQMC_ENOMEM = -2,  /* device allocation failed (context creation only) */
+    DQMC_EDEVICE = -3  /* a HIP runtime call failed */
+} dqmc_status;
+
+typedef struct dqmc_ctx dqmc_ctx;
+
+/* Create a context on HIP device `device` and allocate its scratch (a few
+ * tens of MB at most).  Returns DQMC_ENOMEM / DQMC_EDEVICE on failure, with
+ * *out set to NULL. */
+int dqmc_create(int device, dqmc_ctx **out);
+
+/* Free the context and its scratch.  NULL is ignored.  No call may be in
+ * flight on the context. */
+void dqmc_destroy(dqmc_ctx *ctx);
+
+/* Message for the last failed call on this context (static storage owned by
+ * the context; "" if none).  Thread-compatible, not thread-safe. */
+const char *dqmc_last_error(const dqmc_ctx *ctx);
+
+/* Sizes (pure functions; 0 when n is out of range). */
+uint64_t dqmc_num_cubes(int n);    /* 3^n (Sec. 4.1: the state has one bit per cube) */
+uint64_t dqmc_tt_words(int n);     /* max(1, 2^(n-5)) uint32 words */
+uint64_t dqmc_state_words(int n);  /* 3^max(n-3, 0) uint32 words */
+uint64_t dqmc_dense_words(int n);  /* ceil(3^n / 64) uint64 words */
+
+/* Implicant bitmap M (Sec. 4.1, Lemma on MergeAll/ReduceAll; computed by the
+ * per-dimension Merge transforms of Alg. 3 / Alg. 4): bit rho of d_state is
+ * set iff cube rho is an implicant of f, i.e. f(x) = 1 for every x the cube
+ * covers (Sec. 2, Def. of implicant).
+ *   d_tt     device, dqmc_tt_words(n) words, read only.
+ *   d_state  device, dqmc_state_words(n) words, fully overwritten.
+ * Errors: DQMC_EINVAL for n out of range or NULL pointers. */
+int dqmc_implicants(dqmc_ctx *ctx, int n, const uint32_t *d_tt, uint32_t *d_state, void *stream);
+
+/* Prime implicants (Sec. 2, Def. of prime implicant; Sec. 4.1 ReduceAll and
+ * Alg. 4 including its output step): d_state receives the prime bitmap O
+ * (bit rho set iff cube rho is a prime implicant), and the primes' indices
+ * are written to d_list in increasing order.
+ *   d_tt      device, dqmc_tt_words(n) words, read only.
+ *   d_state   device, dqmc_state_words(n) words, fully overwritten with O.
+ *   d_list    device, room for list_cap uint64; may be NULL (count only).
+ *   d_count   device, one uint64: the total number of primes.
+ * Capacity: if the total exceeds list_cap, only the list_cap smallest
+ * indices are written (this is not an error); O stays in d_state and
+ * dqmc_extract can be called again with a larger list. */
+int dqmc_primes(dqmc_ctx *ctx, int n, const uint32_t *d_tt, uint32_t *d_state, uint64_t *d_list,
+                uint64_t list_cap, uint64_t *d_count, void *stream);
+
+/* Extraction alone (Alg. 4, output step): every set bit of a state bitmap,
+ * as increasing cube indices.  Same list/capacity/count rules as
+ * dqmc_primes; d_state is read only. */
+int dqmc_extract(dqmc_ctx *ctx, int n, const uint32_t *d_state, uint64_t *d_list, uint64_t list_cap,
+                 uint64_t *d_count, void *stream);
+
+/* Repack a T27 state into the exact 3^n-bit bitmap: bit rho of the
+ * little-endian uint64 array d_dense (dqmc_dense_words(n) words, fully
+ * overwritten; bits >= 3^n are 0).  Interoperability and tests; not part of
+ * the prime computation. */
+int dqmc_bitmap_to_dense(dqmc_ctx *ctx, int n, const uint32_t *d_state, uint64_t *d_dense, void *stream);
+
+/* One function of a batch.  The array of jobs lives in HOST memory; the
+ * buffers it points to are device memory with the sizes and meaning of
+ * dqmc_primes (list may be NULL).  `status` is written by the library:
+ * DQMC_OK, or DQMC_EINVAL for a malformed job, which is skipped while the
+ * other jobs still run. */
+typedef struct {
+    int32_t n;
+    int32_t status;
+    const uint32_t *tt;
+    uint32_t *state;
+    uint64_t *list;
+    uint64_t list_cap;
+    uint64_t *count;
+} dqmc_job;
+
+/* Prime implicants of many independent functions (the batch bit-slicing of
+ * independent executions, Sec. 4.2) in one enqueued launch sequence.  The
+ * result of each job is exactly what dqmc_primes gives for it alone.
+ * Returns DQMC_OK if at least the call itself was valid (per-job errors are
+ * in jobs[i].status), DQMC_EINVAL for a NULL/negative job array. */
+int dqmc_primes_batch(dqmc_ctx *ctx, dqmc_job *jobs, int32_t njobs, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DQMC_H */

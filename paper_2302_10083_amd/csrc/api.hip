@@ -1,0 +1,274 @@
+// C ABI of libdqmc (declared in include/dqmc.h): argument checks, the pass
+// plan for a given n, and the launch sequence.
+//
+// Pass plan for n > 12 (Alg. 4 with dimensions grouped; any order of the
+// Merge dimensions, then any order of the Reduce dimensions, gives the same
+// result - Sec. 4.1, and Sec. 6 fuses bottom Merge and Reduce layers):
+//   1. low tiles from the truth table: merge digits 1..12 (only tiles whose
+//      digits 13..n are binary hold data at that point);
+//   2. column passes merging the high digit groups G_1 .. G_{k-1};
+//   3. the top group G_k: merge and reduce in one pass;
+//   4. column passes reducing G_{k-1} .. G_1;
+//   5. low tiles: reduce digits 1..12, write O, extract the list.
+// For n <= 12 one workgroup does everything in LDS.
+#include <stdio.h>
+#include <string.h>
+
+#include <vector>
+
+#include "../../include/dqmc.h"
+#include "launch.h"
+#include "t27.h"
+
+using namespace dqmc;
+
+struct dqmc_ctx {
+    int device;
+    uint64_t *desc;      // look-back descriptors, one per low tile
+    uint64_t desc_cap;
+    uint32_t *ticket;
+    char err[512];
+};
+
+namespace {
+
+constexpr int kLowDigits = 12;  // digits 1..12 live in one low tile
+
+struct Group {
+    int g0;  // first digit (1-based)
+    int gr;  // digits in registers
+    int gw;  // digits across wavefronts
+    int size() const { return gr + gw; }
+};
+
+std::vector<Group> plan_groups(int n)
+{
+    std::vector<Group> out;
+    const int H = n - kLowDigits;
+    if (H <= 0) return out;
+    const int k = (H + 5) / 6;
+    int g0 = kLowDigits + 1;
+    for (int j = 0; j < k; ++j) {
+        const int s = H / k + (j < H % k ? 1 : 0);
+        const int gr = s < 4 ? s : 4;
+        out.push_back({g0, gr, s - gr});
+        g0 += s;
+    }
+    return out;
+}
+
+uint64_t pow2u(int k) { return 1ull << k; }
+
+int fail(dqmc_ctx *ctx, int code, const char *fmt, const char *detail)
+{
+    if (ctx) snprintf(ctx->err, sizeof(ctx->err), fmt, detail);
+    return code;
+}
+
+#define DQMC_HIP(ctx, call)                                                                   \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess) return fail((ctx), DQMC_EDEVICE, "HIP error: %s", hipGetErrorString(e_)); \
+    } while (0)
+
+bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+int check_common(dqmc_ctx *ctx, int n)
+{
+    if (ctx == nullptr) return DQMC_EINVAL;
+    ctx->err[0] = 0;
+    if (n < 0 || n > DQMC_MAX_N) {
+        char buf[64];
+        snprintf(buf, sizeof(buf), "%d", n);
+        return fail(ctx, DQMC_EINVAL, "n = %s is outside [0, 25]", buf);
+    }
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, DQMC_EDEVICE, "%s", "hipSetDevice failed");
+    return DQMC_OK;
+}
+
+LowArgs low_args(dqmc_ctx *ctx, int n)
+{
+    LowArgs a{};
+    a.n = n;
+    a.lw = n <= 3 ? 0 : (n - 3 < 9 ? n - 3 : 9);
+    a.tw = (uint32_t)pow3(a.lw);
+    a.ntiles = n <= kLowDigits ? 1 : pow3(n - kLowDigits);
+    a.desc = a.ntiles > 1 ? ctx->desc : nullptr;
+    a.ticket = ctx->ticket;
+    a.cap = 0;
+    return a;
+}
+
+ColArgs col_args(uint32_t *state, int n, const Group &g, bool outer_binary)
+{
+    ColArgs c{};
+    c.state = state;
+    c.L = pow3(g.g0 - 4);
+    const uint64_t lanes = (uint64_t)col_lanes_per_block(g.gw);
+    c.nlb = (c.L + lanes - 1) / lanes;
+    const int od = n - (g.g0 + g.size() - 1);
+    c.outer_binary = outer_binary ? 1 : 0;
+    c.nouter = outer_binary ? pow2u(od) : pow3(od);
+    c.nblocks = c.nlb * c.nouter;
+    return c;
+}
+
+// Steps 1-2 (and the top group's merge when reduce == false).
+int enqueue_merge(dqmc_ctx *ctx, int n, const uint32_t *tt, uint32_t *state, bool fuse_top_reduce,
+                  hipStream_t s)
+{
+    LowArgs a = low_args(ctx, n);
+    a.tt = tt;
+    a.state = state;
+    DQMC_HIP(ctx, launch_low(kLowMergeTT, a, pow2u(n - kLowDigits), s));
+    const std::vector<Group> gs = plan_groups(n);
+    for (size_t j = 0; j < gs.size(); ++j) {
+        const bool top = j + 1 == gs.size();
+        const int mode = (top && fuse_top_reduce) ? kColMergeReduce : kColMerge;
+        const ColArgs c = col_args(state, n, gs[j], true);
+        DQMC_HIP(ctx, launch_col(gs[j].gr, gs[j].gw, mode, c, s));
+    }
+    return DQMC_OK;
+}
+
+int enqueue_extract_tiles(dqmc_ctx *ctx, int n, int mode, uint32_t *state, uint64_t *list, uint64_t cap,
+                          uint64_t *count, hipStream_t s)
+{
+    LowArgs a = low_args(ctx, n);
+    a.state = state;
+    a.list = list;
+    a.cap = list ? cap : 0;
+    a.count = count;
+    if (a.desc) DQMC_HIP(ctx, launch_fill_u64(a.desc, a.ntiles, 0, s));
+    DQMC_HIP(ctx, launch_fill_u32(a.ticket, 1, 0, s));
+    DQMC_HIP(ctx, launch_low(mode, a, a.ntiles, s));
+    return DQMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+uint64_t dqmc_num_cubes(int n) { return (n < 0 || n > DQMC_MAX_N) ? 0 : pow3(n); }
+uint64_t dqmc_tt_words(int n) { return (n < 0 || n > DQMC_MAX_N) ? 0 : (n <= 5 ? 1 : (1ull << (n - 5))); }
+uint64_t dqmc_state_words(int n) { return (n < 0 || n > DQMC_MAX_N) ? 0 : pow3(n > 3 ? n - 3 : 0); }
+uint64_t dqmc_dense_words(int n) { return (n < 0 || n > DQMC_MAX_N) ? 0 : (pow3(n) + 63) / 64; }
+
+int dqmc_create(int device, dqmc_ctx **out)
+{
+    if (out == nullptr) return DQMC_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return DQMC_EDEVICE;
+    if (hipSetDevice(device) != hipSuccess) return DQMC_EDEVICE;
+    if (low_setup() != hipSuccess || col_setup() != hipSuccess) return DQMC_EDEVICE;
+    dqmc_ctx *c = new dqmc_ctx();
+    c->device = device;
+    c->desc_cap = pow3(DQMC_MAX_N - kLowDigits);
+    c->err[0] = 0;
+    if (hipMalloc((void **)&c->desc, c->desc_cap * sizeof(uint64_t)) != hipSuccess) {
+        delete c;
+        return DQMC_ENOMEM;
+    }
+    if (hipMalloc((void **)&c->ticket, 256) != hipSuccess) {
+        (void)hipFree(c->desc);
+        delete c;
+        return DQMC_ENOMEM;
+    }
+    *out = c;
+    return DQMC_OK;
+}
+
+void dqmc_destroy(dqmc_ctx *ctx)
+{
+    if (ctx == nullptr) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipFree(ctx->desc);
+    (void)hipFree(ctx->ticket);
+    delete ctx;
+}
+
+const char *dqmc_last_error(const dqmc_ctx *ctx) { return ctx ? ctx->err : "no context"; }
+
+int dqmc_implicants(dqmc_ctx *ctx, int n, const uint32_t *d_tt, uint32_t *d_state, void *stream)
+{
+    int rc = check_common(ctx, n);
+    if (rc != DQMC_OK) return rc;
+    if (d_tt == nullptr || d_state == nullptr) return fail(ctx, DQMC_EINVAL, "%s", "NULL truth table or state");
+    if (!aligned(d_tt, 4) || !aligned(d_state, 4)) return fail(ctx, DQMC_EINVAL, "%s", "misaligned buffer");
+    hipStream_t s = (hipStream_t)stream;
+    if (n <= kLowDigits) {
+        LowArgs a = low_args(ctx, n);
+        a.tt = d_tt;
+        a.state = d_state;
+        DQMC_HIP(ctx, launch_low(kLowMergeTT, a, 1, s));
+        return DQMC_OK;
+    }
+    return enqueue_merge(ctx, n, d_tt, d_state, false, s);
+}
+
+int dqmc_primes(dqmc_ctx *ctx, int n, const uint32_t *d_tt, uint32_t *d_state, uint64_t *d_list,
+                uint64_t list_cap, uint64_t *d_count, void *stream)
+{
+    int rc = check_common(ctx, n);
+    if (rc != DQMC_OK) return rc;
+    if (d_tt == nullptr || d_state == nullptr || d_count == nullptr)
+        return fail(ctx, DQMC_EINVAL, "%s", "NULL truth table, state or count");
+    if (!aligned(d_tt, 4) || !aligned(d_state, 4) || !aligned(d_count, 8) || !aligned(d_list, 8))
+        return fail(ctx, DQMC_EINVAL, "%s", "misaligned buffer");
+    hipStream_t s = (hipStream_t)stream;
+    if (n <= kLowDigits) {
+        LowArgs a = low_args(ctx, n);
+        a.tt = d_tt;
+        a.state = d_state;
+        a.list = d_list;
+        a.cap = d_list ? list_cap : 0;
+        a.count = d_count;
+        DQMC_HIP(ctx, launch_low(kLowPrimesTT, a, 1, s));
+        return DQMC_OK;
+    }
+    rc = enqueue_merge(ctx, n, d_tt, d_state, true, s);
+    if (rc != DQMC_OK) return rc;
+    const std::vector<Group> gs = plan_groups(n);
+    for (int j = (int)gs.size() - 2; j >= 0; --j) {
+        const ColArgs c = col_args(d_state, n, gs[j], false);
+        DQMC_HIP(ctx, launch_col(gs[j].gr, gs[j].gw, kColReduce, c, s));
+    }
+    return enqueue_extract_tiles(ctx, n, kLowReduceExtract, d_state, d_list, list_cap, d_count, s);
+}
+
+int dqmc_extract(dqmc_ctx *ctx, int n, const uint32_t *d_state, uint64_t *d_list, uint64_t list_cap,
+                 uint64_t *d_count, void *stream)
+{
+    int rc = check_common(ctx, n);
+    if (rc != DQMC_OK) return rc;
+    if (d_state == nullptr || d_count == nullptr) return fail(ctx, DQMC_EINVAL, "%s", "NULL state or count");
+    if (!aligned(d_state, 4) || !aligned(d_count, 8) || !aligned(d_list, 8))
+        return fail(ctx, DQMC_EINVAL, "%s", "misaligned buffer");
+    return enqueue_extract_tiles(ctx, n, kLowExtract, const_cast<uint32_t *>(d_state), d_list, list_cap, d_count,
+                                 (hipStream_t)stream);
+}
+
+int dqmc_bitmap_to_dense(dqmc_ctx *ctx, int n, const uint32_t *d_state, uint64_t *d_dense, void *stream)
+{
+    int rc = check_common(ctx, n);
+    if (rc != DQMC_OK) return rc;
+    if (d_state == nullptr || d_dense == nullptr) return fail(ctx, DQMC_EINVAL, "%s", "NULL state or output");
+    if (!aligned(d_state, 4) || !aligned(d_dense, 8)) return fail(ctx, DQMC_EINVAL, "%s", "misaligned buffer");
+    DQMC_HIP(ctx, launch_to_dense(n, d_state, d_dense, (hipStream_t)stream));
+    return DQMC_OK;
+}
+
+int dqmc_primes_batch(dqmc_ctx *ctx, dqmc_job *jobs, int32_t njobs, void *stream)
+{
+    if (ctx == nullptr || njobs < 0 || (jobs == nullptr && njobs > 0)) return DQMC_EINVAL;
+    ctx->err[0] = 0;
+    for (int32_t i = 0; i < njobs; ++i) {
+        dqmc_job &j = jobs[i];
+        j.status = dqmc_primes(ctx, j.n, j.tt, j.state, j.list, j.list_cap, j.count, stream);
+        if (j.status == DQMC_EDEVICE) return DQMC_EDEVICE;
+    }
+    return DQMC_OK;
+}
+
+}  // extern "C"

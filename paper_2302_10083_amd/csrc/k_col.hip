@@ -1,0 +1,212 @@
+// Column passes: Merge / Reduce over a group of high digits (digit >= 13).
+//
+// These are the top-layer dimensions of Sec. 4.2: for digit i the triples
+// are words at distance 3^(i-4) (eq. indexes), processed as a batch bit-slice
+// over all 27 cubes of a word at once.  Instead of one memory sweep per digit
+// (Alg. 4), a pass takes a group of G = GR + GW consecutive digits g0.. and
+// applies all of them while the data is on chip:
+//
+//   word index  w = l + L * (cr + 3^GR * (cw + 3^GW * o)),   L = 3^(g0-4)
+//
+// l (digits 4..g0-1) runs over consecutive words, one per lane, so every
+// access of a wavefront is 64 consecutive words; cr (GR digits) indexes a
+// lane's registers; cw (GW digits) is the wavefront within the workgroup;
+// o is the combination of the digits above the group.  Digits of cr are
+// transformed in registers, digits of cw through LDS.
+#include "launch.h"
+#include "t27.h"
+
+namespace dqmc {
+
+// Position of wave combination cw among the non-binary combinations.
+template <int GW>
+__device__ __forceinline__ int star_slot(int cw)
+{
+    int k = 0;
+    for (int c = 0; c < cw; ++c) {
+        int q = c;
+        bool b = true;
+        for (int r = 0; r < GW; ++r, q /= 3) b = b && (q % 3 != 2);
+        k += b ? 0 : 1;
+    }
+    return k;
+}
+
+template <int GW>
+__host__ __device__ constexpr int col_threads()
+{
+    return GW == 0 ? 256 : 64 * (int)pow3(GW);
+}
+
+template <int GR, int GW, int MODE>
+__global__ __launch_bounds__(col_threads<GW>()) void col_kernel(ColArgs a)
+{
+    constexpr int CR = (int)pow3(GR);
+    constexpr int CW = (int)pow3(GW);
+    constexpr int BR = 1 << GR;
+    constexpr int BW = 1 << GW;
+    constexpr int LANES = GW == 0 ? 256 : 64;
+    constexpr bool NEED_MERGE = MODE != kColReduce;
+    constexpr bool NEED_REDUCE = MODE != kColMerge;
+    // LDS: merge exchange of binary waves' binary combos, reduce exchange of
+    // star waves' full columns
+    constexpr int XM = GW > 0 ? BW * BR * 64 : 1;
+    constexpr int XR = (GW > 0 && NEED_REDUCE) ? (CW - BW) * CR * 64 : 1;
+    constexpr int XSZ = XM > XR ? XM : XR;
+    __shared__ uint32_t xch[XSZ];
+
+    const uint64_t logical = xcd_remap(blockIdx.x, a.nblocks);
+    const uint64_t lb = logical % a.nlb, ob = logical / a.nlb;
+    uint64_t o = ob;
+    if (a.outer_binary) {
+        o = 0;
+        uint64_t p = 1;
+        for (uint64_t b = ob; b != 0; b >>= 1, p *= 3) o += (b & 1) * p;
+    }
+    const int cw = GW == 0 ? 0 : (int)(threadIdx.x / 64);
+    const uint32_t lane = GW == 0 ? threadIdx.x : (threadIdx.x & 63);
+    const uint64_t l = lb * LANES + lane;
+    const bool active = l < a.L;
+    const uint64_t L = a.L;
+    uint32_t *base = a.state + l + L * (uint64_t)CR * ((uint64_t)cw + (uint64_t)CW * o);
+
+    uint32_t x[CR];
+    bool cw_binary = true;
+    if constexpr (GW > 0) {
+        int c = cw;
+        for (int r = 0; r < GW; ++r, c /= 3) cw_binary = cw_binary && (c % 3 != 2);
+    }
+
+    if constexpr (NEED_MERGE) {
+        // 1. binary cubes of the group come from earlier passes
+        static_for<CR>([&](auto ci) { x[decltype(ci)::value] = 0u; });
+        if (cw_binary && active) {
+            static_for<CR>([&](auto ci) {
+                constexpr int c = decltype(ci)::value;
+                if constexpr (all_binary(c, GR)) x[c] = base[(uint64_t)c * L];
+            });
+        }
+        // 2. wave digits: u = s AND t across wavefronts (on binary cr only)
+        if constexpr (GW > 0) {
+            if (cw_binary) {
+                int bs = 0;
+                {
+                    int c = cw, p = 1;
+                    for (int r = 0; r < GW; ++r, c /= 3, p <<= 1) bs += (c % 3) * p;
+                }
+                static_for<CR>([&](auto ci) {
+                    constexpr int c = decltype(ci)::value;
+                    if constexpr (all_binary(c, GR)) xch[(bs * BR + bin_index(c, GR)) * 64 + lane] = x[c];
+                });
+            }
+            __syncthreads();
+            if (!cw_binary) {
+                // AND over the binary wave combinations covered by cw
+                uint32_t cover = 0;  // bit b set: binary wave b is covered by cw
+                for (int b = 0; b < BW; ++b) {
+                    bool ok = true;
+                    int cc = cw;
+                    for (int r = 0; r < GW; ++r, cc /= 3) {
+                        const int d = cc % 3, bit = (b >> r) & 1;
+                        if (d != 2 && d != bit) ok = false;
+                    }
+                    cover |= ok ? (1u << b) : 0u;
+                }
+                static_for<CR>([&](auto ci) {
+                    constexpr int c = decltype(ci)::value;
+                    if constexpr (all_binary(c, GR)) {
+                        uint32_t acc = ~0u;
+                        for (int b = 0; b < BW; ++b)
+                            if ((cover >> b) & 1u) acc &= xch[(b * BR + bin_index(c, GR)) * 64 + lane];
+                        x[c] = acc;
+                    }
+                });
+            }
+        }
+        // 3. register digits
+        reg_merge<GR>(x);
+        if constexpr (MODE == kColMerge) {
+            if (active) {
+                static_for<CR>([&](auto ci) {
+                    constexpr int c = decltype(ci)::value;
+                    if (!cw_binary || !all_binary(c, GR)) base[(uint64_t)c * L] = x[c];
+                });
+            }
+            return;
+        }
+    } else {
+        static_for<CR>([&](auto ci) {
+            constexpr int c = decltype(ci)::value;
+            x[c] = active ? base[(uint64_t)c * L] : 0u;
+        });
+    }
+
+    if constexpr (NEED_REDUCE) {
+        // 4. wave digits first, all against the star neighbours' values
+        //    before any of this group's reduces (same as doing those
+        //    dimensions one after another)
+        if constexpr (GW > 0) {
+            if constexpr (NEED_MERGE) __syncthreads();  // xch reuse
+            if (!cw_binary) {
+                const int ss = star_slot<GW>(cw);
+                static_for<CR>([&](auto ci) {
+                    constexpr int c = decltype(ci)::value;
+                    xch[(ss * CR + c) * 64 + lane] = x[c];
+                });
+            }
+            __syncthreads();
+            int cc = cw, p = 1;
+            for (int r = 0; r < GW; ++r, cc /= 3, p *= 3) {
+                const int d = cc % 3;
+                if (d == 2) continue;
+                const int ss = star_slot<GW>(cw + (2 - d) * p);  // star neighbour in digit r
+                static_for<CR>([&](auto ci) {
+                    constexpr int c = decltype(ci)::value;
+                    x[c] &= ~xch[(ss * CR + c) * 64 + lane];
+                });
+            }
+        }
+        // 5. register digits, one after another
+        reg_reduce<GR>(x);
+        if (active) {
+            const bool cw_allstar = (GW == 0) || (cw == CW - 1);
+            static_for<CR>([&](auto ci) {
+                constexpr int c = decltype(ci)::value;
+                if (MODE == kColMergeReduce || !(cw_allstar && c == CR - 1)) base[(uint64_t)c * L] = x[c];
+            });
+        }
+    }
+}
+
+int col_lanes_per_block(int gw) { return gw == 0 ? 256 : 64; }
+
+template <int GR, int GW>
+static hipError_t launch_col_gw(int mode, const ColArgs &a, hipStream_t s)
+{
+    const dim3 grid((uint32_t)a.nblocks), block(col_threads<GW>());
+    switch (mode) {
+    case kColMerge: hipLaunchKernelGGL((col_kernel<GR, GW, kColMerge>), grid, block, 0, s, a); break;
+    case kColMergeReduce: hipLaunchKernelGGL((col_kernel<GR, GW, kColMergeReduce>), grid, block, 0, s, a); break;
+    case kColReduce: hipLaunchKernelGGL((col_kernel<GR, GW, kColReduce>), grid, block, 0, s, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_col(int gr, int gw, int mode, const ColArgs &a, hipStream_t s)
+{
+#define DQMC_COL(R, W) \
+    if (gr == R && gw == W) return launch_col_gw<R, W>(mode, a, s);
+    DQMC_COL(1, 0)
+    DQMC_COL(2, 0)
+    DQMC_COL(3, 0)
+    DQMC_COL(4, 0)
+    DQMC_COL(4, 1)
+    DQMC_COL(4, 2)
+#undef DQMC_COL
+    return hipErrorInvalidValue;
+}
+
+hipError_t col_setup() { return hipSuccess; }
+
+}  // namespace dqmc

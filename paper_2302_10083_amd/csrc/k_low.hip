@@ -1,0 +1,217 @@
+// Low tile kernels: the in-word digits 1..3 and the word digits 4..12 of one
+// tile of 3^min(n,12) cubes, processed in LDS.
+//
+// Alg. 4 loads the support into the state, then applies the Merge transform
+// per dimension (top layer over whole blocks, bottom layer inside a block),
+// then Reduce, then scans the state for the output list.  Here a tile is the
+// unit of on-chip work: digits 1..3 use the in-word shift-and-mask form of the
+// bottom layer (Sec. 4.2, masks mu_i), digits 4..12 use the top-layer triple
+// indexing of Sec. 4.2 (eq. indexes) on LDS words, three digits at a time in
+// registers.  Digits above 12 are handled by the column passes (k_col.hip).
+#include "launch.h"
+#include "t27.h"
+
+namespace dqmc {
+
+// Apply Merge (MERGE) or Reduce to the K tile digits j..j+K-1 (stride s = 3^j
+// words) of every column of the tile.
+template <int K, bool MERGE>
+__device__ __forceinline__ void lds_group(uint32_t *t, uint32_t tw, uint32_t s)
+{
+    constexpr int C = (int)pow3(K);
+    const uint32_t ncols = tw / C;
+    for (uint32_t q = threadIdx.x; q < ncols; q += blockDim.x) {
+        const uint32_t lo = q % s, hi = q / s;
+        uint32_t *col = t + lo + hi * s * C;
+        uint32_t x[C];
+        if constexpr (MERGE) {
+            static_for<C>([&](auto ci) {
+                constexpr int c = decltype(ci)::value;
+                x[c] = all_binary(c, K) ? col[c * s] : 0u;
+            });
+            reg_merge<K>(x);
+            static_for<C>([&](auto ci) {
+                constexpr int c = decltype(ci)::value;
+                if constexpr (!all_binary(c, K)) col[c * s] = x[c];
+            });
+        } else {
+            static_for<C>([&](auto ci) {
+                constexpr int c = decltype(ci)::value;
+                x[c] = col[c * s];
+            });
+            reg_reduce<K>(x);
+            static_for<C - 1>([&](auto ci) {
+                constexpr int c = decltype(ci)::value;
+                col[c * s] = x[c];
+            });
+        }
+    }
+}
+
+template <bool MERGE>
+__device__ __forceinline__ void lds_all_digits(uint32_t *t, uint32_t tw, int lw)
+{
+    uint32_t s = 1;
+    for (int j = 0; j < lw;) {
+        const int k = lw - j >= 3 ? 3 : lw - j;
+        if (k == 3) lds_group<3, MERGE>(t, tw, s);
+        else if (k == 2) lds_group<2, MERGE>(t, tw, s);
+        else lds_group<1, MERGE>(t, tw, s);
+        __syncthreads();
+        s *= (uint32_t)pow3(k);
+        j += k;
+    }
+}
+
+// Fill the tile from the truth table: the word of every cube group whose word
+// digits are all binary gets the merged in-word pattern of its 8 minterms;
+// every other word starts at 0 (Alg. 4, "Load input").
+__device__ __forceinline__ void load_tile_from_tt(uint32_t *t, uint32_t *lut, const LowArgs &a, uint64_t bh)
+{
+    lut[threadIdx.x] = inword_merge(expand_byte(threadIdx.x));  // blockDim == 256
+    for (uint32_t w = threadIdx.x; w < a.tw; w += blockDim.x) t[w] = 0;
+    __syncthreads();
+    const uint32_t nb = 1u << a.lw;
+    const uint32_t bytemask = a.n >= 3 ? 0xFFu : ((1u << (1u << a.n)) - 1u);
+    for (uint32_t xm = threadIdx.x; xm < nb; xm += blockDim.x) {
+        const uint64_t bi = (bh << a.lw) + xm;  // byte index = x >> 3
+        const uint32_t byte = (a.tt[bi >> 2] >> ((bi & 3) * 8)) & bytemask;
+        uint32_t w = 0, p = 1;
+        for (int j = 0; j < a.lw; ++j, p *= 3) w += ((xm >> j) & 1u) * p;
+        t[w] = lut[byte];
+    }
+    __syncthreads();
+}
+
+// Ordered compaction of the set bits of an LDS tile into the global list.
+// Offsets across tiles come from decoupled look-back when desc != nullptr;
+// otherwise the tile is the only one.
+__device__ __forceinline__ void tile_extract(const uint32_t *t, const LowArgs &a, uint64_t tile, uint64_t *sh)
+{
+    const uint32_t nw = blockDim.x / 64, wv = threadIdx.x / 64, lane = lane_id();
+    const uint32_t seg = (a.tw + nw - 1) / nw;
+    const uint32_t s0 = min(a.tw, wv * seg), s1 = min(a.tw, s0 + seg);
+    uint64_t c = 0;
+    for (uint32_t w = s0 + lane; w < s1; w += 64) c += __popc(t[w]);
+    c = wave_sum(c);
+    if (lane == 0) sh[wv] = c;
+    __syncthreads();
+    if (wv == 0) {
+        const uint64_t mine = lane < nw ? sh[lane] : 0;
+        const uint64_t incl = wave_inclusive_scan(mine);
+        const uint64_t total = __shfl(incl, 63, 64);
+        uint64_t off = 0;
+        if (a.desc != nullptr) {
+            if (lane == 0) desc_store(a.desc + tile, (tile == 0 ? kFlagPrefix : kFlagAgg) | total);
+            if (tile > 0) {
+                off = lookback_exclusive(a.desc, tile);
+                if (lane == 0) desc_store(a.desc + tile, kFlagPrefix | (off + total));
+            }
+        }
+        if (lane < nw) sh[nw + lane] = off + incl - mine;
+        if (lane == 0 && tile == a.ntiles - 1 && a.count != nullptr) *a.count = off + total;
+    }
+    __syncthreads();
+    if (a.list == nullptr) return;
+    uint64_t run = sh[nw + wv];
+    const uint64_t wbase = tile * (uint64_t)a.tw;
+    const bool words = a.n >= 3;
+    for (uint32_t r0 = s0; r0 < s1 && run < a.cap; r0 += 64) {
+        const uint32_t w = r0 + lane;
+        uint32_t v = w < s1 ? t[w] : 0u;
+        const uint64_t cc = __popc(v);
+        const uint64_t incl = wave_inclusive_scan(cc);
+        uint64_t pos = run + incl - cc;
+        const uint64_t rbase = words ? 27ull * (wbase + w) : 0ull;
+        while (v != 0u && pos < a.cap) {
+            const uint32_t b = __builtin_ctz(v);
+            v &= v - 1u;
+            a.list[pos++] = rbase + b;
+        }
+        run += __shfl(incl, 63, 64);
+    }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kLowThreads) void low_kernel(LowArgs a)
+{
+    extern __shared__ uint32_t dyn[];
+    __shared__ uint64_t sh[2 * (kLowThreads / 64) + 2];
+    uint32_t *t = dyn;
+
+    if constexpr (MODE == kLowMergeTT || MODE == kLowPrimesTT) {
+        // tile with binary digits 13..n given by the bits of blockIdx.x
+        const uint64_t bh = blockIdx.x;
+        load_tile_from_tt(t, dyn + a.tw, a, bh);
+        lds_all_digits<true>(t, a.tw, a.lw);
+        uint64_t tile = 0;
+        for (int j = 0, nh = a.n - 12; j < nh; ++j)
+            if ((bh >> j) & 1) tile += pow3(j);
+        if constexpr (MODE == kLowMergeTT) {
+            uint32_t *dst = a.state + tile * a.tw;
+            for (uint32_t w = threadIdx.x; w < a.tw; w += blockDim.x) dst[w] = t[w];
+        } else {
+            for (uint32_t w = threadIdx.x; w < a.tw; w += blockDim.x) t[w] = inword_reduce(t[w]);
+            __syncthreads();
+            lds_all_digits<false>(t, a.tw, a.lw);
+            for (uint32_t w = threadIdx.x; w < a.tw; w += blockDim.x) a.state[w] = t[w];
+            tile_extract(t, a, 0, sh);
+        }
+    } else {
+        // tiles are taken in order from a ticket so that every tile a
+        // look-back waits on is already resident
+        if (threadIdx.x == 0) sh[2 * (kLowThreads / 64)] = atomicAdd(a.ticket, 1u);
+        __syncthreads();
+        const uint64_t tile = sh[2 * (kLowThreads / 64)];
+        const uint32_t *src = a.state + tile * a.tw;
+        if constexpr (MODE == kLowReduceExtract) {
+            for (uint32_t w = threadIdx.x; w < a.tw; w += blockDim.x) t[w] = inword_reduce(src[w]);
+            __syncthreads();
+            lds_all_digits<false>(t, a.tw, a.lw);
+            uint32_t *dst = a.state + tile * a.tw;
+            for (uint32_t w = threadIdx.x; w < a.tw; w += blockDim.x) dst[w] = t[w];
+        } else {
+            for (uint32_t w = threadIdx.x; w < a.tw; w += blockDim.x) t[w] = src[w];
+            __syncthreads();
+        }
+        tile_extract(t, a, tile, sh);
+    }
+}
+
+static size_t low_lds_bytes(int mode, uint32_t tw)
+{
+    return (size_t)tw * 4 + ((mode == kLowMergeTT || mode == kLowPrimesTT) ? 256 * 4 : 0);
+}
+
+hipError_t low_setup()
+{
+    const int bytes = (int)low_lds_bytes(kLowMergeTT, (uint32_t)pow3(9));
+    hipError_t e;
+    if ((e = hipFuncSetAttribute((const void *)low_kernel<kLowMergeTT>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, bytes)) != hipSuccess)
+        return e;
+    if ((e = hipFuncSetAttribute((const void *)low_kernel<kLowPrimesTT>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, bytes)) != hipSuccess)
+        return e;
+    if ((e = hipFuncSetAttribute((const void *)low_kernel<kLowReduceExtract>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, bytes)) != hipSuccess)
+        return e;
+    return hipFuncSetAttribute((const void *)low_kernel<kLowExtract>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
+hipError_t launch_low(int mode, const LowArgs &a, uint64_t nblocks, hipStream_t s)
+{
+    const size_t lds = low_lds_bytes(mode, a.tw);
+    const dim3 grid((uint32_t)nblocks), block(kLowThreads);
+    switch (mode) {
+    case kLowMergeTT: hipLaunchKernelGGL(low_kernel<kLowMergeTT>, grid, block, lds, s, a); break;
+    case kLowPrimesTT: hipLaunchKernelGGL(low_kernel<kLowPrimesTT>, grid, block, lds, s, a); break;
+    case kLowReduceExtract: hipLaunchKernelGGL(low_kernel<kLowReduceExtract>, grid, block, lds, s, a); break;
+    case kLowExtract: hipLaunchKernelGGL(low_kernel<kLowExtract>, grid, block, lds, s, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace dqmc

@@ -1,0 +1,77 @@
+// Small helper kernels: fills (used instead of memset so that every enqueued
+// operation is a kernel node) and the T27 -> exact 3^n-bit repack.
+#include "launch.h"
+#include "t27.h"
+
+namespace dqmc {
+
+__global__ void fill_u64_kernel(uint64_t *p, uint64_t count, uint64_t value)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) p[i] = value;
+}
+
+__global__ void fill_u32_kernel(uint32_t *p, uint64_t count, uint32_t value)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) p[i] = value;
+}
+
+static uint32_t fill_grid(uint64_t count)
+{
+    uint64_t g = (count + 255) / 256;
+    if (g > 4096) g = 4096;
+    return (uint32_t)(g == 0 ? 1 : g);
+}
+
+hipError_t launch_fill_u64(uint64_t *p, uint64_t count, uint64_t value, hipStream_t s)
+{
+    if (count == 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_u64_kernel, dim3(fill_grid(count)), dim3(256), 0, s, p, count, value);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t *p, uint64_t count, uint32_t value, hipStream_t s)
+{
+    if (count == 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(fill_grid(count)), dim3(256), 0, s, p, count, value);
+    return hipGetLastError();
+}
+
+// Output word j holds cubes 64j .. 64j+63, which come from T27 words
+// floor(64j/27) .. floor((64j+63)/27) (at most 4 words).
+__global__ void to_dense_kernel(int n, const uint32_t *state, uint64_t *dense, uint64_t nwords, uint64_t ncubes)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < nwords; j += stride) {
+        uint64_t out = 0;
+        if (n < 3) {
+            out = state[0];
+        } else {
+            const uint64_t r0 = 64 * j;
+            uint64_t w = r0 / 27;
+            uint32_t b = (uint32_t)(r0 % 27);
+            const uint64_t nsw = ncubes / 27;
+            uint32_t filled = 0;
+            while (filled < 64 && w < nsw) {
+                const uint64_t bits = (uint64_t)(state[w] >> b);
+                out |= bits << filled;
+                filled += 27 - b;
+                b = 0;
+                ++w;
+            }
+        }
+        const uint64_t rem = ncubes - 64 * j;
+        if (rem < 64) out &= (1ull << rem) - 1;
+        dense[j] = out;
+    }
+}
+
+hipError_t launch_to_dense(int n, const uint32_t *state, uint64_t *dense, hipStream_t s)
+{
+    const uint64_t ncubes = pow3(n), nwords = (ncubes + 63) / 64;
+    hipLaunchKernelGGL(to_dense_kernel, dim3(fill_grid(nwords)), dim3(256), 0, s, n, state, dense, nwords, ncubes);
+    return hipGetLastError();
+}
+
+}  // namespace dqmc

@@ -1,0 +1,63 @@
+// Internal launchers shared by the kernel files and the C ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dqmc {
+
+// Low tile: the cubes whose digits 13..n are fixed, i.e. 3^min(n-3, 9)
+// consecutive state words (3^min(n,12) cubes), held in LDS.
+enum LowMode : int {
+    kLowMergeTT = 0,        // truth table -> merged tile (digits 1..12) -> state
+    kLowPrimesTT = 1,       // n <= 12: truth table -> M -> O -> state + list
+    kLowReduceExtract = 2,  // state -> reduce digits 1..12 -> state + list
+    kLowExtract = 3,        // state -> list only (no transform, no write)
+};
+
+struct LowArgs {
+    const uint32_t *tt;
+    uint32_t *state;
+    uint64_t *list;
+    uint64_t cap;
+    uint64_t *count;
+    uint64_t *desc;     // look-back descriptors, one per tile (zeroed before)
+    uint32_t *ticket;   // dynamic tile counter (zeroed before)
+    uint64_t ntiles;
+    uint32_t tw;        // words per tile
+    int n;
+    int lw;             // word digits inside a tile (tw = 3^lw)
+};
+
+constexpr int kLowThreads = 256;
+
+hipError_t low_setup();
+hipError_t launch_low(int mode, const LowArgs &a, uint64_t nblocks, hipStream_t s);
+
+// High-digit groups: one pass applies Merge and/or Reduce for a group of
+// consecutive digits g0 .. g0+GR+GW-1 (g0 >= 13) with GR digits held in
+// registers and GW digits spread over 3^GW wavefronts of one workgroup.
+enum ColMode : int {
+    kColMerge = 0,        // merge the group; outer digits binary; write * combos
+    kColMergeReduce = 1,  // merge then reduce the group; write everything
+    kColReduce = 2,       // reduce the group
+};
+
+struct ColArgs {
+    uint32_t *state;
+    uint64_t L;          // 3^(g0-4): words spanned by digits 4..g0-1
+    uint64_t nlb;        // l-blocks
+    uint64_t nouter;     // outer (above the group) combinations launched
+    uint64_t nblocks;    // nlb * nouter
+    int outer_binary;    // 1: outer index enumerates binary digit combos
+};
+
+hipError_t col_setup();
+hipError_t launch_col(int gr, int gw, int mode, const ColArgs &a, hipStream_t s);
+int col_lanes_per_block(int gw);  // l values per workgroup
+
+hipError_t launch_fill_u64(uint64_t *p, uint64_t count, uint64_t value, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t *p, uint64_t count, uint32_t value, hipStream_t s);
+hipError_t launch_to_dense(int n, const uint32_t *state, uint64_t *dense, hipStream_t s);
+
+}  // namespace dqmc

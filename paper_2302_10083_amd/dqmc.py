@@ -1,0 +1,293 @@
+"""Python binding of libdqmc (ctypes; argument marshalling only).
+
+Every function here forwards to the C ABI of the same name declared in
+``include/dqmc.h``; all computation happens in the HIP kernels of
+``libdqmc.so``.  Device buffers are torch tensors on a ROCm device (torch is
+used for device memory and streams only); they are passed by ``data_ptr()``
+together with the current torch stream.  There is no fallback: if the library
+cannot be loaded or the GPU is unavailable, calls raise.
+
+dtypes: truth tables and states are ``torch.int32`` tensors holding the
+uint32 words bit for bit; lists, counts and dense bitmaps are ``torch.int64``
+tensors holding uint64 values.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdqmc.so")
+
+DQMC_OK, DQMC_EINVAL, DQMC_ENOMEM, DQMC_EDEVICE = 0, -1, -2, -3
+DQMC_MAX_N = 25
+
+_lib = None
+_lock = threading.Lock()
+
+
+class DqmcError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("dqmc error %d: %s" % (code, msg))
+        self.code = code
+
+
+class dqmc_job(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int32),
+        ("status", ctypes.c_int32),
+        ("tt", ctypes.c_void_p),
+        ("state", ctypes.c_void_p),
+        ("list", ctypes.c_void_p),
+        ("list_cap", ctypes.c_uint64),
+        ("count", ctypes.c_void_p),
+    ]
+
+
+def load():
+    """Load libdqmc.so (building it first only if it does not exist)."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(LIB_PATH):
+            from . import build as _build
+
+            _build.build()
+        lib = ctypes.CDLL(LIB_PATH)
+        u64, i32, vp = ctypes.c_uint64, ctypes.c_int, ctypes.c_void_p
+        sig = {
+            "dqmc_create": (i32, [i32, ctypes.POINTER(vp)]),
+            "dqmc_destroy": (None, [vp]),
+            "dqmc_last_error": (ctypes.c_char_p, [vp]),
+            "dqmc_num_cubes": (u64, [i32]),
+            "dqmc_tt_words": (u64, [i32]),
+            "dqmc_state_words": (u64, [i32]),
+            "dqmc_dense_words": (u64, [i32]),
+            "dqmc_implicants": (i32, [vp, i32, vp, vp, vp]),
+            "dqmc_primes": (i32, [vp, i32, vp, vp, vp, u64, vp, vp]),
+            "dqmc_extract": (i32, [vp, i32, vp, vp, u64, vp, vp]),
+            "dqmc_bitmap_to_dense": (i32, [vp, i32, vp, vp, vp]),
+            "dqmc_primes_batch": (i32, [vp, ctypes.POINTER(dqmc_job), ctypes.c_int32, vp]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(lib, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = lib
+        return lib
+
+
+# ----------------------------------------------------------------------------
+# sizes (pure host functions)
+
+def dqmc_num_cubes(n: int) -> int:
+    return int(load().dqmc_num_cubes(n))
+
+
+def dqmc_tt_words(n: int) -> int:
+    return int(load().dqmc_tt_words(n))
+
+
+def dqmc_state_words(n: int) -> int:
+    return int(load().dqmc_state_words(n))
+
+
+def dqmc_dense_words(n: int) -> int:
+    return int(load().dqmc_dense_words(n))
+
+
+# ----------------------------------------------------------------------------
+# marshalling helpers
+
+def _ptr(t, what, dtype, min_numel):
+    import torch
+
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch tensor" % what)
+    if t.device.type != "cuda":
+        raise ValueError("%s must be a device tensor" % what)
+    if t.dtype != dtype:
+        raise TypeError("%s must have dtype %s (got %s)" % (what, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % what)
+    if t.numel() < min_numel:
+        raise ValueError("%s has %d elements, needs %d" % (what, t.numel(), min_numel))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _check(ctx, rc):
+    if rc != DQMC_OK:
+        msg = load().dqmc_last_error(ctx)
+        raise DqmcError(rc, msg.decode() if msg else "")
+
+
+# ----------------------------------------------------------------------------
+# the C ABI, one function each
+
+def dqmc_create(device: int = 0) -> ctypes.c_void_p:
+    import torch
+
+    if not torch.cuda.is_available():
+        raise DqmcError(DQMC_EDEVICE, "no ROCm device visible")
+    out = ctypes.c_void_p()
+    rc = load().dqmc_create(device, ctypes.byref(out))
+    if rc != DQMC_OK:
+        raise DqmcError(rc, "dqmc_create(%d) failed" % device)
+    return out
+
+
+def dqmc_destroy(ctx) -> None:
+    load().dqmc_destroy(ctx)
+
+
+def dqmc_last_error(ctx) -> str:
+    m = load().dqmc_last_error(ctx)
+    return m.decode() if m else ""
+
+
+def dqmc_implicants(ctx, n, tt, state, stream=None) -> None:
+    import torch
+
+    _check(ctx, load().dqmc_implicants(
+        ctx, n, _ptr(tt, "tt", torch.int32, dqmc_tt_words(n)),
+        _ptr(state, "state", torch.int32, dqmc_state_words(n)), _stream(stream)))
+
+
+def dqmc_primes(ctx, n, tt, state, lst, list_cap, count, stream=None) -> None:
+    import torch
+
+    cap = 0 if lst is None else int(list_cap)
+    _check(ctx, load().dqmc_primes(
+        ctx, n, _ptr(tt, "tt", torch.int32, dqmc_tt_words(n)),
+        _ptr(state, "state", torch.int32, dqmc_state_words(n)),
+        _ptr(lst, "list", torch.int64, cap), cap,
+        _ptr(count, "count", torch.int64, 1), _stream(stream)))
+
+
+def dqmc_extract(ctx, n, state, lst, list_cap, count, stream=None) -> None:
+    import torch
+
+    cap = 0 if lst is None else int(list_cap)
+    _check(ctx, load().dqmc_extract(
+        ctx, n, _ptr(state, "state", torch.int32, dqmc_state_words(n)),
+        _ptr(lst, "list", torch.int64, cap), cap,
+        _ptr(count, "count", torch.int64, 1), _stream(stream)))
+
+
+def dqmc_bitmap_to_dense(ctx, n, state, dense, stream=None) -> None:
+    import torch
+
+    _check(ctx, load().dqmc_bitmap_to_dense(
+        ctx, n, _ptr(state, "state", torch.int32, dqmc_state_words(n)),
+        _ptr(dense, "dense", torch.int64, dqmc_dense_words(n)), _stream(stream)))
+
+
+def dqmc_primes_batch(ctx, jobs, stream=None) -> list:
+    """``jobs``: list of dicts with keys n, tt, state, list (or None),
+    list_cap, count (device tensors).  Returns the per-job status codes."""
+    import torch
+
+    arr = (dqmc_job * max(1, len(jobs)))()
+    for i, j in enumerate(jobs):
+        n = int(j["n"])
+        nn = n if 0 <= n <= DQMC_MAX_N else 0
+        lst = j.get("list")
+        cap = 0 if lst is None else int(j.get("list_cap", lst.numel()))
+        arr[i].n = n
+        arr[i].status = 0
+        arr[i].tt = _ptr(j["tt"], "tt", torch.int32, dqmc_tt_words(nn)) if j["tt"] is not None else None
+        arr[i].state = _ptr(j["state"], "state", torch.int32, dqmc_state_words(nn)) if j["state"] is not None else None
+        arr[i].list = _ptr(lst, "list", torch.int64, cap)
+        arr[i].list_cap = cap
+        arr[i].count = _ptr(j["count"], "count", torch.int64, 1) if j["count"] is not None else None
+    _check(ctx, load().dqmc_primes_batch(ctx, arr, len(jobs), _stream(stream)))
+    return [int(arr[i].status) for i in range(len(jobs))]
+
+
+# ----------------------------------------------------------------------------
+# convenience wrapper
+
+class Context:
+    """Owns a dqmc context on one device and allocates result tensors."""
+
+    def __init__(self, device: int = 0):
+        import torch
+
+        self.device = device
+        self.torch_device = torch.device("cuda", device)
+        self.ctx = dqmc_create(device)
+
+    def close(self):
+        if self.ctx is not None:
+            dqmc_destroy(self.ctx)
+            self.ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def tt_to_device(self, tt_u32):
+        """Host uint32 numpy truth table -> device int32 tensor."""
+        import numpy as np
+        import torch
+
+        a = np.ascontiguousarray(tt_u32, dtype=np.uint32).view(np.int32)
+        return torch.from_numpy(a.copy()).to(self.torch_device)
+
+    def new_state(self, n):
+        import torch
+
+        return torch.empty(dqmc_state_words(n), dtype=torch.int32, device=self.torch_device)
+
+    def implicants(self, n, tt, state=None, stream=None):
+        state = self.new_state(n) if state is None else state
+        dqmc_implicants(self.ctx, n, tt, state, stream)
+        return state
+
+    def primes(self, n, tt, state=None, list_cap=None, stream=None):
+        """(state, list, count) device tensors; with list_cap None the list
+        has room for every possible prime of this call's count (two passes)."""
+        import torch
+
+        state = self.new_state(n) if state is None else state
+        count = torch.zeros(1, dtype=torch.int64, device=self.torch_device)
+        if list_cap is None:
+            dqmc_primes(self.ctx, n, tt, state, None, 0, count, stream)
+            cap = int(count.item())
+            lst = torch.empty(max(cap, 1), dtype=torch.int64, device=self.torch_device)
+            dqmc_extract(self.ctx, n, state, lst, cap, count, stream)
+            return state, lst[:cap], count
+        lst = torch.empty(max(int(list_cap), 1), dtype=torch.int64, device=self.torch_device)
+        dqmc_primes(self.ctx, n, tt, state, lst, list_cap, count, stream)
+        return state, lst, count
+
+    def extract(self, n, state, list_cap, stream=None):
+        import torch
+
+        count = torch.zeros(1, dtype=torch.int64, device=self.torch_device)
+        lst = torch.empty(max(int(list_cap), 1), dtype=torch.int64, device=self.torch_device)
+        dqmc_extract(self.ctx, n, state, lst, list_cap, count, stream)
+        return lst, count
+
+    def to_dense(self, n, state, stream=None):
+        import torch
+
+        dense = torch.empty(dqmc_dense_words(n), dtype=torch.int64, device=self.torch_device)
+        dqmc_bitmap_to_dense(self.ctx, n, state, dense, stream)
+        return dense

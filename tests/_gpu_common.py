@@ -1,0 +1,113 @@
+"""Shared helpers for the GPU tests (test code, not product code)."""
+import functools
+import sys
+
+import numpy as np
+
+import oracle
+from paper_2302_10083_amd import inputs
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@functools.lru_cache(maxsize=None)
+def context():
+    from paper_2302_10083_amd import dqmc
+
+    return dqmc.Context(0)
+
+
+def t27_to_dense(n, state_u32):
+    """Host conversion of a T27 state (uint32 words) into the exact 3^n-bit
+    bitmap (uint64 words), written independently of the library's repack."""
+    N = 3**n
+    if n < 3:
+        bits = np.array([(int(state_u32[0]) >> b) & 1 for b in range(N)], dtype=np.uint8)
+    else:
+        w = np.ascontiguousarray(state_u32, dtype=np.uint32)
+        if np.any(w >> np.uint32(27)):
+            raise AssertionError("padding bits 27..31 set in a state word")
+        bits = np.unpackbits(w.view(np.uint8), bitorder="little").reshape(-1, 32)[:, :27].reshape(-1)
+        bits = bits[:N]
+    nbytes = ((N + 63) // 64) * 8
+    packed = np.packbits(bits, bitorder="little")
+    buf = np.zeros(nbytes, dtype=np.uint8)
+    buf[: packed.size] = packed
+    return buf.view(np.uint64)
+
+
+def dev_to_u32(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+def dev_to_u64(t):
+    return t.cpu().numpy().view(np.uint64)
+
+
+def run_primes(n, tt, list_cap=None):
+    """GPU prime computation; returns (state_dev, list_np, count)."""
+    import torch
+
+    ctx = context()
+    ttd = ctx.tt_to_device(tt)
+    if list_cap is None:
+        list_cap = 3**n
+    state, lst, count = ctx.primes(n, ttd, list_cap=min(list_cap, 3**n))
+    torch.cuda.synchronize()
+    c = int(count.item())
+    k = min(c, list_cap)
+    return state, dev_to_u64(lst[:k]) if k > 0 else np.zeros(0, dtype=np.uint64), c
+
+
+def run_implicants(n, tt):
+    import torch
+
+    ctx = context()
+    state = ctx.implicants(n, ctx.tt_to_device(tt))
+    torch.cuda.synchronize()
+    return state
+
+
+def dense_of(n, state):
+    import torch
+
+    d = context().to_dense(n, state)
+    torch.cuda.synchronize()
+    return dev_to_u64(d)
+
+
+@functools.lru_cache(maxsize=64)
+def _oracle_cached(n, key):
+    tt = _TT_STORE[key]
+    return oracle.primes(n, tt)
+
+
+_TT_STORE = {}
+
+
+def oracle_primes(n, tt):
+    key = (n, tt.tobytes())
+    _TT_STORE[key] = tt
+    return _oracle_cached(n, key)
+
+
+def rho_of_binary(n, x):
+    return sum(((x >> i) & 1) * 3**i for i in range(n))
+
+
+def make_tt(n, kind, seed):
+    if kind == "const0":
+        return inputs.constant(n, 0)
+    if kind == "const1":
+        return inputs.constant(n, 1)
+    if kind == "parity":
+        return inputs.parity(n)
+    if kind.startswith("bern"):
+        return inputs.bernoulli(n, float(kind[4:]), seed)
+    if kind.startswith("dnf"):
+        T = int(kind[3:])
+        return inputs.dnf(n, T, max(1, n // 4), max(2, n // 2), seed)
+    raise ValueError(kind)
