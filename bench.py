@@ -1,0 +1,204 @@
+"""Benchmark: prime implicants of one n = 24 function on one MI355X.
+
+One step = the whole hot path on one resident truth table: implicants
+(MergeAll), primes (ReduceAll), the prime bitmap and the sorted prime list
+written to HBM (dqmc_primes).  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
+PAPER_N24_SECONDS = 120.0  # Table 1, DenseQMC at n = 24 (one EPYC core), context only
+
+
+def csrc_hash() -> str:
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2302_10083_amd", "csrc")
+    for fn in sorted(os.listdir(d)):
+        with open(os.path.join(d, fn), "rb") as f:
+            h.update(fn.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(kernel: str, workload: str):
+    """HBM traffic measured with rocprofv3 counters for this kernel source, from
+    profiles/pmc_<kernel>_<workload>.md (lines 'key: value'); None when absent
+    or taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", "pmc_%s_%s.md" % (kernel, workload))
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip().lstrip("- ")] = v.strip()
+    if kv.get("csrc_hash") != csrc_hash():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(n, tt, seconds, threads):
+    """The oracle's per-cube prime test on uniformly random cubes of the same
+    function, on the host cores, for about `seconds` seconds."""
+    import numpy as np
+
+    import oracle
+    from paper_2302_10083_amd import inputs
+
+    k = 2000
+    done, elapsed, used = 0, 0.0, 0
+    rhos_all = []
+    res_all = []
+    while elapsed < seconds:
+        r = (inputs.u64_array(0xC0FFEE, k, start=done) % np.uint64(3**n)).astype(np.uint64)
+        t0 = time.perf_counter()
+        res, used = oracle.sample(n, tt, r, "prime", threads)
+        dt = time.perf_counter() - t0
+        elapsed += dt
+        done += k
+        rhos_all.append(r)
+        res_all.append(res)
+        if dt < seconds / 8:
+            k *= 2
+    return done / elapsed, used, elapsed, np.concatenate(rhos_all), np.concatenate(res_all)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c3_n24_dnf2000_noise")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-threads", type=int, default=16)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU: the prime-implicant path has no "
+              "multi-GPU mode (--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2302_10083_amd import dqmc, inputs
+
+    spec = inputs.CONFIGS[args.workload]
+    n = spec["n"]
+    tt = inputs.make(spec)
+    ctx = dqmc.Context(0)
+    dev = ctx.torch_device
+    ttd = ctx.tt_to_device(tt)
+    state = ctx.new_state(n)
+    count = torch.zeros(1, dtype=torch.int64, device=dev)
+    print("bench: n=%d workload=%s state=%.2f GB" % (n, args.workload, state.numel() * 4 / 1e9),
+          file=sys.stderr, flush=True)
+    # size the list with a count-only run
+    dqmc.dqmc_primes(ctx.ctx, n, ttd, state, None, 0, count)
+    torch.cuda.synchronize()
+    nprimes = int(count.item())
+    lst = torch.empty(max(nprimes, 1), dtype=torch.int64, device=dev)
+    print("bench: %d primes (list %.2f GB)" % (nprimes, nprimes * 8 / 1e9), file=sys.stderr, flush=True)
+
+    for _ in range(args.warmup):
+        dqmc.dqmc_primes(ctx.ctx, n, ttd, state, lst, nprimes, count)
+    torch.cuda.synchronize()
+
+    dqmc.dqmc_profile(ctx.ctx, True)
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record()
+    for _ in range(args.steps):
+        dqmc.dqmc_primes(ctx.ctx, n, ttd, state, lst, nprimes, count)
+    end.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    recs = dqmc.dqmc_profile_read(ctx.ctx)
+    dqmc.dqmc_profile(ctx.ctx, False)
+    assert int(count.item()) == nprimes
+    ms_step = start.elapsed_time(end) / args.steps
+    cubes = 3**n
+
+    # per-pass figures (average over the timed steps)
+    passes = {}
+    for r in recs:
+        p = passes.setdefault(r["pass_name"], dict(ms=0.0, k=0, model_bytes=r["model_bytes"],
+                                                   lbpp=r["list_bytes_per_prime"]))
+        p["ms"] += r["ms"]
+        p["k"] += 1
+    pass_rows = []
+    total_bytes = 0.0
+    for name, p in passes.items():
+        ms = p["ms"] / p["k"]
+        b = p["model_bytes"] + p["lbpp"] * nprimes
+        total_bytes += b
+        pass_rows.append(dict(name=name, ms=round(ms, 4), model_GB=round(b / 1e9, 3),
+                              GBps=round(b / (ms / 1e3) / 1e9, 1)))
+    dom = max(pass_rows, key=lambda r: r["ms"])
+    dom_bytes = dom["model_GB"] * 1e9
+    achieved = dom_bytes / (dom["ms"] / 1e3) / 1e9
+    traffic = read_traffic(dom["name"], args.workload)
+
+    out = {
+        "metric": "ternary cubes/s (DenseQMC primes at n=24: truth table -> prime bitmap + sorted list)",
+        "value": cubes / (ms_step / 1e3),
+        "unit": "cubes/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": n, "cubes": cubes, "truth_table": spec,
+                   "primes": nprimes, "layout": "T27", "parallelism": "single-gpu"},
+        "hbm_GBps_model": total_bytes / (ms_step / 1e3) / 1e9,
+        "hbm_frac_model": total_bytes / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBPS,
+        "model_bytes_per_step": total_bytes,
+        "wall_s_timed": wall,
+        "passes": pass_rows,
+        "roofline": {"bound": "hbm", "kernel": dom["name"], "achieved": achieved, "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
+                     "traffic": traffic, "model_bytes_per_launch": dom_bytes},
+        "paper_context": {"n24_seconds_one_core": PAPER_N24_SECONDS,
+                          "n24_cubes_per_s": cubes / PAPER_N24_SECONDS if n == 24 else None},
+    }
+
+    if not args.no_cpu_baseline:
+        rate, used, el, rhos, ref = cpu_baseline(n, tt, args.cpu_seconds, args.cpu_threads)
+        # the sampled cubes double as a parity check of the GPU bitmap
+        r_t = torch.from_numpy(rhos.astype(np.int64)).to(dev)
+        words = torch.div(r_t, 27, rounding_mode="floor") if n >= 3 else torch.zeros_like(r_t)
+        bits = torch.remainder(r_t, 27) if n >= 3 else r_t
+        got = ((state[words].to(torch.int64) >> bits) & 1).cpu().numpy().astype(bool)
+        mism = int(np.count_nonzero(got != ref))
+        out["cpu_baseline"] = {"value": rate, "unit": "cubes/s", "cores": used, "kind": "oracle",
+                               "sample": "%d uniformly random cubes of the same n=%d function, per-cube "
+                                         "prime test (Sec. 2 definitions), %.1f s" % (len(rhos), n, el)}
+        out["sample_parity"] = {"cubes": int(len(rhos)), "primes_in_sample": int(ref.sum()), "mismatches": mism}
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

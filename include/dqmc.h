@@ -133,6 +133,35 @@ typedef struct {
  * in jobs[i].status), DQMC_EINVAL for a NULL/negative job array. */
 int dqmc_primes_batch(dqmc_ctx *ctx, dqmc_job *jobs, int32_t njobs, void *stream);
 
+/* ---------------------------------------------------------------------------
+ * Diagnostics: per-pass device timing.
+ *
+ * With profiling enabled, every compute call on the context records a HIP
+ * event right before and right after each kernel pass it enqueues, on the
+ * caller's stream (at most DQMC_MAX_RECORDS passes are kept; later ones are
+ * not recorded).  model_bytes is the pass's algorithmic HBM traffic: the
+ * state words it must read and write under the pass plan, plus the truth
+ * table it reads; for passes that write the prime list, add 8 bytes per
+ * listed prime (list_bytes_per_prime = 8).
+ */
+#define DQMC_MAX_RECORDS 64
+
+typedef struct {
+    char pass[40];              /* e.g. "low_merge_tt", "col_reduce_g13_6" */
+    int32_t n;
+    int32_t list_bytes_per_prime;
+    float ms;                   /* elapsed device time of the pass */
+    double model_bytes;
+} dqmc_pass_record;
+
+/* enable != 0 starts recording (clearing older records); 0 stops. */
+int dqmc_profile(dqmc_ctx *ctx, int enable);
+
+/* Waits for the recorded events, copies up to cap records into out (host
+ * memory), clears them and returns how many were copied (negative dqmc_status
+ * on error). */
+int dqmc_profile_read(dqmc_ctx *ctx, dqmc_pass_record *out, int cap);
+
 #ifdef __cplusplus
 }
 #endif

@@ -65,6 +65,8 @@ def _load():
             lib.orc_enum_O.argtypes = [i32, vp, vp, i32]
             lib.orc_extract.restype = u64
             lib.orc_extract.argtypes = [i32, vp, vp, u64]
+            lib.orc_sample.restype = i32
+            lib.orc_sample.argtypes = [i32, vp, vp, u64, vp, i32, i32]
             _lib = lib
     return _lib
 
@@ -129,6 +131,17 @@ def extract(n: int, O: np.ndarray, cap: int | None = None):
     out = np.zeros(max(k, 1), dtype=np.uint64)
     lib.orc_extract(n, O.ctypes.data, out.ctypes.data, k)
     return out[:k], cnt
+
+
+def sample(n: int, tt, rhos, what: str = "prime", threads: int = 0):
+    """Per-cube definitions on an array of cube indices: returns (bool array,
+    threads used)."""
+    a = _tt(tt)
+    r = np.ascontiguousarray(rhos, dtype=np.uint64)
+    out = np.zeros(max(1, r.size), dtype=np.uint8)
+    used = _load().orc_sample(n, a.ctypes.data, r.ctypes.data, r.size, out.ctypes.data,
+                              1 if what == "prime" else 0, threads)
+    return out[: r.size].astype(bool), int(used)
 
 
 def primes(n: int, tt, threads: int = 0):

@@ -332,3 +332,42 @@ uint64_t orc_extract(int n, const uint64_t *O, uint64_t *list, uint64_t cap)
     }
     return cnt;
 }
+
+/* ------------------------------------------------------------------------
+ * Per-cube definitions over a sample of cubes (for sizes where the whole
+ * bitmap is too large): out[k] = orc_is_prime / orc_is_implicant of rhos[k].
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int n, what;
+    const uint32_t *tt;
+    const uint64_t *rhos;
+    uint8_t *out;
+    uint64_t k;
+    uint64_t next;
+} sample_job;
+
+static void *sample_worker(void *arg)
+{
+    sample_job *J = (sample_job *)arg;
+    for (;;) {
+        uint64_t i0 = __atomic_fetch_add(&J->next, 256, __ATOMIC_RELAXED);
+        if (i0 >= J->k) break;
+        uint64_t i1 = i0 + 256 < J->k ? i0 + 256 : J->k;
+        for (uint64_t i = i0; i < i1; ++i)
+            J->out[i] = (uint8_t)(J->what ? orc_is_prime(J->n, J->tt, J->rhos[i])
+                                          : orc_is_implicant(J->n, J->tt, J->rhos[i]));
+    }
+    return NULL;
+}
+
+/* what = 1: prime test, 0: implicant test.  Returns the threads used. */
+int orc_sample(int n, const uint32_t *tt, const uint64_t *rhos, uint64_t k, uint8_t *out, int what, int nthreads)
+{
+    sample_job J = {n, what, tt, rhos, out, k, 0};
+    int T = resolve_threads(nthreads);
+    if (T > 256) T = 256;
+    pthread_t th[256];
+    for (int i = 0; i < T; ++i) pthread_create(&th[i], NULL, sample_worker, &J);
+    for (int i = 0; i < T; ++i) pthread_join(th[i], NULL);
+    return T;
+}

@@ -14,9 +14,10 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <cmath>
 #include <vector>
 
-#include "../../include/dqmc.h"
+#include "dqmc.h"  // include/dqmc.h (the public C ABI)
 #include "launch.h"
 #include "t27.h"
 
@@ -28,6 +29,12 @@ struct dqmc_ctx {
     uint64_t desc_cap;
     uint32_t *ticket;
     char err[512];
+    // per-pass timing (diagnostics)
+    bool prof;
+    bool events_made;
+    int nrec;
+    hipEvent_t ev[2 * DQMC_MAX_RECORDS];
+    dqmc_pass_record rec[DQMC_MAX_RECORDS];
 };
 
 namespace {
@@ -86,6 +93,29 @@ int check_common(dqmc_ctx *ctx, int n)
     return DQMC_OK;
 }
 
+double state_bytes(int n) { return 4.0 * (double)pow3(n > 3 ? n - 3 : 0); }
+double tt_bytes(int n) { return n <= 5 ? 4.0 : (double)(1ull << (n - 3)); }
+
+// Enqueue one kernel pass; with profiling on, bracket it with events.
+template <typename F>
+int run_pass(dqmc_ctx *ctx, hipStream_t s, const char *name, int n, double model_bytes, int list_bpp, F &&launch)
+{
+    int k = -1;
+    if (ctx->prof && ctx->nrec < DQMC_MAX_RECORDS) {
+        k = ctx->nrec++;
+        dqmc_pass_record &r = ctx->rec[k];
+        snprintf(r.pass, sizeof(r.pass), "%s", name);
+        r.n = n;
+        r.list_bytes_per_prime = list_bpp;
+        r.ms = 0.f;
+        r.model_bytes = model_bytes;
+        DQMC_HIP(ctx, hipEventRecord(ctx->ev[2 * k], s));
+    }
+    DQMC_HIP(ctx, launch());
+    if (k >= 0) DQMC_HIP(ctx, hipEventRecord(ctx->ev[2 * k + 1], s));
+    return DQMC_OK;
+}
+
 LowArgs low_args(dqmc_ctx *ctx, int n)
 {
     LowArgs a{};
@@ -120,13 +150,24 @@ int enqueue_merge(dqmc_ctx *ctx, int n, const uint32_t *tt, uint32_t *state, boo
     LowArgs a = low_args(ctx, n);
     a.tt = tt;
     a.state = state;
-    DQMC_HIP(ctx, launch_low(kLowMergeTT, a, pow2u(n - kLowDigits), s));
+    const double S = state_bytes(n);
+    const double binfrac_high = std::pow(2.0 / 3.0, n - kLowDigits);
+    int rc = run_pass(ctx, s, "low_merge_tt", n, tt_bytes(n) + S * binfrac_high, 0,
+                      [&] { return launch_low(kLowMergeTT, a, pow2u(n - kLowDigits), s); });
+    if (rc != DQMC_OK) return rc;
     const std::vector<Group> gs = plan_groups(n);
     for (size_t j = 0; j < gs.size(); ++j) {
         const bool top = j + 1 == gs.size();
         const int mode = (top && fuse_top_reduce) ? kColMergeReduce : kColMerge;
         const ColArgs c = col_args(state, n, gs[j], true);
-        DQMC_HIP(ctx, launch_col(gs[j].gr, gs[j].gw, mode, c, s));
+        const int od = n - (gs[j].g0 + gs[j].size() - 1);
+        const double fo = std::pow(2.0 / 3.0, od), fg = std::pow(2.0 / 3.0, gs[j].size());
+        const double bytes = mode == kColMerge ? S * fo * (fg + (1.0 - fg)) : S * fo * (fg + 1.0);
+        char name[40];
+        snprintf(name, sizeof(name), "%s_g%d_%d", mode == kColMerge ? "col_merge" : "col_merge_reduce", gs[j].g0,
+                 gs[j].size());
+        rc = run_pass(ctx, s, name, n, bytes, 0, [&] { return launch_col(gs[j].gr, gs[j].gw, mode, c, s); });
+        if (rc != DQMC_OK) return rc;
     }
     return DQMC_OK;
 }
@@ -141,8 +182,10 @@ int enqueue_extract_tiles(dqmc_ctx *ctx, int n, int mode, uint32_t *state, uint6
     a.count = count;
     if (a.desc) DQMC_HIP(ctx, launch_fill_u64(a.desc, a.ntiles, 0, s));
     DQMC_HIP(ctx, launch_fill_u32(a.ticket, 1, 0, s));
-    DQMC_HIP(ctx, launch_low(mode, a, a.ntiles, s));
-    return DQMC_OK;
+    const double S = state_bytes(n);
+    const bool reduce = mode == kLowReduceExtract;
+    return run_pass(ctx, s, reduce ? "low_reduce_extract" : "low_extract", n, reduce ? 2 * S : S, list ? 8 : 0,
+                    [&] { return launch_low(mode, a, a.ntiles, s); });
 }
 
 }  // namespace
@@ -166,6 +209,9 @@ int dqmc_create(int device, dqmc_ctx **out)
     c->device = device;
     c->desc_cap = pow3(DQMC_MAX_N - kLowDigits);
     c->err[0] = 0;
+    c->prof = false;
+    c->events_made = false;
+    c->nrec = 0;
     if (hipMalloc((void **)&c->desc, c->desc_cap * sizeof(uint64_t)) != hipSuccess) {
         delete c;
         return DQMC_ENOMEM;
@@ -183,6 +229,8 @@ void dqmc_destroy(dqmc_ctx *ctx)
 {
     if (ctx == nullptr) return;
     (void)hipSetDevice(ctx->device);
+    if (ctx->events_made)
+        for (int i = 0; i < 2 * DQMC_MAX_RECORDS; ++i) (void)hipEventDestroy(ctx->ev[i]);
     (void)hipFree(ctx->desc);
     (void)hipFree(ctx->ticket);
     delete ctx;
@@ -201,8 +249,8 @@ int dqmc_implicants(dqmc_ctx *ctx, int n, const uint32_t *d_tt, uint32_t *d_stat
         LowArgs a = low_args(ctx, n);
         a.tt = d_tt;
         a.state = d_state;
-        DQMC_HIP(ctx, launch_low(kLowMergeTT, a, 1, s));
-        return DQMC_OK;
+        return run_pass(ctx, s, "low_merge_tt", n, tt_bytes(n) + state_bytes(n), 0,
+                        [&] { return launch_low(kLowMergeTT, a, 1, s); });
     }
     return enqueue_merge(ctx, n, d_tt, d_state, false, s);
 }
@@ -224,15 +272,20 @@ int dqmc_primes(dqmc_ctx *ctx, int n, const uint32_t *d_tt, uint32_t *d_state, u
         a.list = d_list;
         a.cap = d_list ? list_cap : 0;
         a.count = d_count;
-        DQMC_HIP(ctx, launch_low(kLowPrimesTT, a, 1, s));
-        return DQMC_OK;
+        return run_pass(ctx, s, "low_primes_tt", n, tt_bytes(n) + state_bytes(n), d_list ? 8 : 0,
+                        [&] { return launch_low(kLowPrimesTT, a, 1, s); });
     }
     rc = enqueue_merge(ctx, n, d_tt, d_state, true, s);
     if (rc != DQMC_OK) return rc;
     const std::vector<Group> gs = plan_groups(n);
     for (int j = (int)gs.size() - 2; j >= 0; --j) {
         const ColArgs c = col_args(d_state, n, gs[j], false);
-        DQMC_HIP(ctx, launch_col(gs[j].gr, gs[j].gw, kColReduce, c, s));
+        const double S = state_bytes(n);
+        char name[40];
+        snprintf(name, sizeof(name), "col_reduce_g%d_%d", gs[j].g0, gs[j].size());
+        rc = run_pass(ctx, s, name, n, S * (2.0 - std::pow(3.0, -gs[j].size())), 0,
+                      [&] { return launch_col(gs[j].gr, gs[j].gw, kColReduce, c, s); });
+        if (rc != DQMC_OK) return rc;
     }
     return enqueue_extract_tiles(ctx, n, kLowReduceExtract, d_state, d_list, list_cap, d_count, s);
 }
@@ -255,8 +308,9 @@ int dqmc_bitmap_to_dense(dqmc_ctx *ctx, int n, const uint32_t *d_state, uint64_t
     if (rc != DQMC_OK) return rc;
     if (d_state == nullptr || d_dense == nullptr) return fail(ctx, DQMC_EINVAL, "%s", "NULL state or output");
     if (!aligned(d_state, 4) || !aligned(d_dense, 8)) return fail(ctx, DQMC_EINVAL, "%s", "misaligned buffer");
-    DQMC_HIP(ctx, launch_to_dense(n, d_state, d_dense, (hipStream_t)stream));
-    return DQMC_OK;
+    hipStream_t s = (hipStream_t)stream;
+    return run_pass(ctx, s, "to_dense", n, state_bytes(n) + 8.0 * (double)dqmc_dense_words(n), 0,
+                    [&] { return launch_to_dense(n, d_state, d_dense, s); });
 }
 
 int dqmc_primes_batch(dqmc_ctx *ctx, dqmc_job *jobs, int32_t njobs, void *stream)
@@ -269,6 +323,35 @@ int dqmc_primes_batch(dqmc_ctx *ctx, dqmc_job *jobs, int32_t njobs, void *stream
         if (j.status == DQMC_EDEVICE) return DQMC_EDEVICE;
     }
     return DQMC_OK;
+}
+
+int dqmc_profile(dqmc_ctx *ctx, int enable)
+{
+    if (ctx == nullptr) return DQMC_EINVAL;
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, DQMC_EDEVICE, "%s", "hipSetDevice failed");
+    if (enable && !ctx->events_made) {
+        for (int i = 0; i < 2 * DQMC_MAX_RECORDS; ++i) DQMC_HIP(ctx, hipEventCreate(&ctx->ev[i]));
+        ctx->events_made = true;
+    }
+    ctx->prof = enable != 0;
+    ctx->nrec = 0;
+    return DQMC_OK;
+}
+
+int dqmc_profile_read(dqmc_ctx *ctx, dqmc_pass_record *out, int cap)
+{
+    if (ctx == nullptr || (out == nullptr && cap > 0) || cap < 0) return DQMC_EINVAL;
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, DQMC_EDEVICE, "%s", "hipSetDevice failed");
+    const int k = ctx->nrec < cap ? ctx->nrec : cap;
+    for (int i = 0; i < k; ++i) {
+        DQMC_HIP(ctx, hipEventSynchronize(ctx->ev[2 * i + 1]));
+        float ms = 0.f;
+        DQMC_HIP(ctx, hipEventElapsedTime(&ms, ctx->ev[2 * i], ctx->ev[2 * i + 1]));
+        ctx->rec[i].ms = ms;
+        out[i] = ctx->rec[i];
+    }
+    ctx->nrec = 0;
+    return k;
 }
 
 }  // extern "C"

@@ -63,12 +63,16 @@ __global__ __launch_bounds__(col_threads<GW>()) void col_kernel(ColArgs a)
         uint64_t p = 1;
         for (uint64_t b = ob; b != 0; b >>= 1, p *= 3) o += (b & 1) * p;
     }
-    const int cw = GW == 0 ? 0 : (int)(threadIdx.x / 64);
+    // cw is uniform per wavefront; readfirstlane lets the row bases live in
+    // scalar registers so that each access is (scalar base + lane offset)
+    const int cw = GW == 0 ? 0 : __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64));
     const uint32_t lane = GW == 0 ? threadIdx.x : (threadIdx.x & 63);
-    const uint64_t l = lb * LANES + lane;
-    const bool active = l < a.L;
     const uint64_t L = a.L;
-    uint32_t *base = a.state + l + L * (uint64_t)CR * ((uint64_t)cw + (uint64_t)CW * o);
+    const uint64_t l64 = lb * LANES + lane;
+    const bool active = l64 < L;
+    const uint32_t l = (uint32_t)l64;  // L <= 3^18 for n <= 25
+    uint32_t *rows = a.state + L * (uint64_t)CR * ((uint64_t)cw + (uint64_t)CW * o);
+#define ROW(c) (rows + (uint64_t)(c) * L)
 
     uint32_t x[CR];
     bool cw_binary = true;
@@ -83,7 +87,7 @@ __global__ __launch_bounds__(col_threads<GW>()) void col_kernel(ColArgs a)
         if (cw_binary && active) {
             static_for<CR>([&](auto ci) {
                 constexpr int c = decltype(ci)::value;
-                if constexpr (all_binary(c, GR)) x[c] = base[(uint64_t)c * L];
+                if constexpr (all_binary(c, GR)) x[c] = ROW(c)[l];
             });
         }
         // 2. wave digits: u = s AND t across wavefronts (on binary cr only)
@@ -129,7 +133,7 @@ __global__ __launch_bounds__(col_threads<GW>()) void col_kernel(ColArgs a)
             if (active) {
                 static_for<CR>([&](auto ci) {
                     constexpr int c = decltype(ci)::value;
-                    if (!cw_binary || !all_binary(c, GR)) base[(uint64_t)c * L] = x[c];
+                    if (!cw_binary || !all_binary(c, GR)) ROW(c)[l] = x[c];
                 });
             }
             return;
@@ -137,7 +141,7 @@ __global__ __launch_bounds__(col_threads<GW>()) void col_kernel(ColArgs a)
     } else {
         static_for<CR>([&](auto ci) {
             constexpr int c = decltype(ci)::value;
-            x[c] = active ? base[(uint64_t)c * L] : 0u;
+            x[c] = active ? ROW(c)[l] : 0u;
         });
     }
 
@@ -172,11 +176,13 @@ __global__ __launch_bounds__(col_threads<GW>()) void col_kernel(ColArgs a)
             const bool cw_allstar = (GW == 0) || (cw == CW - 1);
             static_for<CR>([&](auto ci) {
                 constexpr int c = decltype(ci)::value;
-                if (MODE == kColMergeReduce || !(cw_allstar && c == CR - 1)) base[(uint64_t)c * L] = x[c];
+                if (MODE == kColMergeReduce || !(cw_allstar && c == CR - 1)) ROW(c)[l] = x[c];
             });
         }
     }
 }
+
+#undef ROW
 
 int col_lanes_per_block(int gw) { return gw == 0 ? 256 : 64; }
 

@@ -91,9 +91,9 @@ __device__ __forceinline__ void tile_extract(const uint32_t *t, const LowArgs &a
     const uint32_t nw = blockDim.x / 64, wv = threadIdx.x / 64, lane = lane_id();
     const uint32_t seg = (a.tw + nw - 1) / nw;
     const uint32_t s0 = min(a.tw, wv * seg), s1 = min(a.tw, s0 + seg);
-    uint64_t c = 0;
+    uint32_t c = 0;
     for (uint32_t w = s0 + lane; w < s1; w += 64) c += __popc(t[w]);
-    c = wave_sum(c);
+    c = wave_sum32(c);
     if (lane == 0) sh[wv] = c;
     __syncthreads();
     if (wv == 0) {
@@ -119,9 +119,10 @@ __device__ __forceinline__ void tile_extract(const uint32_t *t, const LowArgs &a
     for (uint32_t r0 = s0; r0 < s1 && run < a.cap; r0 += 64) {
         const uint32_t w = r0 + lane;
         uint32_t v = w < s1 ? t[w] : 0u;
-        const uint64_t cc = __popc(v);
-        const uint64_t incl = wave_inclusive_scan(cc);
-        uint64_t pos = run + incl - cc;
+        if (__ballot(v != 0u) == 0) continue;  // nothing to list in these 64 words
+        const uint32_t cc = __popc(v);
+        const uint32_t incl = wave_inclusive_scan32(cc);
+        uint64_t pos = run + (incl - cc);
         const uint64_t rbase = words ? 27ull * (wbase + w) : 0ull;
         while (v != 0u && pos < a.cap) {
             const uint32_t b = __builtin_ctz(v);
@@ -132,11 +133,79 @@ __device__ __forceinline__ void tile_extract(const uint32_t *t, const LowArgs &a
     }
 }
 
+constexpr uint32_t kMaxTileWords = 19683;  // 3^9
+
 template <int MODE>
-__global__ __launch_bounds__(kLowThreads) void low_kernel(LowArgs a)
+__host__ __device__ constexpr int low_threads()
 {
+    // the tile passes over HBM-resident states use one 27-word column per
+    // thread per LDS round (729 columns in a full tile)
+    return (MODE == kLowReduceExtract || MODE == kLowExtract) ? 768 : kLowThreads;
+}
+
+// Copy a tile from HBM into LDS (optionally applying the in-word Reduce),
+// with every load of a thread issued before the first LDS store.
+template <bool REDUCE, int THREADS>
+__device__ __forceinline__ void load_tile(uint32_t *t, const uint32_t *src, uint32_t tw)
+{
+    constexpr int U = (kMaxTileWords + THREADS - 1) / THREADS;
+    uint32_t v[U];
+    static_for<U>([&](auto ui) {
+        constexpr int u = decltype(ui)::value;
+        const uint32_t w = threadIdx.x + u * THREADS;
+        v[u] = w < tw ? __builtin_nontemporal_load(src + w) : 0u;
+    });
+    static_for<U>([&](auto ui) {
+        constexpr int u = decltype(ui)::value;
+        const uint32_t w = threadIdx.x + u * THREADS;
+        if (w < tw) t[w] = REDUCE ? inword_reduce(v[u]) : v[u];
+    });
+}
+
+template <int THREADS>
+__device__ __forceinline__ void store_tile(uint32_t *dst, const uint32_t *t, uint32_t tw)
+{
+    constexpr int U = (kMaxTileWords + THREADS - 1) / THREADS;
+    uint32_t v[U];
+    static_for<U>([&](auto ui) {
+        constexpr int u = decltype(ui)::value;
+        const uint32_t w = threadIdx.x + u * THREADS;
+        v[u] = w < tw ? t[w] : 0u;
+    });
+    static_for<U>([&](auto ui) {
+        constexpr int u = decltype(ui)::value;
+        const uint32_t w = threadIdx.x + u * THREADS;
+        if (w < tw) __builtin_nontemporal_store(v[u], dst + w);
+    });
+}
+
+// Last Reduce round of a full tile (digits 10..12, stride 729 words): thread q
+// owns column q, reduces it, and writes it both back to LDS (for the list)
+// and to HBM (the prime bitmap); consecutive threads write consecutive words.
+__device__ __forceinline__ void last_round_to_hbm(uint32_t *t, uint32_t *dst)
+{
+    constexpr uint32_t S = 729;
+    const uint32_t q = threadIdx.x;
+    if (q >= S) return;
+    uint32_t x[27];
+    static_for<27>([&](auto ci) {
+        constexpr int c = decltype(ci)::value;
+        x[c] = t[q + c * S];
+    });
+    reg_reduce<3>(x);
+    static_for<27>([&](auto ci) {
+        constexpr int c = decltype(ci)::value;
+        if constexpr (c != 26) t[q + c * S] = x[c];
+        __builtin_nontemporal_store(x[c], dst + q + c * S);
+    });
+}
+
+template <int MODE>
+__global__ __launch_bounds__(low_threads<MODE>()) void low_kernel(LowArgs a)
+{
+    constexpr int THREADS = low_threads<MODE>();
     extern __shared__ uint32_t dyn[];
-    __shared__ uint64_t sh[2 * (kLowThreads / 64) + 2];
+    __shared__ uint64_t sh[2 * (THREADS / 64) + 2];
     uint32_t *t = dyn;
 
     if constexpr (MODE == kLowMergeTT || MODE == kLowPrimesTT) {
@@ -160,18 +229,23 @@ __global__ __launch_bounds__(kLowThreads) void low_kernel(LowArgs a)
     } else {
         // tiles are taken in order from a ticket so that every tile a
         // look-back waits on is already resident
-        if (threadIdx.x == 0) sh[2 * (kLowThreads / 64)] = atomicAdd(a.ticket, 1u);
+        if (threadIdx.x == 0) sh[2 * (THREADS / 64)] = atomicAdd(a.ticket, 1u);
         __syncthreads();
-        const uint64_t tile = sh[2 * (kLowThreads / 64)];
+        const uint64_t tile = sh[2 * (THREADS / 64)];
         const uint32_t *src = a.state + tile * a.tw;
         if constexpr (MODE == kLowReduceExtract) {
-            for (uint32_t w = threadIdx.x; w < a.tw; w += blockDim.x) t[w] = inword_reduce(src[w]);
+            // always a full tile here (n > 12): digits 4..6, 7..9 in LDS,
+            // digits 10..12 in the last round, straight to HBM
+            load_tile<true, THREADS>(t, src, a.tw);
             __syncthreads();
-            lds_all_digits<false>(t, a.tw, a.lw);
-            uint32_t *dst = a.state + tile * a.tw;
-            for (uint32_t w = threadIdx.x; w < a.tw; w += blockDim.x) dst[w] = t[w];
+            lds_group<3, false>(t, a.tw, 1);
+            __syncthreads();
+            lds_group<3, false>(t, a.tw, 27);
+            __syncthreads();
+            last_round_to_hbm(t, a.state + tile * a.tw);
+            __syncthreads();
         } else {
-            for (uint32_t w = threadIdx.x; w < a.tw; w += blockDim.x) t[w] = src[w];
+            load_tile<false, THREADS>(t, src, a.tw);
             __syncthreads();
         }
         tile_extract(t, a, tile, sh);
@@ -203,12 +277,20 @@ hipError_t low_setup()
 hipError_t launch_low(int mode, const LowArgs &a, uint64_t nblocks, hipStream_t s)
 {
     const size_t lds = low_lds_bytes(mode, a.tw);
-    const dim3 grid((uint32_t)nblocks), block(kLowThreads);
+    const dim3 grid((uint32_t)nblocks);
     switch (mode) {
-    case kLowMergeTT: hipLaunchKernelGGL(low_kernel<kLowMergeTT>, grid, block, lds, s, a); break;
-    case kLowPrimesTT: hipLaunchKernelGGL(low_kernel<kLowPrimesTT>, grid, block, lds, s, a); break;
-    case kLowReduceExtract: hipLaunchKernelGGL(low_kernel<kLowReduceExtract>, grid, block, lds, s, a); break;
-    case kLowExtract: hipLaunchKernelGGL(low_kernel<kLowExtract>, grid, block, lds, s, a); break;
+    case kLowMergeTT:
+        hipLaunchKernelGGL(low_kernel<kLowMergeTT>, grid, dim3(low_threads<kLowMergeTT>()), lds, s, a);
+        break;
+    case kLowPrimesTT:
+        hipLaunchKernelGGL(low_kernel<kLowPrimesTT>, grid, dim3(low_threads<kLowPrimesTT>()), lds, s, a);
+        break;
+    case kLowReduceExtract:
+        hipLaunchKernelGGL(low_kernel<kLowReduceExtract>, grid, dim3(low_threads<kLowReduceExtract>()), lds, s, a);
+        break;
+    case kLowExtract:
+        hipLaunchKernelGGL(low_kernel<kLowExtract>, grid, dim3(low_threads<kLowExtract>()), lds, s, a);
+        break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -163,6 +163,24 @@ __device__ __forceinline__ uint64_t wave_inclusive_scan(uint64_t v)
     return v;
 }
 
+__device__ __forceinline__ uint32_t wave_inclusive_scan32(uint32_t v)
+{
+    const uint32_t lane = lane_id();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        uint32_t o = __shfl_up(v, d, 64);
+        if (lane >= (uint32_t)d) v += o;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_sum32(uint32_t v)
+{
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    return v;
+}
+
 __device__ __forceinline__ uint64_t wave_sum(uint64_t v)
 {
 #pragma unroll

@@ -33,6 +33,19 @@ class DqmcError(RuntimeError):
         self.code = code
 
 
+class dqmc_pass_record(ctypes.Structure):
+    _fields_ = [
+        ("pass_", ctypes.c_char * 40),
+        ("n", ctypes.c_int32),
+        ("list_bytes_per_prime", ctypes.c_int32),
+        ("ms", ctypes.c_float),
+        ("model_bytes", ctypes.c_double),
+    ]
+
+
+DQMC_MAX_RECORDS = 64
+
+
 class dqmc_job(ctypes.Structure):
     _fields_ = [
         ("n", ctypes.c_int32),
@@ -70,6 +83,8 @@ def load():
             "dqmc_extract": (i32, [vp, i32, vp, vp, u64, vp, vp]),
             "dqmc_bitmap_to_dense": (i32, [vp, i32, vp, vp, vp]),
             "dqmc_primes_batch": (i32, [vp, ctypes.POINTER(dqmc_job), ctypes.c_int32, vp]),
+            "dqmc_profile": (i32, [vp, i32]),
+            "dqmc_profile_read": (i32, [vp, ctypes.POINTER(dqmc_pass_record), i32]),
         }
         for name, (res, args) in sig.items():
             f = getattr(lib, name)
@@ -216,6 +231,22 @@ def dqmc_primes_batch(ctx, jobs, stream=None) -> list:
         arr[i].count = _ptr(j["count"], "count", torch.int64, 1) if j["count"] is not None else None
     _check(ctx, load().dqmc_primes_batch(ctx, arr, len(jobs), _stream(stream)))
     return [int(arr[i].status) for i in range(len(jobs))]
+
+
+def dqmc_profile(ctx, enable: bool) -> None:
+    _check(ctx, load().dqmc_profile(ctx, 1 if enable else 0))
+
+
+def dqmc_profile_read(ctx) -> list:
+    """Records of the passes enqueued since profiling was enabled or last
+    read: dicts with pass, n, ms, model_bytes, list_bytes_per_prime."""
+    arr = (dqmc_pass_record * DQMC_MAX_RECORDS)()
+    k = load().dqmc_profile_read(ctx, arr, DQMC_MAX_RECORDS)
+    if k < 0:
+        _check(ctx, k)
+    return [dict(pass_name=arr[i].pass_.decode(), n=arr[i].n, ms=float(arr[i].ms),
+                 model_bytes=float(arr[i].model_bytes), list_bytes_per_prime=arr[i].list_bytes_per_prime)
+            for i in range(k)]
 
 
 # ----------------------------------------------------------------------------

@@ -343,3 +343,16 @@ def test_per_cube_definitions_match_bitmaps():
         r = rng.randrange(3**n)
         assert oracle.is_implicant(n, tt, r) == (r in Ms)
         assert oracle.is_prime(n, tt, r) == (r in Os)
+
+
+def test_sample_matches_bitmaps():
+    n = 10
+    tt = inputs.bernoulli(n, 0.88, 1234)
+    M, O, _ = oracle.primes(n, tt)
+    rng = np.random.default_rng(3)
+    rhos = rng.integers(0, 3**n, size=3000, dtype=np.uint64)
+    pr, _ = oracle.sample(n, tt, rhos, "prime")
+    im, _ = oracle.sample(n, tt, rhos, "implicant")
+    Os, Ms = oracle.bitmap_to_set(n, O), oracle.bitmap_to_set(n, M)
+    assert [bool(int(r) in Os) for r in rhos] == pr.tolist()
+    assert [bool(int(r) in Ms) for r in rhos] == im.tolist()
