@@ -134,6 +134,21 @@ typedef struct {
 int dqmc_primes_batch(dqmc_ctx *ctx, dqmc_job *jobs, int32_t njobs, void *stream);
 
 /* ---------------------------------------------------------------------------
+ * Tuning: the pass plan.
+ *
+ * For n > 12 the digits 13..n are processed by column passes over groups of
+ * consecutive digits (Alg. 4's top-layer dimensions, several per memory
+ * sweep).  dqmc_set_plan chooses the group sizes used by this context for
+ * functions with n variables: sizes[0..ngroups) are the group sizes from
+ * digit 13 upwards, each in 1..6, summing to n - 12.  ngroups == 0 restores
+ * the default plan.  Every plan gives identical results; only speed differs.
+ * dqmc_get_plan writes the plan in use (at most cap sizes) and returns the
+ * number of groups.  Errors: DQMC_EINVAL for a bad n or bad sizes.
+ */
+int dqmc_set_plan(dqmc_ctx *ctx, int n, const int32_t *sizes, int ngroups);
+int dqmc_get_plan(const dqmc_ctx *ctx, int n, int32_t *sizes, int cap);
+
+/* ---------------------------------------------------------------------------
  * Diagnostics: per-pass device timing.
  *
  * With profiling enabled, every compute call on the context records a HIP

@@ -25,9 +25,12 @@ using namespace dqmc;
 
 struct dqmc_ctx {
     int device;
-    uint64_t *desc;      // look-back descriptors, one per low tile
-    uint64_t desc_cap;
-    uint32_t *ticket;
+    // per low tile: count of set bits, non-zero chunk map, list offset
+    uint64_t tiles_cap;
+    uint32_t *counts;
+    uint32_t *chunkmap;
+    uint64_t *offs;
+    uint64_t *sums;  // per-block sums of the count scan
     char err[512];
     // per-pass timing (diagnostics)
     bool prof;
@@ -35,6 +38,9 @@ struct dqmc_ctx {
     int nrec;
     hipEvent_t ev[2 * DQMC_MAX_RECORDS];
     dqmc_pass_record rec[DQMC_MAX_RECORDS];
+    // pass plan overrides: group sizes of digits 13..n (0 groups = default)
+    int plan_len[DQMC_MAX_N + 1];
+    int plan[DQMC_MAX_N + 1][DQMC_MAX_N];
 };
 
 namespace {
@@ -48,20 +54,36 @@ struct Group {
     int size() const { return gr + gw; }
 };
 
-std::vector<Group> plan_groups(int n)
+constexpr int kMaxGroup = 6;  // 4 digits in registers + 2 across wavefronts
+
+// Default plan: as few groups as possible, sizes as equal as possible.
+std::vector<int> default_sizes(int n)
 {
-    std::vector<Group> out;
+    std::vector<int> out;
     const int H = n - kLowDigits;
     if (H <= 0) return out;
-    const int k = (H + 5) / 6;
+    const int k = (H + kMaxGroup - 1) / kMaxGroup;
+    for (int j = 0; j < k; ++j) out.push_back(H / k + (j < H % k ? 1 : 0));
+    return out;
+}
+
+std::vector<Group> groups_of(const std::vector<int> &sizes)
+{
+    std::vector<Group> out;
     int g0 = kLowDigits + 1;
-    for (int j = 0; j < k; ++j) {
-        const int s = H / k + (j < H % k ? 1 : 0);
+    for (int s : sizes) {
         const int gr = s < 4 ? s : 4;
         out.push_back({g0, gr, s - gr});
         g0 += s;
     }
     return out;
+}
+
+std::vector<int> plan_sizes(const dqmc_ctx *ctx, int n)
+{
+    if (ctx != nullptr && n >= 0 && n <= DQMC_MAX_N && ctx->plan_len[n] > 0)
+        return std::vector<int>(ctx->plan[n], ctx->plan[n] + ctx->plan_len[n]);
+    return default_sizes(n);
 }
 
 uint64_t pow2u(int k) { return 1ull << k; }
@@ -123,8 +145,8 @@ LowArgs low_args(dqmc_ctx *ctx, int n)
     a.lw = n <= 3 ? 0 : (n - 3 < 9 ? n - 3 : 9);
     a.tw = (uint32_t)pow3(a.lw);
     a.ntiles = n <= kLowDigits ? 1 : pow3(n - kLowDigits);
-    a.desc = a.ntiles > 1 ? ctx->desc : nullptr;
-    a.ticket = ctx->ticket;
+    a.counts = ctx->counts;
+    a.chunkmap = ctx->chunkmap;
     a.cap = 0;
     return a;
 }
@@ -155,7 +177,7 @@ int enqueue_merge(dqmc_ctx *ctx, int n, const uint32_t *tt, uint32_t *state, boo
     int rc = run_pass(ctx, s, "low_merge_tt", n, tt_bytes(n) + S * binfrac_high, 0,
                       [&] { return launch_low(kLowMergeTT, a, pow2u(n - kLowDigits), s); });
     if (rc != DQMC_OK) return rc;
-    const std::vector<Group> gs = plan_groups(n);
+    const std::vector<Group> gs = groups_of(plan_sizes(ctx, n));
     for (size_t j = 0; j < gs.size(); ++j) {
         const bool top = j + 1 == gs.size();
         const int mode = (top && fuse_top_reduce) ? kColMergeReduce : kColMerge;
@@ -172,20 +194,28 @@ int enqueue_merge(dqmc_ctx *ctx, int n, const uint32_t *tt, uint32_t *state, boo
     return DQMC_OK;
 }
 
+// Final low-tile pass (reduce or plain count), scan of the tile counts, and
+// the list pass.
 int enqueue_extract_tiles(dqmc_ctx *ctx, int n, int mode, uint32_t *state, uint64_t *list, uint64_t cap,
                           uint64_t *count, hipStream_t s)
 {
     LowArgs a = low_args(ctx, n);
     a.state = state;
-    a.list = list;
-    a.cap = list ? cap : 0;
-    a.count = count;
-    if (a.desc) DQMC_HIP(ctx, launch_fill_u64(a.desc, a.ntiles, 0, s));
-    DQMC_HIP(ctx, launch_fill_u32(a.ticket, 1, 0, s));
     const double S = state_bytes(n);
-    const bool reduce = mode == kLowReduceExtract;
-    return run_pass(ctx, s, reduce ? "low_reduce_extract" : "low_extract", n, reduce ? 2 * S : S, list ? 8 : 0,
-                    [&] { return launch_low(mode, a, a.ntiles, s); });
+    const bool reduce = mode == kLowReduceCount;
+    int rc = run_pass(ctx, s, reduce ? "low_reduce_count" : "low_count", n,
+                      (reduce ? 2 * S : S) + a.ntiles * 4.0 * (1 + kMapWords), 0,
+                      [&] { return launch_low(mode, a, a.ntiles, s); });
+    if (rc != DQMC_OK) return rc;
+    rc = run_pass(ctx, s, "scan_counts", n, a.ntiles * 12.0, 0,
+                  [&] { return launch_scan_counts(ctx->counts, a.ntiles, ctx->offs, count, ctx->sums, s); });
+    if (rc != DQMC_OK || list == nullptr) return rc;
+    // the list pass reads the summaries and the non-zero chunks (data
+    // dependent, so only the summaries are in the model) and writes 8 bytes
+    // per listed prime
+    return run_pass(ctx, s, "list", n, a.ntiles * 4.0 * (3 + kMapWords), 8, [&] {
+        return launch_list(n, state, a.tw, a.ntiles, ctx->counts, ctx->chunkmap, ctx->offs, list, cap, s);
+    });
 }
 
 }  // namespace
@@ -207,18 +237,21 @@ int dqmc_create(int device, dqmc_ctx **out)
     if (low_setup() != hipSuccess || col_setup() != hipSuccess) return DQMC_EDEVICE;
     dqmc_ctx *c = new dqmc_ctx();
     c->device = device;
-    c->desc_cap = pow3(DQMC_MAX_N - kLowDigits);
+    c->tiles_cap = pow3(DQMC_MAX_N - kLowDigits);
+    c->counts = nullptr;
+    c->chunkmap = nullptr;
+    c->offs = nullptr;
+    c->sums = nullptr;
     c->err[0] = 0;
     c->prof = false;
     c->events_made = false;
     c->nrec = 0;
-    if (hipMalloc((void **)&c->desc, c->desc_cap * sizeof(uint64_t)) != hipSuccess) {
-        delete c;
-        return DQMC_ENOMEM;
-    }
-    if (hipMalloc((void **)&c->ticket, 256) != hipSuccess) {
-        (void)hipFree(c->desc);
-        delete c;
+    for (int i = 0; i <= DQMC_MAX_N; ++i) c->plan_len[i] = 0;
+    if (hipMalloc((void **)&c->counts, c->tiles_cap * sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc((void **)&c->chunkmap, c->tiles_cap * kMapWords * sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc((void **)&c->offs, c->tiles_cap * sizeof(uint64_t)) != hipSuccess ||
+        hipMalloc((void **)&c->sums, scan_scratch_words(c->tiles_cap) * sizeof(uint64_t)) != hipSuccess) {
+        dqmc_destroy(c);
         return DQMC_ENOMEM;
     }
     *out = c;
@@ -231,8 +264,10 @@ void dqmc_destroy(dqmc_ctx *ctx)
     (void)hipSetDevice(ctx->device);
     if (ctx->events_made)
         for (int i = 0; i < 2 * DQMC_MAX_RECORDS; ++i) (void)hipEventDestroy(ctx->ev[i]);
-    (void)hipFree(ctx->desc);
-    (void)hipFree(ctx->ticket);
+    if (ctx->counts) (void)hipFree(ctx->counts);
+    if (ctx->chunkmap) (void)hipFree(ctx->chunkmap);
+    if (ctx->offs) (void)hipFree(ctx->offs);
+    if (ctx->sums) (void)hipFree(ctx->sums);
     delete ctx;
 }
 
@@ -277,7 +312,7 @@ int dqmc_primes(dqmc_ctx *ctx, int n, const uint32_t *d_tt, uint32_t *d_state, u
     }
     rc = enqueue_merge(ctx, n, d_tt, d_state, true, s);
     if (rc != DQMC_OK) return rc;
-    const std::vector<Group> gs = plan_groups(n);
+    const std::vector<Group> gs = groups_of(plan_sizes(ctx, n));
     for (int j = (int)gs.size() - 2; j >= 0; --j) {
         const ColArgs c = col_args(d_state, n, gs[j], false);
         const double S = state_bytes(n);
@@ -287,7 +322,7 @@ int dqmc_primes(dqmc_ctx *ctx, int n, const uint32_t *d_tt, uint32_t *d_state, u
                       [&] { return launch_col(gs[j].gr, gs[j].gw, kColReduce, c, s); });
         if (rc != DQMC_OK) return rc;
     }
-    return enqueue_extract_tiles(ctx, n, kLowReduceExtract, d_state, d_list, list_cap, d_count, s);
+    return enqueue_extract_tiles(ctx, n, kLowReduceCount, d_state, d_list, list_cap, d_count, s);
 }
 
 int dqmc_extract(dqmc_ctx *ctx, int n, const uint32_t *d_state, uint64_t *d_list, uint64_t list_cap,
@@ -298,7 +333,7 @@ int dqmc_extract(dqmc_ctx *ctx, int n, const uint32_t *d_state, uint64_t *d_list
     if (d_state == nullptr || d_count == nullptr) return fail(ctx, DQMC_EINVAL, "%s", "NULL state or count");
     if (!aligned(d_state, 4) || !aligned(d_count, 8) || !aligned(d_list, 8))
         return fail(ctx, DQMC_EINVAL, "%s", "misaligned buffer");
-    return enqueue_extract_tiles(ctx, n, kLowExtract, const_cast<uint32_t *>(d_state), d_list, list_cap, d_count,
+    return enqueue_extract_tiles(ctx, n, kLowCount, const_cast<uint32_t *>(d_state), d_list, list_cap, d_count,
                                  (hipStream_t)stream);
 }
 
@@ -323,6 +358,32 @@ int dqmc_primes_batch(dqmc_ctx *ctx, dqmc_job *jobs, int32_t njobs, void *stream
         if (j.status == DQMC_EDEVICE) return DQMC_EDEVICE;
     }
     return DQMC_OK;
+}
+
+int dqmc_set_plan(dqmc_ctx *ctx, int n, const int32_t *sizes, int ngroups)
+{
+    if (ctx == nullptr) return DQMC_EINVAL;
+    ctx->err[0] = 0;
+    if (n <= kLowDigits || n > DQMC_MAX_N || ngroups < 0 || ngroups > DQMC_MAX_N ||
+        (ngroups > 0 && sizes == nullptr))
+        return fail(ctx, DQMC_EINVAL, "%s", "plan needs 12 < n <= 25 and 0 <= ngroups");
+    int sum = 0;
+    for (int i = 0; i < ngroups; ++i) {
+        if (sizes[i] < 1 || sizes[i] > kMaxGroup) return fail(ctx, DQMC_EINVAL, "%s", "group size outside 1..6");
+        sum += sizes[i];
+    }
+    if (ngroups > 0 && sum != n - kLowDigits) return fail(ctx, DQMC_EINVAL, "%s", "group sizes must sum to n - 12");
+    for (int i = 0; i < ngroups; ++i) ctx->plan[n][i] = sizes[i];
+    ctx->plan_len[n] = ngroups;
+    return DQMC_OK;
+}
+
+int dqmc_get_plan(const dqmc_ctx *ctx, int n, int32_t *sizes, int cap)
+{
+    if (ctx == nullptr || n < 0 || n > DQMC_MAX_N || cap < 0 || (sizes == nullptr && cap > 0)) return DQMC_EINVAL;
+    const std::vector<int> v = plan_sizes(ctx, n);
+    for (int i = 0; i < (int)v.size() && i < cap; ++i) sizes[i] = v[i];
+    return (int)v.size();
 }
 
 int dqmc_profile(dqmc_ctx *ctx, int enable)

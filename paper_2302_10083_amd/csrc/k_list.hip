@@ -1,0 +1,189 @@
+// Output step of Alg. 4: every set bit of the prime bitmap, as increasing
+// cube indices.  The bitmap pass leaves a summary per low tile (its number of
+// set bits and which 64-word chunks are non-zero); a scan turns the counts
+// into list offsets, and the list pass reads only the non-zero chunks.
+#include "launch.h"
+#include "t27.h"
+
+namespace dqmc {
+
+// Tile counts -> exclusive list offsets, in two launches: per-block sums of
+// kScanBlock counts, then every block adds up the sums of the blocks before
+// it and scans its own counts.
+constexpr int kScanThreads = 1024;
+constexpr int kScanPerThread = 8;
+constexpr int kScanBlock = kScanThreads * kScanPerThread;
+
+__global__ __launch_bounds__(kScanThreads) void block_sums_kernel(const uint32_t *counts, uint64_t ntiles,
+                                                                  uint64_t *sums)
+{
+    __shared__ uint64_t wsum[kScanThreads / 64];
+    const uint64_t b0 = (uint64_t)blockIdx.x * kScanBlock;
+    uint64_t c = 0;
+    for (int j = 0; j < kScanPerThread; ++j) {
+        const uint64_t t = b0 + (uint64_t)j * kScanThreads + threadIdx.x;
+        c += t < ntiles ? counts[t] : 0u;
+    }
+    c = wave_sum(c);
+    if (lane_id() == 0) wsum[threadIdx.x / 64] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t all = 0;
+        for (int w = 0; w < kScanThreads / 64; ++w) all += wsum[w];
+        sums[blockIdx.x] = all;
+    }
+}
+
+__global__ __launch_bounds__(kScanThreads) void scan_apply_kernel(const uint32_t *counts, uint64_t ntiles,
+                                                                  const uint64_t *sums, uint64_t nblocks,
+                                                                  uint64_t *offs, uint64_t *total)
+{
+    __shared__ uint64_t wsum[kScanThreads / 64];
+    __shared__ uint64_t base_sh;
+    const uint32_t wv = threadIdx.x / 64, lane = lane_id();
+    // sum of the blocks before this one (and of all blocks, for the total)
+    uint64_t before = 0, all = 0;
+    for (uint64_t b = threadIdx.x; b < nblocks; b += kScanThreads) {
+        before += b < blockIdx.x ? sums[b] : 0;
+        all += sums[b];
+    }
+    before = wave_sum(before);
+    all = wave_sum(all);
+    if (lane == 0) wsum[wv] = before;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t x = 0;
+        for (int w = 0; w < kScanThreads / 64; ++w) x += wsum[w];
+        base_sh = x;
+    }
+    __syncthreads();
+    const uint64_t base = base_sh;
+    __syncthreads();
+    if (lane == 0) wsum[wv] = all;
+    __syncthreads();
+    if (blockIdx.x == 0 && threadIdx.x == 0 && total != nullptr) {
+        uint64_t x = 0;
+        for (int w = 0; w < kScanThreads / 64; ++w) x += wsum[w];
+        *total = x;
+    }
+    __syncthreads();
+    // this thread's kScanPerThread consecutive counts
+    const uint64_t t0 = (uint64_t)blockIdx.x * kScanBlock + (uint64_t)threadIdx.x * kScanPerThread;
+    uint32_t v[kScanPerThread];
+    uint64_t mine = 0;
+    for (int j = 0; j < kScanPerThread; ++j) {
+        v[j] = t0 + j < ntiles ? counts[t0 + j] : 0u;
+        mine += v[j];
+    }
+    const uint64_t incl = wave_inclusive_scan(mine);
+    if (lane == 63) wsum[wv] = incl;
+    __syncthreads();
+    uint64_t run = base + incl - mine;
+    for (uint32_t w = 0; w < wv; ++w) run += wsum[w];
+    for (int j = 0; j < kScanPerThread; ++j) {
+        if (t0 + j < ntiles) offs[t0 + j] = run;
+        run += v[j];
+    }
+}
+
+hipError_t launch_scan_counts(const uint32_t *counts, uint64_t ntiles, uint64_t *offs, uint64_t *count,
+                              uint64_t *sums, hipStream_t s)
+{
+    const uint64_t nb = (ntiles + kScanBlock - 1) / kScanBlock;
+    hipLaunchKernelGGL(block_sums_kernel, dim3((uint32_t)nb), dim3(kScanThreads), 0, s, counts, ntiles, sums);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(scan_apply_kernel, dim3((uint32_t)nb), dim3(kScanThreads), 0, s, counts, ntiles, sums, nb,
+                       offs, count);
+    return hipGetLastError();
+}
+
+uint64_t scan_scratch_words(uint64_t ntiles) { return (ntiles + kScanBlock - 1) / kScanBlock; }
+
+struct ListArgs {
+    const uint32_t *state;
+    const uint32_t *counts;
+    const uint32_t *chunkmap;
+    const uint64_t *offs;
+    uint64_t *list;
+    uint64_t cap;
+    uint64_t ntiles;
+    uint32_t tw;
+    int n;
+};
+
+constexpr int kListThreads = 256;
+constexpr int kListBatch = 16;  // chunks whose words are loaded together
+
+// One wavefront per tile (grid-stride over tiles).  The non-zero chunks of
+// the tile are listed in order from its chunk map; their words are loaded
+// kListBatch chunks at a time, and each chunk's set bits are written at the
+// tile offset plus the running count (word-major, then bit).
+__global__ __launch_bounds__(kListThreads) void list_kernel(ListArgs a)
+{
+    constexpr int NW = kListThreads / 64;
+    __shared__ uint16_t nzs[NW][kTileChunks];
+    const uint32_t wv = threadIdx.x / 64, lane = lane_id();
+    uint16_t *nz = nzs[wv];
+    const bool words = a.n >= 3;
+    const uint64_t nwaves = (uint64_t)gridDim.x * NW;
+    for (uint64_t tile = (uint64_t)blockIdx.x * NW + wv; tile < a.ntiles; tile += nwaves) {
+        const uint32_t c = a.counts[tile];
+        const uint64_t off = a.offs[tile];
+        if (c == 0 || off >= a.cap) continue;
+        // ordered list of the non-zero chunks
+        const uint32_t mw = lane < (uint32_t)kMapWords ? a.chunkmap[tile * kMapWords + lane] : 0u;
+        const uint32_t pc = __popc(mw);
+        const uint32_t incl = wave_inclusive_scan32(pc);
+        const uint32_t m = __shfl(incl, 63, 64);
+        uint32_t pos = incl - pc, bits = mw;
+        while (bits != 0u) {
+            const uint32_t b = __builtin_ctz(bits);
+            bits &= bits - 1u;
+            nz[pos++] = (uint16_t)(lane * 32 + b);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        const uint32_t *src = a.state + tile * a.tw;
+        uint64_t run = off;
+        for (uint32_t r0 = 0; r0 < m && run < a.cap; r0 += kListBatch) {
+            uint32_t v[kListBatch];
+            static_for<kListBatch>([&](auto ii) {
+                constexpr int i = decltype(ii)::value;
+                const uint32_t w = (r0 + i < m) ? (uint32_t)nz[r0 + i] * kChunkWords + lane : a.tw;
+                v[i] = w < a.tw ? src[w] : 0u;
+            });
+            static_for<kListBatch>([&](auto ii) {
+                constexpr int i = decltype(ii)::value;
+                if (r0 + i < m) {
+                    uint32_t x = v[i];
+                    const uint32_t cc = __popc(x);
+                    const uint32_t inc = wave_inclusive_scan32(cc);
+                    uint64_t p = run + (inc - cc);
+                    const uint64_t w = (uint64_t)nz[r0 + i] * kChunkWords + lane;
+                    const uint64_t rbase = words ? 27ull * (tile * a.tw + w) : 0ull;
+                    while (x != 0u && p < a.cap) {
+                        const uint32_t b = __builtin_ctz(x);
+                        x &= x - 1u;
+                        a.list[p++] = rbase + b;
+                    }
+                    run += __shfl(inc, 63, 64);
+                }
+            });
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();  // nz is reused by the next tile
+    }
+}
+
+hipError_t launch_list(int n, const uint32_t *state, uint32_t tw, uint64_t ntiles, const uint32_t *counts,
+                       const uint32_t *chunkmap, const uint64_t *offs, uint64_t *list, uint64_t cap, hipStream_t s)
+{
+    ListArgs a{state, counts, chunkmap, offs, list, cap, ntiles, tw, n};
+    const uint64_t waves = (ntiles + 3) / 4;
+    uint64_t g = waves < 8192 ? waves : 8192;
+    hipLaunchKernelGGL(list_kernel, dim3((uint32_t)(g == 0 ? 1 : g)), dim3(kListThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace dqmc

@@ -83,10 +83,9 @@ __device__ __forceinline__ void load_tile_from_tt(uint32_t *t, uint32_t *lut, co
     __syncthreads();
 }
 
-// Ordered compaction of the set bits of an LDS tile into the global list.
-// Offsets across tiles come from decoupled look-back when desc != nullptr;
-// otherwise the tile is the only one.
-__device__ __forceinline__ void tile_extract(const uint32_t *t, const LowArgs &a, uint64_t tile, uint64_t *sh)
+// Ordered compaction of the set bits of a single-tile state (n <= 12) into
+// the list, and the total count.
+__device__ __forceinline__ void single_tile_extract(const uint32_t *t, const LowArgs &a, uint64_t *sh)
 {
     const uint32_t nw = blockDim.x / 64, wv = threadIdx.x / 64, lane = lane_id();
     const uint32_t seg = (a.tw + nw - 1) / nw;
@@ -96,25 +95,14 @@ __device__ __forceinline__ void tile_extract(const uint32_t *t, const LowArgs &a
     c = wave_sum32(c);
     if (lane == 0) sh[wv] = c;
     __syncthreads();
-    if (wv == 0) {
-        const uint64_t mine = lane < nw ? sh[lane] : 0;
-        const uint64_t incl = wave_inclusive_scan(mine);
-        const uint64_t total = __shfl(incl, 63, 64);
-        uint64_t off = 0;
-        if (a.desc != nullptr) {
-            if (lane == 0) desc_store(a.desc + tile, (tile == 0 ? kFlagPrefix : kFlagAgg) | total);
-            if (tile > 0) {
-                off = lookback_exclusive(a.desc, tile);
-                if (lane == 0) desc_store(a.desc + tile, kFlagPrefix | (off + total));
-            }
-        }
-        if (lane < nw) sh[nw + lane] = off + incl - mine;
-        if (lane == 0 && tile == a.ntiles - 1 && a.count != nullptr) *a.count = off + total;
+    uint64_t before = 0, total = 0;
+    for (uint32_t w = 0; w < nw; ++w) {
+        before += w < wv ? sh[w] : 0;
+        total += sh[w];
     }
-    __syncthreads();
+    if (threadIdx.x == 0 && a.count != nullptr) *a.count = total;
     if (a.list == nullptr) return;
-    uint64_t run = sh[nw + wv];
-    const uint64_t wbase = tile * (uint64_t)a.tw;
+    uint64_t run = before;
     const bool words = a.n >= 3;
     for (uint32_t r0 = s0; r0 < s1 && run < a.cap; r0 += 64) {
         const uint32_t w = r0 + lane;
@@ -123,7 +111,7 @@ __device__ __forceinline__ void tile_extract(const uint32_t *t, const LowArgs &a
         const uint32_t cc = __popc(v);
         const uint32_t incl = wave_inclusive_scan32(cc);
         uint64_t pos = run + (incl - cc);
-        const uint64_t rbase = words ? 27ull * (wbase + w) : 0ull;
+        const uint64_t rbase = words ? 27ull * w : 0ull;
         while (v != 0u && pos < a.cap) {
             const uint32_t b = __builtin_ctz(v);
             v &= v - 1u;
@@ -133,6 +121,27 @@ __device__ __forceinline__ void tile_extract(const uint32_t *t, const LowArgs &a
     }
 }
 
+// Summary of an LDS tile for the list pass: its number of set bits and the
+// bitmap of its non-zero 64-word chunks.
+__device__ __forceinline__ void tile_summary(const uint32_t *t, const LowArgs &a, uint64_t tile, uint32_t *red)
+{
+    const uint32_t nw = blockDim.x / 64, wv = threadIdx.x / 64, lane = lane_id();
+    if (threadIdx.x < kMapWords + 1) red[threadIdx.x] = 0;
+    __syncthreads();
+    uint32_t c = 0;
+    for (uint32_t k = wv; k < (uint32_t)kTileChunks; k += nw) {
+        const uint32_t w = k * kChunkWords + lane;
+        const uint32_t v = w < a.tw ? t[w] : 0u;
+        c += __popc(v);
+        if (__ballot(v != 0u) != 0 && lane == 0) atomicOr(&red[1 + k / 32], 1u << (k % 32));
+    }
+    c = wave_sum32(c);
+    if (lane == 0) atomicAdd(&red[0], c);
+    __syncthreads();
+    if (threadIdx.x == 0) a.counts[tile] = red[0];
+    if (threadIdx.x < kMapWords) a.chunkmap[tile * kMapWords + threadIdx.x] = red[1 + threadIdx.x];
+}
+
 constexpr uint32_t kMaxTileWords = 19683;  // 3^9
 
 template <int MODE>
@@ -140,7 +149,7 @@ __host__ __device__ constexpr int low_threads()
 {
     // the tile passes over HBM-resident states use one 27-word column per
     // thread per LDS round (729 columns in a full tile)
-    return (MODE == kLowReduceExtract || MODE == kLowExtract) ? 768 : kLowThreads;
+    return (MODE == kLowReduceCount || MODE == kLowCount) ? 768 : kLowThreads;
 }
 
 // Copy a tile from HBM into LDS (optionally applying the in-word Reduce),
@@ -180,24 +189,34 @@ __device__ __forceinline__ void store_tile(uint32_t *dst, const uint32_t *t, uin
 }
 
 // Last Reduce round of a full tile (digits 10..12, stride 729 words): thread q
-// owns column q, reduces it, and writes it both back to LDS (for the list)
-// and to HBM (the prime bitmap); consecutive threads write consecutive words.
-__device__ __forceinline__ void last_round_to_hbm(uint32_t *t, uint32_t *dst)
+// owns column q, reduces it, and writes it to HBM (the prime bitmap);
+// consecutive threads write consecutive words.  It also builds the tile
+// summary in `red` (zeroed before): red[0] = set bits, red[1..] = map of the
+// non-zero 64-word chunks.
+__device__ __forceinline__ void last_round_to_hbm(uint32_t *t, uint32_t *dst, uint32_t *red)
 {
     constexpr uint32_t S = 729;
     const uint32_t q = threadIdx.x;
-    if (q >= S) return;
-    uint32_t x[27];
-    static_for<27>([&](auto ci) {
-        constexpr int c = decltype(ci)::value;
-        x[c] = t[q + c * S];
-    });
-    reg_reduce<3>(x);
-    static_for<27>([&](auto ci) {
-        constexpr int c = decltype(ci)::value;
-        if constexpr (c != 26) t[q + c * S] = x[c];
-        __builtin_nontemporal_store(x[c], dst + q + c * S);
-    });
+    uint32_t c = 0;
+    if (q < S) {
+        uint32_t x[27];
+        static_for<27>([&](auto ci) {
+            constexpr int k = decltype(ci)::value;
+            x[k] = t[q + k * S];
+        });
+        reg_reduce<3>(x);
+        static_for<27>([&](auto ci) {
+            constexpr int k = decltype(ci)::value;
+            __builtin_nontemporal_store(x[k], dst + q + k * S);
+            c += __popc(x[k]);
+            if (x[k] != 0u) {
+                const uint32_t chunk = (q + k * S) / kChunkWords;
+                atomicOr(&red[1 + chunk / 32], 1u << (chunk % 32));
+            }
+        });
+    }
+    c = wave_sum32(c);
+    if (lane_id() == 0 && c != 0) atomicAdd(&red[0], c);
 }
 
 template <int MODE>
@@ -205,7 +224,7 @@ __global__ __launch_bounds__(low_threads<MODE>()) void low_kernel(LowArgs a)
 {
     constexpr int THREADS = low_threads<MODE>();
     extern __shared__ uint32_t dyn[];
-    __shared__ uint64_t sh[2 * (THREADS / 64) + 2];
+    __shared__ uint64_t sh[THREADS / 64];
     uint32_t *t = dyn;
 
     if constexpr (MODE == kLowMergeTT || MODE == kLowPrimesTT) {
@@ -224,31 +243,32 @@ __global__ __launch_bounds__(low_threads<MODE>()) void low_kernel(LowArgs a)
             __syncthreads();
             lds_all_digits<false>(t, a.tw, a.lw);
             for (uint32_t w = threadIdx.x; w < a.tw; w += blockDim.x) a.state[w] = t[w];
-            tile_extract(t, a, 0, sh);
+            single_tile_extract(t, a, sh);
         }
     } else {
-        // tiles are taken in order from a ticket so that every tile a
-        // look-back waits on is already resident
-        if (threadIdx.x == 0) sh[2 * (THREADS / 64)] = atomicAdd(a.ticket, 1u);
-        __syncthreads();
-        const uint64_t tile = sh[2 * (THREADS / 64)];
+        __shared__ uint32_t red[kMapWords + 1];
+        const uint64_t tile = blockIdx.x;
         const uint32_t *src = a.state + tile * a.tw;
-        if constexpr (MODE == kLowReduceExtract) {
+        if constexpr (MODE == kLowReduceCount) {
             // always a full tile here (n > 12): digits 4..6, 7..9 in LDS,
             // digits 10..12 in the last round, straight to HBM
+            if (threadIdx.x < kMapWords + 1) red[threadIdx.x] = 0;
             load_tile<true, THREADS>(t, src, a.tw);
             __syncthreads();
             lds_group<3, false>(t, a.tw, 1);
             __syncthreads();
             lds_group<3, false>(t, a.tw, 27);
             __syncthreads();
-            last_round_to_hbm(t, a.state + tile * a.tw);
+            last_round_to_hbm(t, a.state + tile * a.tw, red);
             __syncthreads();
+            if (threadIdx.x == 0) a.counts[tile] = red[0];
+            if (threadIdx.x < kMapWords) a.chunkmap[tile * kMapWords + threadIdx.x] = red[1 + threadIdx.x];
+            return;
         } else {
             load_tile<false, THREADS>(t, src, a.tw);
             __syncthreads();
         }
-        tile_extract(t, a, tile, sh);
+        tile_summary(t, a, tile, red);
     }
 }
 
@@ -267,10 +287,10 @@ hipError_t low_setup()
     if ((e = hipFuncSetAttribute((const void *)low_kernel<kLowPrimesTT>,
                                  hipFuncAttributeMaxDynamicSharedMemorySize, bytes)) != hipSuccess)
         return e;
-    if ((e = hipFuncSetAttribute((const void *)low_kernel<kLowReduceExtract>,
+    if ((e = hipFuncSetAttribute((const void *)low_kernel<kLowReduceCount>,
                                  hipFuncAttributeMaxDynamicSharedMemorySize, bytes)) != hipSuccess)
         return e;
-    return hipFuncSetAttribute((const void *)low_kernel<kLowExtract>,
+    return hipFuncSetAttribute((const void *)low_kernel<kLowCount>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
@@ -285,11 +305,11 @@ hipError_t launch_low(int mode, const LowArgs &a, uint64_t nblocks, hipStream_t 
     case kLowPrimesTT:
         hipLaunchKernelGGL(low_kernel<kLowPrimesTT>, grid, dim3(low_threads<kLowPrimesTT>()), lds, s, a);
         break;
-    case kLowReduceExtract:
-        hipLaunchKernelGGL(low_kernel<kLowReduceExtract>, grid, dim3(low_threads<kLowReduceExtract>()), lds, s, a);
+    case kLowReduceCount:
+        hipLaunchKernelGGL(low_kernel<kLowReduceCount>, grid, dim3(low_threads<kLowReduceCount>()), lds, s, a);
         break;
-    case kLowExtract:
-        hipLaunchKernelGGL(low_kernel<kLowExtract>, grid, dim3(low_threads<kLowExtract>()), lds, s, a);
+    case kLowCount:
+        hipLaunchKernelGGL(low_kernel<kLowCount>, grid, dim3(low_threads<kLowCount>()), lds, s, a);
         break;
     default: return hipErrorInvalidValue;
     }

@@ -11,9 +11,15 @@ namespace dqmc {
 enum LowMode : int {
     kLowMergeTT = 0,        // truth table -> merged tile (digits 1..12) -> state
     kLowPrimesTT = 1,       // n <= 12: truth table -> M -> O -> state + list
-    kLowReduceExtract = 2,  // state -> reduce digits 1..12 -> state + list
-    kLowExtract = 3,        // state -> list only (no transform, no write)
+    kLowReduceCount = 2,    // state -> reduce digits 1..12 -> state + tile info
+    kLowCount = 3,          // state -> tile info only (no transform, no write)
 };
+
+// Per-tile summary written by kLowReduceCount / kLowCount: the number of set
+// bits, and a bitmap of the 64-word chunks that hold any set bit.
+constexpr int kChunkWords = 64;
+constexpr int kTileChunks = (19683 + kChunkWords - 1) / kChunkWords;  // 308
+constexpr int kMapWords = (kTileChunks + 31) / 32;                   // 10
 
 struct LowArgs {
     const uint32_t *tt;
@@ -21,8 +27,8 @@ struct LowArgs {
     uint64_t *list;
     uint64_t cap;
     uint64_t *count;
-    uint64_t *desc;     // look-back descriptors, one per tile (zeroed before)
-    uint32_t *ticket;   // dynamic tile counter (zeroed before)
+    uint32_t *counts;   // per tile: number of set bits (count modes)
+    uint32_t *chunkmap; // per tile: kMapWords words, bit k = chunk k non-zero
     uint64_t ntiles;
     uint32_t tw;        // words per tile
     int n;
@@ -32,6 +38,16 @@ struct LowArgs {
 constexpr int kLowThreads = 256;
 
 hipError_t low_setup();
+
+// Exclusive scan of the tile counts into offs (uint64, one per tile) and the
+// total into *count.
+hipError_t launch_scan_counts(const uint32_t *counts, uint64_t ntiles, uint64_t *offs, uint64_t *count,
+                              uint64_t *sums, hipStream_t s);
+uint64_t scan_scratch_words(uint64_t ntiles);  // size of `sums`
+// List of the set bits of the tiles in increasing cube index, using the tile
+// summaries and offsets (only chunks marked non-zero are read).
+hipError_t launch_list(int n, const uint32_t *state, uint32_t tw, uint64_t ntiles, const uint32_t *counts,
+                       const uint32_t *chunkmap, const uint64_t *offs, uint64_t *list, uint64_t cap, hipStream_t s);
 hipError_t launch_low(int mode, const LowArgs &a, uint64_t nblocks, hipStream_t s);
 
 // High-digit groups: one pass applies Merge and/or Reduce for a group of

@@ -199,46 +199,4 @@ __device__ __forceinline__ uint64_t xcd_remap(uint64_t b, uint64_t nb)
     return (xcd < rem) ? xcd * (q + 1) + slot : rem * (q + 1) + (xcd - rem) * q + slot;
 }
 
-// ---------------------------------------------------------------------------
-// decoupled look-back descriptors (Merrill and Garland, "Single-pass parallel
-// prefix scan with decoupled look-back", 2016)
-
-constexpr uint64_t kFlagAgg = 1ull << 62;
-constexpr uint64_t kFlagPrefix = 2ull << 62;
-constexpr uint64_t kValMask = (1ull << 62) - 1;
-
-__device__ __forceinline__ void desc_store(uint64_t *p, uint64_t v)
-{
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ uint64_t desc_load(const uint64_t *p)
-{
-    return __hip_atomic_load(const_cast<uint64_t *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Called by one whole wavefront of tile `t` after lane 0 published its own
-// aggregate.  Returns the exclusive prefix of tile t (sum over tiles < t).
-__device__ __forceinline__ uint64_t lookback_exclusive(const uint64_t *desc, uint64_t t)
-{
-    const uint32_t lane = lane_id();
-    uint64_t excl = 0;
-    int64_t j = (int64_t)t - 1;
-    for (;;) {
-        const int64_t idx = j - (int64_t)lane;
-        uint64_t d = idx >= 0 ? desc_load(desc + idx) : kFlagPrefix;
-        while (__ballot(d == 0) != 0) {
-            __builtin_amdgcn_s_sleep(1);
-            if (d == 0) d = desc_load(desc + idx);
-        }
-        const uint64_t pref = __ballot((d & kFlagPrefix) != 0);
-        const uint32_t stop = pref ? (uint32_t)__builtin_ctzll(pref) : 64u;
-        uint64_t v = (lane <= stop) ? (d & kValMask) : 0;
-        excl += wave_sum(v);
-        if (pref) break;
-        j -= 64;
-    }
-    return excl;
-}
-
 }  // namespace dqmc

@@ -84,6 +84,8 @@ def load():
             "dqmc_bitmap_to_dense": (i32, [vp, i32, vp, vp, vp]),
             "dqmc_primes_batch": (i32, [vp, ctypes.POINTER(dqmc_job), ctypes.c_int32, vp]),
             "dqmc_profile": (i32, [vp, i32]),
+            "dqmc_set_plan": (i32, [vp, i32, ctypes.POINTER(ctypes.c_int32), i32]),
+            "dqmc_get_plan": (i32, [vp, i32, ctypes.POINTER(ctypes.c_int32), i32]),
             "dqmc_profile_read": (i32, [vp, ctypes.POINTER(dqmc_pass_record), i32]),
         }
         for name, (res, args) in sig.items():
@@ -231,6 +233,20 @@ def dqmc_primes_batch(ctx, jobs, stream=None) -> list:
         arr[i].count = _ptr(j["count"], "count", torch.int64, 1) if j["count"] is not None else None
     _check(ctx, load().dqmc_primes_batch(ctx, arr, len(jobs), _stream(stream)))
     return [int(arr[i].status) for i in range(len(jobs))]
+
+
+def dqmc_set_plan(ctx, n: int, sizes) -> None:
+    """Group sizes of digits 13..n for this context ([] = default plan)."""
+    arr = (ctypes.c_int32 * max(1, len(sizes)))(*[int(x) for x in sizes])
+    _check(ctx, load().dqmc_set_plan(ctx, n, arr, len(sizes)))
+
+
+def dqmc_get_plan(ctx, n: int) -> list:
+    arr = (ctypes.c_int32 * 32)()
+    k = load().dqmc_get_plan(ctx, n, arr, 32)
+    if k < 0:
+        _check(ctx, k)
+    return [int(arr[i]) for i in range(k)]
 
 
 def dqmc_profile(ctx, enable: bool) -> None:

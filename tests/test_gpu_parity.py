@@ -166,3 +166,46 @@ def test_variable_permutation_equivariance_n16():
     digs = (l0.astype(np.int64)[:, None] // p3[None, :]) % 3
     mapped = (digs[:, perm] * p3[None, :]).sum(axis=1)
     assert np.array_equal(np.sort(mapped), l1.astype(np.int64))
+
+
+# ----------------------------------------------------------------------------
+# every plan gives the same primes; forcing plans exercises every column-pass
+# shape (registers x wavefronts) in every mode at sizes the oracle handles
+
+
+PLANS = [
+    (16, [2, 2]), (16, [1, 3]), (16, [3, 1]), (17, [1, 1, 1, 1, 1]), (17, [5]),
+    (18, [5, 1]), (18, [2, 2, 2]), (18, [1, 5]), (18, [6]),
+    (19, [6, 1]), (19, [1, 6]), (19, [3, 4]), (19, [4, 3]), (19, [5, 2]),
+]
+
+
+@pytest.mark.parametrize("n,sizes", PLANS)
+def test_forced_plans(n, sizes):
+    from paper_2302_10083_amd import dqmc
+
+    ctx = context()
+    dqmc.dqmc_set_plan(ctx.ctx, n, sizes)
+    try:
+        assert dqmc.dqmc_get_plan(ctx.ctx, n) == sizes
+        check_against_oracle(n, make_tt(n, "bern0.92", 500 + n + len(sizes)), "plan %s" % sizes)
+    finally:
+        dqmc.dqmc_set_plan(ctx.ctx, n, [])
+
+
+def test_plan_validation():
+    from paper_2302_10083_amd import dqmc
+
+    ctx = context()
+    for n, sizes in ((12, [1]), (16, [2, 1]), (16, [7, -3]), (20, [7, 1]), (26, [14])):
+        with pytest.raises(dqmc.DqmcError):
+            dqmc.dqmc_set_plan(ctx.ctx, n, sizes)
+    assert dqmc.dqmc_get_plan(ctx.ctx, 24) == [6, 6]
+    assert dqmc.dqmc_get_plan(ctx.ctx, 25) == [5, 4, 4]
+    assert dqmc.dqmc_get_plan(ctx.ctx, 12) == []
+
+
+@pytest.mark.parametrize("name", ["c2a_n20_bern09", "c2b_n20_dnf200"])
+def test_config_n20_full_parity(name):
+    tt = inputs.config(name)
+    check_against_oracle(20, tt, name)
