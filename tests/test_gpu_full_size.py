@@ -1,0 +1,185 @@
+"""Parity at the full benchmark sizes (n = 24, 25), where the oracle cannot
+build whole bitmaps: sampled cubes are checked one by one with the oracle's
+per-cube definitions, and closed-form families are checked exactly.  The
+launch sequence is the one bench.py times (dqmc_primes with the default
+plan)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2302_10083_amd import inputs
+
+from _gpu_common import context, log
+
+pytestmark = pytest.mark.gpu
+
+
+def _bits_at(state, n, rhos):
+    """State bits at the given cube indices (gathered on the device)."""
+    import torch
+
+    r = torch.from_numpy(np.asarray(rhos, dtype=np.int64)).to(state.device)
+    w = torch.div(r, 27, rounding_mode="floor")
+    b = torch.remainder(r, 27)
+    return ((state[w].to(torch.int64) >> b) & 1).cpu().numpy().astype(bool)
+
+
+def _popcount_state(state):
+    import torch
+
+    total = 0
+    chunk = 1 << 28
+    for i in range(0, state.numel(), chunk):
+        part = state[i:i + chunk]
+        x = part.to(torch.int64) & 0x7FFFFFF
+        # SWAR popcount on int64 lanes holding 27-bit words
+        x = x - ((x >> 1) & 0x5555555555555555)
+        x = (x & 0x3333333333333333) + ((x >> 2) & 0x3333333333333333)
+        x = (x + (x >> 4)) & 0x0F0F0F0F0F0F0F0F
+        x = (x * 0x0101010101010101) >> 56
+        total += int((x & 0xFF).sum().item())
+        del part, x
+    return total
+
+
+def _run(n, tt, list_cap=None):
+    import torch
+
+    from paper_2302_10083_amd import dqmc
+
+    ctx = context()
+    ttd = ctx.tt_to_device(tt)
+    state = ctx.new_state(n)
+    count = torch.zeros(1, dtype=torch.int64, device=ctx.torch_device)
+    dqmc.dqmc_primes(ctx.ctx, n, ttd, state, None, 0, count)
+    torch.cuda.synchronize()
+    c = int(count.item())
+    lst = None
+    if list_cap is not None:
+        # the same call bench.py times: bitmap and list in one dqmc_primes
+        k = min(c, list_cap)
+        lst = torch.empty(max(k, 1), dtype=torch.int64, device=ctx.torch_device)
+        dqmc.dqmc_primes(ctx.ctx, n, ttd, state, lst, k, count)
+        torch.cuda.synchronize()
+        assert int(count.item()) == c
+        lst = lst[:k]
+    return state, lst, c
+
+
+def test_config_c3_n24_sampled():
+    import torch
+
+    n = 24
+    tt = inputs.config("c3_n24_dnf2000_noise")
+    log("c3 n=24: primes")
+    state, lst, c = _run(n, tt, list_cap=1 << 62)
+    # the bitmap agrees with the per-cube definition on random cubes
+    rng = np.random.default_rng(24)
+    rhos = rng.integers(0, 3**n, size=400_000, dtype=np.int64)
+    got = _bits_at(state, n, rhos)
+    ref, _ = oracle.sample(n, tt, rhos.astype(np.uint64), "prime", 16)
+    assert np.array_equal(got, ref), "%d mismatches" % int(np.count_nonzero(got != ref))
+    # the list: strictly increasing, every entry set in the bitmap, count =
+    # number of set bits, and sampled entries are primes by definition
+    lh = lst.cpu().numpy()
+    assert len(lh) == c
+    assert np.all(np.diff(lh) > 0) and lh[0] >= 0 and lh[-1] < 3**n
+    assert _bits_at(state, n, lh[:: max(1, len(lh) // 200_000)]).all()
+    assert _popcount_state(state) == c
+    pick = lh[:: max(1, len(lh) // 3000)]
+    pr, _ = oracle.sample(n, tt, pick.astype(np.uint64), "prime", 16)
+    assert pr.all()
+    del state, lst
+    torch.cuda.empty_cache()
+
+
+def test_config_c3_n24_implicants_sampled():
+    import torch
+
+    n = 24
+    tt = inputs.config("c3_n24_dnf2000_noise")
+    ctx = context()
+    state = ctx.implicants(n, ctx.tt_to_device(tt))
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(2424)
+    # bias towards low-weight cubes so that implicants are well represented
+    d = rng.choice(3, size=(200_000, n), p=[0.4, 0.4, 0.2])
+    rhos = (d * (3 ** np.arange(n, dtype=np.int64))[None, :]).sum(axis=1)
+    got = _bits_at(state, n, rhos)
+    ref, _ = oracle.sample(n, tt, rhos.astype(np.uint64), "implicant", 16)
+    assert ref.any() and not ref.all()
+    assert np.array_equal(got, ref)
+    del state
+    torch.cuda.empty_cache()
+
+
+def _term_string(n, care, val):
+    return "".join(("1" if (val >> i) & 1 else "0") if (care >> i) & 1 else "*" for i in range(n))
+
+
+@pytest.mark.parametrize("n", [24, 25])
+def test_constants_full_size(n):
+    import torch
+
+    state, lst, c = _run(n, inputs.constant(n, 1), list_cap=16)
+    assert c == 1 and lst.cpu().numpy().tolist() == [3**n - 1]
+    del state
+    state, lst, c = _run(n, inputs.constant(n, 0), list_cap=16)
+    assert c == 0
+    del state
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("n", [24, 25])
+def test_unate_dnf_exact_full_size(n):
+    """Unate DNF: the primes are exactly the terms left after absorption."""
+    import torch
+
+    terms = inputs.unate_terms(n, 300, 6, 14, 7000 + n)
+    tt = inputs.from_terms(n, terms)
+    ts = sorted(set(terms))
+    keep = [t for t in ts if not any(u != t and (u[0] & t[0]) == u[0] for u in ts)]
+    expected = sorted(oracle.rho_of(_term_string(n, c_, v_)) for c_, v_ in keep)
+    log("unate n=%d: %d primes expected" % (n, len(expected)))
+    state, lst, c = _run(n, tt, list_cap=len(expected) + 8)
+    assert c == len(expected)
+    assert lst.cpu().numpy().tolist() == expected
+    del state
+    torch.cuda.empty_cache()
+
+
+def test_parity_n24():
+    import torch
+
+    n = 24
+    state, lst, c = _run(n, inputs.parity(n), list_cap=1 << 24)
+    assert c == 1 << (n - 1)
+    lh = lst.cpu().numpy()
+    assert np.all(np.diff(lh) > 0)
+    # every listed cube is a minterm (no *) with an odd number of ones
+    lh = lh[:: 37]
+    digs = (lh[:, None] // (3 ** np.arange(n, dtype=np.int64))[None, :]) % 3
+    assert not (digs == 2).any()
+    assert np.all(digs.sum(axis=1) % 2 == 1)
+    del state
+    torch.cuda.empty_cache()
+
+
+def test_interval_symmetric_n24_count_and_sample():
+    """f = [a <= |x| <= b]: the primes are the cubes with a ones and b-a stars."""
+    import torch
+
+    n, a, b = 24, 9, 13
+    state, _, c = _run(n, inputs.interval(n, a, b))
+    assert c == math.comb(n, a) * math.comb(n - a, b - a)
+    rng = np.random.default_rng(5)
+    d = rng.choice(3, size=(300_000, n), p=[0.4, 0.4, 0.2])
+    rhos = (d * (3 ** np.arange(n, dtype=np.int64))[None, :]).sum(axis=1)
+    ones, stars = (d == 1).sum(axis=1), (d == 2).sum(axis=1)
+    expect = (ones == a) & (ones + stars == b)
+    assert expect.any()
+    assert np.array_equal(_bits_at(state, n, rhos), expect)
+    del state
+    torch.cuda.empty_cache()
