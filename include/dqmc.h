@@ -27,8 +27,9 @@
  *  stream    a hipStream_t passed as void* (NULL = the null stream).
  *
  *  Ownership: the caller owns and allocates every buffer argument (device
- *  memory unless stated otherwise); the context owns only small scratch
- *  memory allocated when it is created (no entry point allocates).
+ *  memory unless stated otherwise).  The context owns small scratch memory
+ *  allocated when it is created, a batch plan owns its job table allocated
+ *  by dqmc_batch_create; no other entry point allocates.
  *  Asynchrony: compute entry points only enqueue work on `stream` and return;
  *  results are valid after the stream is synchronised.  Argument errors are
  *  found on the host before anything is enqueued and return DQMC_EINVAL;
@@ -127,10 +128,31 @@ typedef struct {
 } dqmc_job;
 
 /* Prime implicants of many independent functions (the batch bit-slicing of
- * independent executions, Sec. 4.2) in one enqueued launch sequence.  The
- * result of each job is exactly what dqmc_primes gives for it alone.
- * Returns DQMC_OK if at least the call itself was valid (per-job errors are
- * in jobs[i].status), DQMC_EINVAL for a NULL/negative job array. */
+ * independent executions, Sec. 4.2).  Functions with n <= 16 run in ONE
+ * persistent launch in which each workgroup takes the next function (largest
+ * first) and runs its whole pipeline; larger functions of the batch take the
+ * single-function path on the same stream afterwards.  The result of each
+ * job is exactly what dqmc_primes gives for it alone.
+ *
+ * Plans separate the host work (checks, ordering, upload of the job table)
+ * from the launch, so that dqmc_batch_run can be captured in a HIP graph and
+ * replayed; it allocates nothing.  The buffers the jobs point to must stay
+ * valid while a plan is run.
+ *   dqmc_batch_create: jobs[i].status is set (DQMC_OK, or DQMC_EINVAL for a
+ *     malformed job, which is left out while the others still run); the
+ *     plan's device memory (job table) is allocated here.  Returns DQMC_OK,
+ *     DQMC_EINVAL for a NULL/negative job array, DQMC_ENOMEM / DQMC_EDEVICE.
+ *   dqmc_batch_config: grid = number of persistent workgroups (0 = default:
+ *     two per compute unit); order = 0 largest first, 1 interleaved sizes.
+ *   dqmc_batch_run: enqueue everything on `stream`.
+ *   dqmc_batch_destroy: free the plan (no run may be in flight).
+ * dqmc_primes_batch = create + run + wait for the stream + destroy: it
+ * returns after the results are complete. */
+typedef struct dqmc_batch dqmc_batch;
+int dqmc_batch_create(dqmc_ctx *ctx, dqmc_job *jobs, int32_t njobs, dqmc_batch **out);
+int dqmc_batch_config(dqmc_batch *plan, int32_t grid, int32_t order);
+int dqmc_batch_run(dqmc_batch *plan, void *stream);
+void dqmc_batch_destroy(dqmc_batch *plan);
 int dqmc_primes_batch(dqmc_ctx *ctx, dqmc_job *jobs, int32_t njobs, void *stream);
 
 /* ---------------------------------------------------------------------------

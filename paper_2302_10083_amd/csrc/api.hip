@@ -14,6 +14,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -234,7 +235,7 @@ int dqmc_create(int device, dqmc_ctx **out)
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return DQMC_EDEVICE;
     if (hipSetDevice(device) != hipSuccess) return DQMC_EDEVICE;
-    if (low_setup() != hipSuccess || col_setup() != hipSuccess) return DQMC_EDEVICE;
+    if (low_setup() != hipSuccess || col_setup() != hipSuccess || batch_setup() != hipSuccess) return DQMC_EDEVICE;
     dqmc_ctx *c = new dqmc_ctx();
     c->device = device;
     c->tiles_cap = pow3(DQMC_MAX_N - kLowDigits);
@@ -348,16 +349,146 @@ int dqmc_bitmap_to_dense(dqmc_ctx *ctx, int n, const uint32_t *d_state, uint64_t
                     [&] { return launch_to_dense(n, d_state, d_dense, s); });
 }
 
-int dqmc_primes_batch(dqmc_ctx *ctx, dqmc_job *jobs, int32_t njobs, void *stream)
+}  // extern "C"
+
+struct dqmc_batch {
+    dqmc_ctx *ctx;
+    BatchJob *d_jobs;
+    uint32_t *d_order;
+    uint32_t *d_ticket;
+    std::vector<BatchJob> small;  // n <= kBatchMaxN, in job-table order
+    std::vector<BatchJob> big;    // larger functions: single-function path
+    int32_t grid;
+    int32_t order_mode;
+};
+
+namespace {
+
+int batch_upload_order(dqmc_batch *b)
 {
-    if (ctx == nullptr || njobs < 0 || (jobs == nullptr && njobs > 0)) return DQMC_EINVAL;
+    const size_t m = b->small.size();
+    std::vector<uint32_t> ord(m);
+    for (size_t i = 0; i < m; ++i) ord[i] = (uint32_t)i;
+    // largest first (stable), so that the longest jobs start early
+    std::stable_sort(ord.begin(), ord.end(), [&](uint32_t x, uint32_t y) { return b->small[x].n > b->small[y].n; });
+    if (b->order_mode == 1) {
+        // interleave from both ends: largest, smallest, second largest, ...
+        std::vector<uint32_t> il;
+        size_t lo = 0, hi = m;
+        while (lo < hi) {
+            il.push_back(ord[lo++]);
+            if (lo < hi) il.push_back(ord[--hi]);
+        }
+        ord.swap(il);
+    }
+    if (m > 0 && hipMemcpy(b->d_order, ord.data(), m * sizeof(uint32_t), hipMemcpyHostToDevice) != hipSuccess)
+        return fail(b->ctx, DQMC_EDEVICE, "%s", "upload of the batch order failed");
+    return DQMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void dqmc_batch_destroy(dqmc_batch *b)
+{
+    if (b == nullptr) return;
+    (void)hipSetDevice(b->ctx->device);
+    if (b->d_jobs) (void)hipFree(b->d_jobs);
+    if (b->d_order) (void)hipFree(b->d_order);
+    if (b->d_ticket) (void)hipFree(b->d_ticket);
+    delete b;
+}
+
+int dqmc_batch_create(dqmc_ctx *ctx, dqmc_job *jobs, int32_t njobs, dqmc_batch **out)
+{
+    if (out != nullptr) *out = nullptr;
+    if (ctx == nullptr || out == nullptr || njobs < 0 || (jobs == nullptr && njobs > 0)) return DQMC_EINVAL;
     ctx->err[0] = 0;
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, DQMC_EDEVICE, "%s", "hipSetDevice failed");
+    dqmc_batch *b = new dqmc_batch();
+    b->ctx = ctx;
+    b->d_jobs = nullptr;
+    b->d_order = nullptr;
+    b->d_ticket = nullptr;
+    b->order_mode = 0;
     for (int32_t i = 0; i < njobs; ++i) {
         dqmc_job &j = jobs[i];
-        j.status = dqmc_primes(ctx, j.n, j.tt, j.state, j.list, j.list_cap, j.count, stream);
-        if (j.status == DQMC_EDEVICE) return DQMC_EDEVICE;
+        const bool ok = j.n >= 0 && j.n <= DQMC_MAX_N && j.tt != nullptr && j.state != nullptr &&
+                        j.count != nullptr && aligned(j.tt, 4) && aligned(j.state, 4) && aligned(j.count, 8) &&
+                        aligned(j.list, 8);
+        j.status = ok ? DQMC_OK : DQMC_EINVAL;
+        if (!ok) continue;
+        BatchJob bj{j.tt, j.state, j.list, j.list ? j.list_cap : 0, j.count, j.n, 0};
+        (j.n <= kBatchMaxN ? b->small : b->big).push_back(bj);
+    }
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess || ncu <= 0)
+        ncu = 256;
+    b->grid = 2 * ncu;
+    const size_t m = b->small.size();
+    if (hipMalloc((void **)&b->d_ticket, 256) != hipSuccess ||
+        (m > 0 && (hipMalloc((void **)&b->d_jobs, m * sizeof(BatchJob)) != hipSuccess ||
+                   hipMalloc((void **)&b->d_order, m * sizeof(uint32_t)) != hipSuccess))) {
+        dqmc_batch_destroy(b);
+        return fail(ctx, DQMC_ENOMEM, "%s", "batch plan allocation failed");
+    }
+    if (m > 0 && hipMemcpy(b->d_jobs, b->small.data(), m * sizeof(BatchJob), hipMemcpyHostToDevice) != hipSuccess) {
+        dqmc_batch_destroy(b);
+        return fail(ctx, DQMC_EDEVICE, "%s", "upload of the batch job table failed");
+    }
+    const int rc = batch_upload_order(b);
+    if (rc != DQMC_OK) {
+        dqmc_batch_destroy(b);
+        return rc;
+    }
+    *out = b;
+    return DQMC_OK;
+}
+
+int dqmc_batch_config(dqmc_batch *b, int32_t grid, int32_t order)
+{
+    if (b == nullptr || grid < 0 || order < 0 || order > 1) return DQMC_EINVAL;
+    if (hipSetDevice(b->ctx->device) != hipSuccess) return fail(b->ctx, DQMC_EDEVICE, "%s", "hipSetDevice failed");
+    if (grid > 0) b->grid = grid;
+    if (order != b->order_mode) {
+        b->order_mode = order;
+        return batch_upload_order(b);
     }
     return DQMC_OK;
+}
+
+int dqmc_batch_run(dqmc_batch *b, void *stream)
+{
+    if (b == nullptr) return DQMC_EINVAL;
+    dqmc_ctx *ctx = b->ctx;
+    ctx->err[0] = 0;
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, DQMC_EDEVICE, "%s", "hipSetDevice failed");
+    hipStream_t s = (hipStream_t)stream;
+    const uint32_t m = (uint32_t)b->small.size();
+    double bytes = 0;
+    for (const BatchJob &j : b->small) bytes += 3.0 * state_bytes(j.n);
+    int rc = run_pass(ctx, s, "batch", -1, bytes, 8, [&] {
+        return launch_batch(b->d_jobs, b->d_order, m, b->d_ticket, (uint32_t)b->grid, s);
+    });
+    if (rc != DQMC_OK) return rc;
+    for (const BatchJob &j : b->big) {
+        rc = dqmc_primes(ctx, j.n, j.tt, j.state, j.list, j.cap, j.count, stream);
+        if (rc != DQMC_OK) return rc;
+    }
+    return DQMC_OK;
+}
+
+int dqmc_primes_batch(dqmc_ctx *ctx, dqmc_job *jobs, int32_t njobs, void *stream)
+{
+    dqmc_batch *b = nullptr;
+    int rc = dqmc_batch_create(ctx, jobs, njobs, &b);
+    if (rc != DQMC_OK) return rc;
+    rc = dqmc_batch_run(b, stream);
+    if (rc == DQMC_OK && hipStreamSynchronize((hipStream_t)stream) != hipSuccess)
+        rc = fail(ctx, DQMC_EDEVICE, "%s", "batch did not complete");
+    dqmc_batch_destroy(b);
+    return rc;
 }
 
 int dqmc_set_plan(dqmc_ctx *ctx, int n, const int32_t *sizes, int ngroups)

@@ -72,6 +72,24 @@ hipError_t col_setup();
 hipError_t launch_col(int gr, int gw, int mode, const ColArgs &a, hipStream_t s);
 int col_lanes_per_block(int gw);  // l values per workgroup
 
+// One function of a batch as the batch kernel sees it (device memory).
+struct BatchJob {
+    const uint32_t *tt;
+    uint32_t *state;
+    uint64_t *list;
+    uint64_t cap;
+    uint64_t *count;
+    int32_t n;
+    int32_t pad;
+};
+
+constexpr int kBatchMaxN = 16;  // larger functions of a batch take the single-function path
+
+hipError_t batch_setup();
+// Persistent launch over njobs jobs in the given order (ticket zeroed first).
+hipError_t launch_batch(const BatchJob *jobs, const uint32_t *order, uint32_t njobs, uint32_t *ticket,
+                        uint32_t grid, hipStream_t s);
+
 hipError_t launch_fill_u64(uint64_t *p, uint64_t count, uint64_t value, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint64_t count, uint32_t value, hipStream_t s);
 hipError_t launch_to_dense(int n, const uint32_t *state, uint64_t *dense, hipStream_t s);

@@ -1,0 +1,194 @@
+// Device building blocks for LDS tiles of the T27 state (shared by the tile
+// kernels and the batch kernel).
+//
+// A tile is the set of cubes with fixed digits 13..n: 3^lw consecutive state
+// words (lw = min(n-3, 9)), i.e. digits 1..3 in each word and digits 4..3+lw
+// across words (Sec. 4.2: bottom layer in a word, top layer across words).
+#pragma once
+
+#include "t27.h"
+
+namespace dqmc {
+
+constexpr uint32_t kMaxTileWords = 19683;  // 3^9
+
+// Apply Merge (MERGE) or Reduce to the K tile digits j..j+K-1 (stride s = 3^j
+// words) of every column of the tile.
+template <int K, bool MERGE>
+__device__ __forceinline__ void lds_group(uint32_t *t, uint32_t tw, uint32_t s)
+{
+    constexpr int C = (int)pow3(K);
+    const uint32_t ncols = tw / C;
+    for (uint32_t q = threadIdx.x; q < ncols; q += blockDim.x) {
+        const uint32_t lo = q % s, hi = q / s;
+        uint32_t *col = t + lo + hi * s * C;
+        uint32_t x[C];
+        if constexpr (MERGE) {
+            static_for<C>([&](auto ci) {
+                constexpr int c = decltype(ci)::value;
+                x[c] = all_binary(c, K) ? col[c * s] : 0u;
+            });
+            reg_merge<K>(x);
+            static_for<C>([&](auto ci) {
+                constexpr int c = decltype(ci)::value;
+                if constexpr (!all_binary(c, K)) col[c * s] = x[c];
+            });
+        } else {
+            static_for<C>([&](auto ci) {
+                constexpr int c = decltype(ci)::value;
+                x[c] = col[c * s];
+            });
+            reg_reduce<K>(x);
+            static_for<C - 1>([&](auto ci) {
+                constexpr int c = decltype(ci)::value;
+                col[c * s] = x[c];
+            });
+        }
+    }
+}
+
+template <bool MERGE>
+__device__ __forceinline__ void lds_all_digits(uint32_t *t, uint32_t tw, int lw)
+{
+    uint32_t s = 1;
+    for (int j = 0; j < lw;) {
+        const int k = lw - j >= 3 ? 3 : lw - j;
+        if (k == 3) lds_group<3, MERGE>(t, tw, s);
+        else if (k == 2) lds_group<2, MERGE>(t, tw, s);
+        else lds_group<1, MERGE>(t, tw, s);
+        __syncthreads();
+        s *= (uint32_t)pow3(k);
+        j += k;
+    }
+}
+
+// Fill a tile from the truth table (Alg. 4, "Load input"): the word of every
+// group of 8 minterms (word digits all binary) gets those minterms placed at
+// their cubes and merged over digits 1..3; every other word starts at 0.
+// `bh` is the binary value of digits 13..n (the tile's high digits).
+__device__ __forceinline__ void tile_from_tt(uint32_t *t, const uint32_t *tt, int n, int lw, uint32_t tw, uint64_t bh)
+{
+    for (uint32_t w = threadIdx.x; w < tw; w += blockDim.x) t[w] = 0;
+    __syncthreads();
+    const uint32_t nb = 1u << lw;
+    const uint32_t bytemask = n >= 3 ? 0xFFu : ((1u << (1u << n)) - 1u);
+    for (uint32_t xm = threadIdx.x; xm < nb; xm += blockDim.x) {
+        const uint64_t bi = (bh << lw) + xm;  // byte index = x >> 3
+        const uint32_t byte = (tt[bi >> 2] >> ((bi & 3) * 8)) & bytemask;
+        uint32_t w = 0, p = 1;
+        for (int j = 0; j < lw; ++j, p *= 3) w += ((xm >> j) & 1u) * p;
+        t[w] = inword_merge(expand_byte(byte));
+    }
+    __syncthreads();
+}
+
+// Ordered compaction of the set bits of an LDS tile whose first word is
+// state word `wbase`: writes cube indices base + (rank) into list (entries at
+// or past cap are dropped) and returns the tile's number of set bits (every
+// thread).  `sh` holds blockDim/64 words.  n < 3 means a one-word state whose
+// bit b is cube b.
+__device__ __forceinline__ uint64_t tile_list(const uint32_t *t, uint32_t tw, int n, uint64_t wbase, uint64_t *list,
+                                              uint64_t cap, uint64_t base, uint64_t *sh)
+{
+    const uint32_t nw = blockDim.x / 64, wv = threadIdx.x / 64, lane = lane_id();
+    const uint32_t seg = (tw + nw - 1) / nw;
+    const uint32_t s0 = min(tw, wv * seg), s1 = min(tw, s0 + seg);
+    uint32_t c = 0;
+    for (uint32_t w = s0 + lane; w < s1; w += 64) c += __popc(t[w]);
+    c = wave_sum32(c);
+    __syncthreads();  // sh may still be read by the previous call
+    if (lane == 0) sh[wv] = c;
+    __syncthreads();
+    uint64_t before = 0, total = 0;
+    for (uint32_t w = 0; w < nw; ++w) {
+        before += w < wv ? sh[w] : 0;
+        total += sh[w];
+    }
+    if (list == nullptr) return total;
+    uint64_t run = base + before;
+    const bool words = n >= 3;
+    for (uint32_t r0 = s0; r0 < s1 && run < cap; r0 += 64) {
+        const uint32_t w = r0 + lane;
+        uint32_t v = w < s1 ? t[w] : 0u;
+        if (__ballot(v != 0u) == 0) continue;  // nothing to list in these 64 words
+        const uint32_t cc = __popc(v);
+        const uint32_t incl = wave_inclusive_scan32(cc);
+        uint64_t pos = run + (incl - cc);
+        const uint64_t rbase = words ? 27ull * (wbase + w) : 0ull;
+        while (v != 0u && pos < cap) {
+            const uint32_t b = __builtin_ctz(v);
+            v &= v - 1u;
+            list[pos++] = rbase + b;
+        }
+        run += __shfl(incl, 63, 64);
+    }
+    return total;
+}
+
+// Copy a tile from HBM into LDS (optionally applying the in-word Reduce),
+// with every load of a thread issued before the first LDS store.
+template <bool REDUCE, int THREADS>
+__device__ __forceinline__ void load_tile(uint32_t *t, const uint32_t *src, uint32_t tw)
+{
+    constexpr int U = (kMaxTileWords + THREADS - 1) / THREADS;
+    uint32_t v[U];
+    // (src + u * THREADS) is uniform: one scalar base per step, one lane offset
+    static_for<U>([&](auto ui) {
+        constexpr int u = decltype(ui)::value;
+        const uint32_t *su = src + u * THREADS;
+        v[u] = threadIdx.x + u * THREADS < tw ? __builtin_nontemporal_load(su + threadIdx.x) : 0u;
+    });
+    static_for<U>([&](auto ui) {
+        constexpr int u = decltype(ui)::value;
+        if (threadIdx.x + u * THREADS < tw) t[threadIdx.x + u * THREADS] = REDUCE ? inword_reduce(v[u]) : v[u];
+    });
+}
+
+template <int THREADS>
+__device__ __forceinline__ void store_tile(uint32_t *dst, const uint32_t *t, uint32_t tw)
+{
+    constexpr int U = (kMaxTileWords + THREADS - 1) / THREADS;
+    uint32_t v[U];
+    static_for<U>([&](auto ui) {
+        constexpr int u = decltype(ui)::value;
+        v[u] = threadIdx.x + u * THREADS < tw ? t[threadIdx.x + u * THREADS] : 0u;
+    });
+    static_for<U>([&](auto ui) {
+        constexpr int u = decltype(ui)::value;
+        uint32_t *du = dst + u * THREADS;
+        if (threadIdx.x + u * THREADS < tw) __builtin_nontemporal_store(v[u], du + threadIdx.x);
+    });
+}
+
+// Last Reduce round of a full tile (digits 10..12, stride 729 words): thread q
+// owns column q, reduces it, and writes it to HBM (the prime bitmap);
+// consecutive threads write consecutive words.  It also builds the tile
+// summary in `red` (zeroed before): red[0] = set bits, red[1..] = map of the
+// non-zero 64-word chunks.
+__device__ __forceinline__ void last_round_to_hbm(uint32_t *t, uint32_t *dst, uint32_t *red)
+{
+    constexpr uint32_t S = 729;
+    const uint32_t q = threadIdx.x;
+    uint32_t c = 0;
+    if (q < S) {
+        uint32_t x[27];
+        static_for<27>([&](auto ci) {
+            constexpr int k = decltype(ci)::value;
+            x[k] = t[q + k * S];
+        });
+        reg_reduce<3>(x);
+        static_for<27>([&](auto ci) {
+            constexpr int k = decltype(ci)::value;
+            __builtin_nontemporal_store(x[k], dst + q + k * S);
+            c += __popc(x[k]);
+            if (x[k] != 0u) {
+                const uint32_t chunk = (q + k * S) / kChunkWords;
+                atomicOr(&red[1 + chunk / 32], 1u << (chunk % 32));
+            }
+        });
+    }
+    c = wave_sum32(c);
+    if (lane_id() == 0 && c != 0) atomicAdd(&red[0], c);
+}
+
+}  // namespace dqmc

@@ -84,6 +84,10 @@ def load():
             "dqmc_bitmap_to_dense": (i32, [vp, i32, vp, vp, vp]),
             "dqmc_primes_batch": (i32, [vp, ctypes.POINTER(dqmc_job), ctypes.c_int32, vp]),
             "dqmc_profile": (i32, [vp, i32]),
+            "dqmc_batch_create": (i32, [vp, ctypes.POINTER(dqmc_job), ctypes.c_int32, ctypes.POINTER(vp)]),
+            "dqmc_batch_config": (i32, [vp, ctypes.c_int32, ctypes.c_int32]),
+            "dqmc_batch_run": (i32, [vp, vp]),
+            "dqmc_batch_destroy": (None, [vp]),
             "dqmc_set_plan": (i32, [vp, i32, ctypes.POINTER(ctypes.c_int32), i32]),
             "dqmc_get_plan": (i32, [vp, i32, ctypes.POINTER(ctypes.c_int32), i32]),
             "dqmc_profile_read": (i32, [vp, ctypes.POINTER(dqmc_pass_record), i32]),
@@ -213,9 +217,7 @@ def dqmc_bitmap_to_dense(ctx, n, state, dense, stream=None) -> None:
         _ptr(dense, "dense", torch.int64, dqmc_dense_words(n)), _stream(stream)))
 
 
-def dqmc_primes_batch(ctx, jobs, stream=None) -> list:
-    """``jobs``: list of dicts with keys n, tt, state, list (or None),
-    list_cap, count (device tensors).  Returns the per-job status codes."""
+def _job_array(jobs):
     import torch
 
     arr = (dqmc_job * max(1, len(jobs)))()
@@ -226,13 +228,52 @@ def dqmc_primes_batch(ctx, jobs, stream=None) -> list:
         cap = 0 if lst is None else int(j.get("list_cap", lst.numel()))
         arr[i].n = n
         arr[i].status = 0
-        arr[i].tt = _ptr(j["tt"], "tt", torch.int32, dqmc_tt_words(nn)) if j["tt"] is not None else None
-        arr[i].state = _ptr(j["state"], "state", torch.int32, dqmc_state_words(nn)) if j["state"] is not None else None
+        arr[i].tt = _ptr(j["tt"], "tt", torch.int32, dqmc_tt_words(nn)) if j.get("tt") is not None else None
+        arr[i].state = _ptr(j["state"], "state", torch.int32, dqmc_state_words(nn)) if j.get("state") is not None else None
         arr[i].list = _ptr(lst, "list", torch.int64, cap)
         arr[i].list_cap = cap
-        arr[i].count = _ptr(j["count"], "count", torch.int64, 1) if j["count"] is not None else None
+        arr[i].count = _ptr(j["count"], "count", torch.int64, 1) if j.get("count") is not None else None
+    return arr
+
+
+def dqmc_primes_batch(ctx, jobs, stream=None) -> list:
+    """``jobs``: list of dicts with keys n, tt, state, list (or None),
+    list_cap, count (device tensors).  Waits for completion; returns the
+    per-job status codes."""
+    arr = _job_array(jobs)
     _check(ctx, load().dqmc_primes_batch(ctx, arr, len(jobs), _stream(stream)))
     return [int(arr[i].status) for i in range(len(jobs))]
+
+
+class Batch:
+    """A batch plan (dqmc_batch_create / config / run / destroy).  The job
+    tensors must stay alive while the plan is used."""
+
+    def __init__(self, ctx, jobs):
+        self.ctx = ctx
+        self._jobs = jobs  # keep the tensors alive
+        arr = _job_array(jobs)
+        out = ctypes.c_void_p()
+        _check(ctx, load().dqmc_batch_create(ctx, arr, len(jobs), ctypes.byref(out)))
+        self.plan = out
+        self.status = [int(arr[i].status) for i in range(len(jobs))]
+
+    def config(self, grid: int = 0, order: int = 0):
+        _check(self.ctx, load().dqmc_batch_config(self.plan, grid, order))
+
+    def run(self, stream=None):
+        _check(self.ctx, load().dqmc_batch_run(self.plan, _stream(stream)))
+
+    def close(self):
+        if self.plan is not None:
+            load().dqmc_batch_destroy(self.plan)
+            self.plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def dqmc_set_plan(ctx, n: int, sizes) -> None:
