@@ -79,6 +79,65 @@ def cpu_baseline(n, tt, seconds, threads):
     return done / elapsed, used, elapsed, np.concatenate(rhos_all), np.concatenate(res_all)
 
 
+def bench_batch(ctx, reps=5):
+    """Batched workload (8192 functions, n uniform 6..16): one graph-replayed
+    persistent launch against one dqmc_primes launch sequence per function."""
+    import torch
+
+    from paper_2302_10083_amd import dqmc, inputs
+
+    specs = inputs.batch_specs(8192, seed=8192)
+    dev = ctx.torch_device
+    jobs = []
+    for s in specs:
+        n = s["n"]
+        jobs.append(dict(n=n, tt=ctx.tt_to_device(inputs.make(s)), state=ctx.new_state(n), list=None, list_cap=0,
+                         count=torch.zeros(1, dtype=torch.int64, device=dev)))
+    dqmc.dqmc_primes_batch(ctx.ctx, jobs)  # count-only pass sizes the lists
+    for j in jobs:
+        c = int(j["count"].item())
+        j["list"] = torch.empty(max(c, 1), dtype=torch.int64, device=dev)
+        j["list_cap"] = c
+    plan = dqmc.Batch(ctx.ctx, jobs)
+    plan.run()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    st = torch.cuda.Stream()
+    st.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(st):
+        with torch.cuda.graph(g, stream=st):
+            plan.run()
+    torch.cuda.current_stream().wait_stream(st)
+    g.replay()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        g.replay()
+    b.record()
+    torch.cuda.synchronize()
+    ms_batch = a.elapsed_time(b) / reps
+    # one launch sequence per function, same buffers
+    for _ in range(2):
+        for j in jobs:
+            dqmc.dqmc_primes(ctx.ctx, j["n"], j["tt"], j["state"], j["list"], j["list_cap"], j["count"])
+    torch.cuda.synchronize()
+    a.record()
+    for j in jobs:
+        dqmc.dqmc_primes(ctx.ctx, j["n"], j["tt"], j["state"], j["list"], j["list_cap"], j["count"])
+    b.record()
+    torch.cuda.synchronize()
+    ms_single = a.elapsed_time(b)
+    state_bytes = sum(4 * 3 ** max(s["n"] - 3, 0) for s in specs)
+    del g
+    plan.close()
+    return {"workload": "8192 functions, n uniform 6..16, half Bernoulli half DNF (seed 8192)",
+            "fns": len(specs), "state_GB": state_bytes / 1e9,
+            "ms": ms_batch, "fns_per_s": len(specs) / (ms_batch / 1e3),
+            "per_fn_launch_ms": ms_single, "per_fn_launch_fns_per_s": len(specs) / (ms_single / 1e3),
+            "speedup_vs_per_fn_launch": ms_single / ms_batch, "graph_captured": True}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -88,6 +147,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--cpu-threads", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -196,6 +256,13 @@ def main():
                                "sample": "%d uniformly random cubes of the same n=%d function, per-cube "
                                          "prime test (Sec. 2 definitions), %.1f s" % (len(rhos), n, el)}
         out["sample_parity"] = {"cubes": int(len(rhos)), "primes_in_sample": int(ref.sum()), "mismatches": mism}
+    if not args.no_batch:
+        del lst, state
+        torch.cuda.empty_cache()
+        out["batch"] = bench_batch(ctx)
+        print("bench: batch %.2f ms (%.0f fns/s), per-function launches %.2f ms" % (
+            out["batch"]["ms"], out["batch"]["fns_per_s"], out["batch"]["per_fn_launch_ms"]), file=sys.stderr, flush=True)
+
     print(json.dumps(out), flush=True)
     ctx.close()
 

@@ -156,6 +156,60 @@ void dqmc_batch_destroy(dqmc_batch *plan);
 int dqmc_primes_batch(dqmc_ctx *ctx, dqmc_job *jobs, int32_t njobs, void *stream);
 
 /* ---------------------------------------------------------------------------
+ * Serving: a request loop over one device.
+ *
+ * Jobs (one truth table each, copied from host memory at submission) are
+ * admitted while the device-memory budget and the execution slots allow it:
+ * a job's footprint is its state (dqmc_state_words(n) words), its truth
+ * table, its count and a list reserve of min(3^n, max(2^18, 3^(n-3)/16))
+ * entries.  Jobs with n <= 16 that are admitted together run as one batch
+ * launch; larger jobs run on their own stream and context.  Jobs that arrive
+ * while others run are admitted as memory and slots free up (continuous
+ * batching), and their work overlaps on the device.  Results stay on the
+ * device until released; the result of a job is exactly what dqmc_primes
+ * gives for it alone (the list holds min(count, reserve) smallest primes).
+ *
+ *   dqmc_server_create: budget in bytes of device memory for resident jobs
+ *     (0 = 90% of the device memory free at creation), slots = number of
+ *     concurrent large jobs (streams).  Starts the scheduler thread.
+ *   dqmc_server_submit: copies the table; *id receives the job id.
+ *     DQMC_EINVAL for bad n / NULL, DQMC_ENOMEM if the footprint exceeds the
+ *     whole budget.  Never waits for the device.
+ *   dqmc_server_poll: 1 if the job finished (*out filled), 0 if not yet,
+ *     negative on error (unknown id).  dqmc_server_wait blocks until done;
+ *     it returns DQMC_ENOMEM instead if the job cannot be admitted while
+ *     nothing runs (the budget is held by results not yet released).
+ *   dqmc_server_release: frees a finished job's device memory.
+ *   dqmc_server_read: copies a finished job's list (up to cap entries) into
+ *     host memory and returns the number copied (negative on error).
+ *   dqmc_server_destroy: waits for running jobs, frees everything.
+ * Times are seconds on one monotonic host clock. */
+typedef struct dqmc_server dqmc_server;
+
+typedef struct {
+    int32_t n;
+    int32_t status;           /* DQMC_OK, or the error of the job's launch */
+    uint64_t count;           /* number of primes */
+    uint64_t listed;          /* entries in list: min(count, reserve) */
+    const uint32_t *state;    /* device: prime bitmap (T27 layout) */
+    const uint64_t *list;     /* device: the smallest `listed` primes, increasing */
+    double t_submit, t_admit, t_done;
+} dqmc_result;
+
+int dqmc_server_create(int device, uint64_t budget_bytes, int32_t slots, dqmc_server **out);
+int dqmc_server_submit(dqmc_server *srv, int32_t n, const uint32_t *h_tt, uint64_t *id);
+int dqmc_server_poll(dqmc_server *srv, uint64_t id, dqmc_result *out);
+int dqmc_server_wait(dqmc_server *srv, uint64_t id, dqmc_result *out);
+int dqmc_server_release(dqmc_server *srv, uint64_t id);
+int64_t dqmc_server_read(dqmc_server *srv, uint64_t id, uint64_t *h_list, uint64_t cap);
+void dqmc_server_destroy(dqmc_server *srv);
+
+/* Order-dependent 64-bit hash of nwords uint32 device words (diagnostics:
+ * comparing device-resident bitmaps without copying them), written to
+ * *d_out (device). */
+int dqmc_hash_words(dqmc_ctx *ctx, const uint32_t *d_words, uint64_t nwords, uint64_t *d_out, void *stream);
+
+/* ---------------------------------------------------------------------------
  * Tuning: the pass plan.
  *
  * For n > 12 the digits 13..n are processed by column passes over groups of

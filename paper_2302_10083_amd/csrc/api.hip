@@ -491,6 +491,15 @@ int dqmc_primes_batch(dqmc_ctx *ctx, dqmc_job *jobs, int32_t njobs, void *stream
     return rc;
 }
 
+int dqmc_hash_words(dqmc_ctx *ctx, const uint32_t *d_words, uint64_t nwords, uint64_t *d_out, void *stream)
+{
+    if (ctx == nullptr || d_out == nullptr || (d_words == nullptr && nwords > 0)) return DQMC_EINVAL;
+    ctx->err[0] = 0;
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, DQMC_EDEVICE, "%s", "hipSetDevice failed");
+    DQMC_HIP(ctx, launch_hash(d_words, nwords, d_out, (hipStream_t)stream));
+    return DQMC_OK;
+}
+
 int dqmc_set_plan(dqmc_ctx *ctx, int n, const int32_t *sizes, int ngroups)
 {
     if (ctx == nullptr) return DQMC_EINVAL;

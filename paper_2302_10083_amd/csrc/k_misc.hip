@@ -74,4 +74,33 @@ hipError_t launch_to_dense(int n, const uint32_t *state, uint64_t *dense, hipStr
     return hipGetLastError();
 }
 
+// Order-dependent hash: sum over i of a 64-bit mix of (i, word i), mod 2^64.
+__device__ __forceinline__ uint64_t mix64(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+__global__ void hash_kernel(const uint32_t *w, uint64_t n, unsigned long long *out)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    uint64_t acc = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        acc += mix64((i << 32) ^ (i >> 32) ^ ((uint64_t)w[i] * 0x9E3779B97F4A7C15ULL));
+    acc = wave_sum(acc);
+    if (lane_id() == 0) atomicAdd(out, (unsigned long long)acc);
+}
+
+hipError_t launch_hash(const uint32_t *w, uint64_t n, uint64_t *out, hipStream_t s)
+{
+    hipError_t e = launch_fill_u64(out, 1, 0, s);
+    if (e != hipSuccess) return e;
+    uint64_t g = (n + 255) / 256;
+    if (g > 8192) g = 8192;
+    hipLaunchKernelGGL(hash_kernel, dim3((uint32_t)(g == 0 ? 1 : g)), dim3(256), 0, s, w, n,
+                       (unsigned long long *)out);
+    return hipGetLastError();
+}
+
 }  // namespace dqmc

@@ -93,5 +93,6 @@ hipError_t launch_batch(const BatchJob *jobs, const uint32_t *order, uint32_t nj
 hipError_t launch_fill_u64(uint64_t *p, uint64_t count, uint64_t value, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint64_t count, uint32_t value, hipStream_t s);
 hipError_t launch_to_dense(int n, const uint32_t *state, uint64_t *dense, hipStream_t s);
+hipError_t launch_hash(const uint32_t *w, uint64_t n, uint64_t *out, hipStream_t s);
 
 }  // namespace dqmc

@@ -1,0 +1,459 @@
+// Serving: a request loop over one device (declared in include/dqmc.h).
+//
+// One scheduler thread owns every HIP call of the server.  Each round it
+//   1. retires finished work (an event per launch), publishing results;
+//   2. admits queued jobs first-fit in arrival order while their footprint
+//      fits the free budget (a job that has waited longer than kAgingSeconds
+//      at the head of the queue stops others from overtaking it);
+//   3. launches: all admitted jobs with n <= kBatchMaxN go into one batch
+//      launch on a free batch slot, each larger job gets a free slot (stream
+//      + context) of its own.
+// Device memory is stream-ordered (hipMallocAsync on the launch stream, freed
+// on an idle release stream once the job is released), so jobs that arrive
+// while others run start as soon as memory and a slot are free and their
+// kernels overlap with the running ones.
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "dqmc.h"
+#include "launch.h"
+#include "t27.h"
+
+using namespace dqmc;
+
+namespace {
+
+constexpr double kAgingSeconds = 0.05;
+constexpr uint32_t kBatchSlotJobs = 2048;  // jobs per batch launch
+
+double now_s()
+{
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+uint64_t list_reserve(int n)
+{
+    const uint64_t all = pow3(n);
+    uint64_t r = pow3(n > 3 ? n - 3 : 0) / 16;
+    if (r < (1ull << 18)) r = 1ull << 18;
+    return r < all ? r : all;
+}
+
+uint64_t tt_words_of(int n) { return n <= 5 ? 1 : (1ull << (n - 5)); }
+
+uint64_t footprint(int n)
+{
+    return 4 * pow3(n > 3 ? n - 3 : 0) + 4 * tt_words_of(n) + 8 * list_reserve(n) + 64;
+}
+
+enum Phase { kPending, kRunning, kDone, kReleased };
+
+struct SJob {
+    uint64_t id = 0;
+    int n = 0;
+    Phase phase = kPending;
+    int status = DQMC_OK;
+    uint32_t *h_tt = nullptr;    // pinned copy of the truth table
+    uint64_t *h_count = nullptr; // pinned landing slot for the count
+    uint32_t *d_tt = nullptr;
+    uint32_t *d_state = nullptr;
+    uint64_t *d_list = nullptr;
+    uint64_t *d_count = nullptr;
+    uint64_t cap = 0;
+    uint64_t count = 0;
+    uint64_t fp = 0;
+    double t_submit = 0, t_admit = 0, t_done = 0;
+};
+
+struct Slot {
+    hipStream_t stream = nullptr;
+    dqmc_ctx *ctx = nullptr;
+    hipEvent_t ev = nullptr;
+    bool busy = false;
+    std::vector<uint64_t> jobs;
+    // batch slots: job table staging
+    BatchJob *h_jobs = nullptr;
+    uint32_t *h_order = nullptr;
+    BatchJob *d_jobs = nullptr;
+    uint32_t *d_order = nullptr;
+    uint32_t *d_ticket = nullptr;
+};
+
+}  // namespace
+
+struct dqmc_server {
+    int device = 0;
+    uint64_t budget = 0, used = 0;
+    std::vector<Slot> big, small;
+    hipStream_t release_stream = nullptr;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::map<uint64_t, SJob> jobs;
+    std::deque<uint64_t> queue;
+    uint64_t next_id = 1;
+    bool stop = false;
+    bool stalled = false;  // queued work that cannot be admitted while nothing runs
+    double head_since = 0;
+    uint64_t head_id = 0;
+    std::thread thr;
+    char err[256] = {0};
+};
+
+namespace {
+
+void free_job_device(dqmc_server *s, SJob &j)
+{
+    if (j.d_tt) (void)hipFreeAsync(j.d_tt, s->release_stream);
+    if (j.d_state) (void)hipFreeAsync(j.d_state, s->release_stream);
+    if (j.d_list) (void)hipFreeAsync(j.d_list, s->release_stream);
+    if (j.d_count) (void)hipFreeAsync(j.d_count, s->release_stream);
+    (void)hipStreamSynchronize(s->release_stream);
+    j.d_tt = nullptr;
+    j.d_state = nullptr;
+    j.d_list = nullptr;
+    j.d_count = nullptr;
+}
+
+// Allocate a job's buffers and enqueue its table upload on `st`.
+bool stage_job(SJob &j, hipStream_t st)
+{
+    const uint64_t nw = tt_words_of(j.n), sw = pow3(j.n > 3 ? j.n - 3 : 0);
+    j.cap = list_reserve(j.n);
+    if (hipMallocAsync((void **)&j.d_tt, nw * 4, st) != hipSuccess) return false;
+    if (hipMallocAsync((void **)&j.d_state, sw * 4, st) != hipSuccess) return false;
+    if (hipMallocAsync((void **)&j.d_list, j.cap * 8, st) != hipSuccess) return false;
+    if (hipMallocAsync((void **)&j.d_count, 8, st) != hipSuccess) return false;
+    return hipMemcpyAsync(j.d_tt, j.h_tt, nw * 4, hipMemcpyHostToDevice, st) == hipSuccess;
+}
+
+void launch_big(dqmc_server *s, Slot &sl, SJob &j)
+{
+    sl.busy = true;
+    sl.jobs.assign(1, j.id);
+    bool ok = stage_job(j, sl.stream);
+    if (ok)
+        ok = dqmc_primes(sl.ctx, j.n, j.d_tt, j.d_state, j.d_list, j.cap, j.d_count, sl.stream) == DQMC_OK;
+    if (ok) ok = hipMemcpyAsync(j.h_count, j.d_count, 8, hipMemcpyDeviceToHost, sl.stream) == hipSuccess;
+    if (!ok) j.status = DQMC_EDEVICE;
+    (void)hipEventRecord(sl.ev, sl.stream);
+}
+
+void launch_small(dqmc_server *s, Slot &sl, const std::vector<uint64_t> &ids)
+{
+    sl.busy = true;
+    sl.jobs = ids;
+    uint32_t m = 0;
+    for (uint64_t id : ids) {
+        SJob &j = s->jobs[id];
+        if (!stage_job(j, sl.stream)) {
+            j.status = DQMC_EDEVICE;
+            continue;
+        }
+        sl.h_jobs[m] = BatchJob{j.d_tt, j.d_state, j.d_list, j.cap, j.d_count, j.n, 0};
+        sl.h_order[m] = m;
+        ++m;
+    }
+    // largest first
+    std::stable_sort(sl.h_order, sl.h_order + m,
+                     [&](uint32_t a, uint32_t b) { return sl.h_jobs[a].n > sl.h_jobs[b].n; });
+    bool ok = hipMemcpyAsync(sl.d_jobs, sl.h_jobs, m * sizeof(BatchJob), hipMemcpyHostToDevice, sl.stream) ==
+                  hipSuccess &&
+              hipMemcpyAsync(sl.d_order, sl.h_order, m * sizeof(uint32_t), hipMemcpyHostToDevice, sl.stream) ==
+                  hipSuccess;
+    int ncu = 256;
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, s->device);
+    uint32_t grid = m < (uint32_t)(2 * ncu) ? m : (uint32_t)(2 * ncu);
+    if (ok) ok = launch_batch(sl.d_jobs, sl.d_order, m, sl.d_ticket, grid == 0 ? 1 : grid, sl.stream) == hipSuccess;
+    for (uint64_t id : ids) {
+        SJob &j = s->jobs[id];
+        if (!ok) j.status = DQMC_EDEVICE;
+        if (j.status == DQMC_OK)
+            (void)hipMemcpyAsync(j.h_count, j.d_count, 8, hipMemcpyDeviceToHost, sl.stream);
+    }
+    (void)hipEventRecord(sl.ev, sl.stream);
+}
+
+void retire(dqmc_server *s, Slot &sl)
+{
+    const double t = now_s();
+    for (uint64_t id : sl.jobs) {
+        SJob &j = s->jobs[id];
+        j.count = *j.h_count;
+        j.t_done = t;
+        j.phase = kDone;
+    }
+    sl.jobs.clear();
+    sl.busy = false;
+}
+
+void scheduler(dqmc_server *s)
+{
+    (void)hipSetDevice(s->device);
+    std::unique_lock<std::mutex> lk(s->mu);
+    while (true) {
+        bool any_running = false, retired = false;
+        for (auto *pool : {&s->big, &s->small})
+            for (Slot &sl : *pool) {
+                if (!sl.busy) continue;
+                if (hipEventQuery(sl.ev) == hipSuccess) {
+                    retire(s, sl);
+                    retired = true;
+                } else {
+                    any_running = true;
+                }
+            }
+        if (retired) s->cv_done.notify_all();
+        if (s->stop && s->queue.empty() && !any_running) break;
+        // admission, first fit in arrival order (with aging of the head)
+        std::vector<uint64_t> small_ids;
+        Slot *free_small = nullptr;
+        for (Slot &sl : s->small)
+            if (!sl.busy) {
+                free_small = &sl;
+                break;
+            }
+        if (!s->queue.empty()) {
+            if (s->queue.front() != s->head_id) {
+                s->head_id = s->queue.front();
+                s->head_since = now_s();
+            }
+        }
+        for (auto it = s->queue.begin(); it != s->queue.end();) {
+            SJob &j = s->jobs[*it];
+            const bool is_head = it == s->queue.begin();
+            const bool fits = s->used + j.fp <= s->budget;
+            Slot *slot = nullptr;
+            if (j.n <= kBatchMaxN) {
+                if (free_small && small_ids.size() < kBatchSlotJobs && fits) slot = free_small;
+            } else if (fits) {
+                for (Slot &sl : s->big)
+                    if (!sl.busy) {
+                        slot = &sl;
+                        break;
+                    }
+            }
+            if (slot == nullptr) {
+                if (is_head && now_s() - s->head_since > kAgingSeconds) break;  // let the head go first
+                ++it;
+                continue;
+            }
+            s->used += j.fp;
+            j.phase = kRunning;
+            j.t_admit = now_s();
+            if (j.n <= kBatchMaxN) {
+                small_ids.push_back(j.id);
+            } else {
+                launch_big(s, *slot, j);
+                any_running = true;
+            }
+            it = s->queue.erase(it);
+        }
+        if (!small_ids.empty()) {
+            launch_small(s, *free_small, small_ids);
+            any_running = true;
+        }
+        // nothing runs and the queue cannot move: only released results can
+        // free memory, so waiters are told instead of blocking forever
+        const bool stalled = !any_running && !s->queue.empty();
+        if (stalled != s->stalled) {
+            s->stalled = stalled;
+            if (stalled) s->cv_done.notify_all();
+        }
+        if (any_running)
+            s->cv_work.wait_for(lk, std::chrono::microseconds(20));
+        else
+            s->cv_work.wait_for(lk, std::chrono::milliseconds(5));
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int dqmc_server_create(int device, uint64_t budget_bytes, int32_t slots, dqmc_server **out)
+{
+    if (out == nullptr || slots < 0) return DQMC_EINVAL;
+    *out = nullptr;
+    if (hipSetDevice(device) != hipSuccess) return DQMC_EDEVICE;
+    dqmc_server *s = new dqmc_server();
+    s->device = device;
+    if (slots == 0) slots = 4;
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+        delete s;
+        return DQMC_EDEVICE;
+    }
+    // keep the freed blocks of the stream-ordered pool for reuse
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess) {
+        uint64_t thr = UINT64_MAX;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+    }
+    bool ok = hipStreamCreateWithFlags(&s->release_stream, hipStreamNonBlocking) == hipSuccess;
+    s->big.resize(slots);
+    s->small.resize(2);
+    for (auto *p : {&s->big, &s->small})
+        for (Slot &sl : *p) {
+            ok = ok && hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) == hipSuccess;
+            ok = ok && hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming) == hipSuccess;
+            ok = ok && dqmc_create(device, &sl.ctx) == DQMC_OK;
+        }
+    for (Slot &sl : s->small) {
+        ok = ok && hipHostMalloc((void **)&sl.h_jobs, kBatchSlotJobs * sizeof(BatchJob), 0) == hipSuccess;
+        ok = ok && hipHostMalloc((void **)&sl.h_order, kBatchSlotJobs * sizeof(uint32_t), 0) == hipSuccess;
+        ok = ok && hipMalloc((void **)&sl.d_jobs, kBatchSlotJobs * sizeof(BatchJob)) == hipSuccess;
+        ok = ok && hipMalloc((void **)&sl.d_order, kBatchSlotJobs * sizeof(uint32_t)) == hipSuccess;
+        ok = ok && hipMalloc((void **)&sl.d_ticket, 256) == hipSuccess;
+    }
+    if (!ok) {
+        dqmc_server_destroy(s);
+        return DQMC_ENOMEM;
+    }
+    if (hipMemGetInfo(&fr, &tot) == hipSuccess && budget_bytes == 0) budget_bytes = (uint64_t)(0.9 * (double)fr);
+    s->budget = budget_bytes;
+    s->thr = std::thread(scheduler, s);
+    *out = s;
+    return DQMC_OK;
+}
+
+int dqmc_server_submit(dqmc_server *s, int32_t n, const uint32_t *h_tt, uint64_t *id)
+{
+    if (s == nullptr || h_tt == nullptr || id == nullptr || n < 0 || n > DQMC_MAX_N) return DQMC_EINVAL;
+    const uint64_t fp = footprint(n);
+    if (fp > s->budget) return DQMC_ENOMEM;
+    const uint64_t nw = tt_words_of(n);
+    SJob j;
+    j.n = n;
+    j.fp = fp;
+    if (hipHostMalloc((void **)&j.h_tt, nw * 4, 0) != hipSuccess ||
+        hipHostMalloc((void **)&j.h_count, 8, 0) != hipSuccess) {
+        if (j.h_tt) (void)hipHostFree(j.h_tt);
+        return DQMC_ENOMEM;
+    }
+    memcpy(j.h_tt, h_tt, nw * 4);
+    *j.h_count = 0;
+    j.t_submit = now_s();
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        j.id = s->next_id++;
+        *id = j.id;
+        s->jobs.emplace(j.id, j);
+        s->queue.push_back(j.id);
+    }
+    s->cv_work.notify_one();
+    return DQMC_OK;
+}
+
+static void fill_result(const SJob &j, dqmc_result *out)
+{
+    out->n = j.n;
+    out->status = j.status;
+    out->count = j.count;
+    out->listed = j.count < j.cap ? j.count : j.cap;
+    out->state = j.d_state;
+    out->list = j.d_list;
+    out->t_submit = j.t_submit;
+    out->t_admit = j.t_admit;
+    out->t_done = j.t_done;
+}
+
+int dqmc_server_poll(dqmc_server *s, uint64_t id, dqmc_result *out)
+{
+    if (s == nullptr) return DQMC_EINVAL;
+    std::lock_guard<std::mutex> g(s->mu);
+    auto it = s->jobs.find(id);
+    if (it == s->jobs.end() || it->second.phase == kReleased) return DQMC_EINVAL;
+    if (it->second.phase != kDone) return 0;
+    if (out) fill_result(it->second, out);
+    return 1;
+}
+
+int dqmc_server_wait(dqmc_server *s, uint64_t id, dqmc_result *out)
+{
+    if (s == nullptr) return DQMC_EINVAL;
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->jobs.find(id);
+    if (it == s->jobs.end() || it->second.phase == kReleased) return DQMC_EINVAL;
+    s->cv_done.wait(lk, [&] { return it->second.phase == kDone || (s->stalled && it->second.phase == kPending); });
+    if (it->second.phase != kDone) {
+        snprintf(s->err, sizeof(s->err), "job %llu cannot be admitted until results are released",
+                 (unsigned long long)id);
+        return DQMC_ENOMEM;
+    }
+    if (out) fill_result(it->second, out);
+    return DQMC_OK;
+}
+
+int64_t dqmc_server_read(dqmc_server *s, uint64_t id, uint64_t *h_list, uint64_t cap)
+{
+    if (s == nullptr || (h_list == nullptr && cap > 0)) return DQMC_EINVAL;
+    std::lock_guard<std::mutex> g(s->mu);
+    auto it = s->jobs.find(id);
+    if (it == s->jobs.end() || it->second.phase != kDone) return DQMC_EINVAL;
+    const SJob &j = it->second;
+    uint64_t k = j.count < j.cap ? j.count : j.cap;
+    if (k > cap) k = cap;
+    if (k > 0 && hipMemcpy(h_list, j.d_list, k * 8, hipMemcpyDeviceToHost) != hipSuccess) return DQMC_EDEVICE;
+    return (int64_t)k;
+}
+
+int dqmc_server_release(dqmc_server *s, uint64_t id)
+{
+    if (s == nullptr) return DQMC_EINVAL;
+    std::lock_guard<std::mutex> g(s->mu);
+    auto it = s->jobs.find(id);
+    if (it == s->jobs.end() || it->second.phase != kDone) return DQMC_EINVAL;
+    SJob &j = it->second;
+    free_job_device(s, j);
+    if (j.h_tt) (void)hipHostFree(j.h_tt);
+    if (j.h_count) (void)hipHostFree(j.h_count);
+    s->used -= j.fp;
+    s->jobs.erase(it);
+    s->stalled = false;
+    s->cv_work.notify_one();
+    return DQMC_OK;
+}
+
+void dqmc_server_destroy(dqmc_server *s)
+{
+    if (s == nullptr) return;
+    if (s->thr.joinable()) {
+        {
+            std::lock_guard<std::mutex> g(s->mu);
+            s->stop = true;
+        }
+        s->cv_work.notify_one();
+        s->thr.join();
+    }
+    (void)hipSetDevice(s->device);
+    for (auto &kv : s->jobs) {
+        free_job_device(s, kv.second);
+        if (kv.second.h_tt) (void)hipHostFree(kv.second.h_tt);
+        if (kv.second.h_count) (void)hipHostFree(kv.second.h_count);
+    }
+    for (auto *p : {&s->big, &s->small})
+        for (Slot &sl : *p) {
+            if (sl.stream) (void)hipStreamSynchronize(sl.stream);
+            if (sl.ctx) dqmc_destroy(sl.ctx);
+            if (sl.ev) (void)hipEventDestroy(sl.ev);
+            if (sl.stream) (void)hipStreamDestroy(sl.stream);
+            if (sl.h_jobs) (void)hipHostFree(sl.h_jobs);
+            if (sl.h_order) (void)hipHostFree(sl.h_order);
+            if (sl.d_jobs) (void)hipFree(sl.d_jobs);
+            if (sl.d_order) (void)hipFree(sl.d_order);
+            if (sl.d_ticket) (void)hipFree(sl.d_ticket);
+        }
+    if (s->release_stream) (void)hipStreamDestroy(s->release_stream);
+    delete s;
+}
+
+}  // extern "C"

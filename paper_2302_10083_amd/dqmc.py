@@ -46,6 +46,20 @@ class dqmc_pass_record(ctypes.Structure):
 DQMC_MAX_RECORDS = 64
 
 
+class dqmc_result(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int32),
+        ("status", ctypes.c_int32),
+        ("count", ctypes.c_uint64),
+        ("listed", ctypes.c_uint64),
+        ("state", ctypes.c_void_p),
+        ("list", ctypes.c_void_p),
+        ("t_submit", ctypes.c_double),
+        ("t_admit", ctypes.c_double),
+        ("t_done", ctypes.c_double),
+    ]
+
+
 class dqmc_job(ctypes.Structure):
     _fields_ = [
         ("n", ctypes.c_int32),
@@ -89,6 +103,14 @@ def load():
             "dqmc_batch_run": (i32, [vp, vp]),
             "dqmc_batch_destroy": (None, [vp]),
             "dqmc_set_plan": (i32, [vp, i32, ctypes.POINTER(ctypes.c_int32), i32]),
+            "dqmc_hash_words": (i32, [vp, vp, u64, vp, vp]),
+            "dqmc_server_create": (i32, [i32, u64, ctypes.c_int32, ctypes.POINTER(vp)]),
+            "dqmc_server_submit": (i32, [vp, ctypes.c_int32, vp, ctypes.POINTER(ctypes.c_uint64)]),
+            "dqmc_server_poll": (i32, [vp, ctypes.c_uint64, ctypes.POINTER(dqmc_result)]),
+            "dqmc_server_wait": (i32, [vp, ctypes.c_uint64, ctypes.POINTER(dqmc_result)]),
+            "dqmc_server_release": (i32, [vp, ctypes.c_uint64]),
+            "dqmc_server_read": (ctypes.c_int64, [vp, ctypes.c_uint64, vp, ctypes.c_uint64]),
+            "dqmc_server_destroy": (None, [vp]),
             "dqmc_get_plan": (i32, [vp, i32, ctypes.POINTER(ctypes.c_int32), i32]),
             "dqmc_profile_read": (i32, [vp, ctypes.POINTER(dqmc_pass_record), i32]),
         }
@@ -274,6 +296,87 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def dqmc_hash_words(ctx, words, nwords: int, out, stream=None) -> None:
+    """Order-dependent hash of nwords device words (a tensor or a raw device
+    address) into the int64 device tensor `out`."""
+    import torch
+
+    addr = ctypes.c_void_p(words.data_ptr() if isinstance(words, torch.Tensor) else int(words))
+    _check(ctx, load().dqmc_hash_words(ctx, addr, int(nwords), _ptr(out, "out", torch.int64, 1), _stream(stream)))
+
+
+def _result_dict(r):
+    return dict(n=r.n, status=r.status, count=int(r.count), listed=int(r.listed), state=r.state, list=r.list,
+                t_submit=r.t_submit, t_admit=r.t_admit, t_done=r.t_done)
+
+
+class Server:
+    """The request loop of dqmc_server_* (admission by memory footprint,
+    continuous batching, results kept on the device until released)."""
+
+    def __init__(self, device: int = 0, budget: int = 0, slots: int = 4):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise DqmcError(DQMC_EDEVICE, "no ROCm device visible")
+        out = ctypes.c_void_p()
+        rc = load().dqmc_server_create(device, int(budget), int(slots), ctypes.byref(out))
+        if rc != DQMC_OK:
+            raise DqmcError(rc, "dqmc_server_create failed")
+        self.srv = out
+
+    def submit(self, n: int, tt) -> int:
+        import numpy as np
+
+        a = np.ascontiguousarray(tt, dtype=np.uint32)
+        if a.size < dqmc_tt_words(n) if 0 <= n <= DQMC_MAX_N else False:
+            raise ValueError("truth table too short")
+        jid = ctypes.c_uint64()
+        rc = load().dqmc_server_submit(self.srv, int(n), a.ctypes.data, ctypes.byref(jid))
+        if rc != DQMC_OK:
+            raise DqmcError(rc, "submit failed")
+        return int(jid.value)
+
+    def poll(self, jid: int):
+        r = dqmc_result()
+        rc = load().dqmc_server_poll(self.srv, jid, ctypes.byref(r))
+        if rc < 0:
+            raise DqmcError(rc, "poll: unknown job %d" % jid)
+        return _result_dict(r) if rc == 1 else None
+
+    def wait(self, jid: int):
+        r = dqmc_result()
+        rc = load().dqmc_server_wait(self.srv, jid, ctypes.byref(r))
+        if rc != DQMC_OK:
+            raise DqmcError(rc, "wait: unknown job %d" % jid)
+        return _result_dict(r)
+
+    def read(self, jid: int, cap: int):
+        import numpy as np
+
+        out = np.zeros(max(1, int(cap)), dtype=np.uint64)
+        k = load().dqmc_server_read(self.srv, jid, out.ctypes.data, int(cap))
+        if k < 0:
+            raise DqmcError(int(k), "read failed")
+        return out[:k]
+
+    def release(self, jid: int):
+        rc = load().dqmc_server_release(self.srv, jid)
+        if rc != DQMC_OK:
+            raise DqmcError(rc, "release failed")
+
+    def close(self):
+        if self.srv is not None:
+            load().dqmc_server_destroy(self.srv)
+            self.srv = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 def dqmc_set_plan(ctx, n: int, sizes) -> None:
