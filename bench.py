@@ -138,6 +138,96 @@ def bench_batch(ctx, reps=5):
             "speedup_vs_per_fn_launch": ms_single / ms_batch, "graph_captured": True}
 
 
+def bench_serving(nreq=200, seed=25):
+    """Serving mix (n in {10,14,18,22,25} with weights .4/.3/.15/.1/.05):
+    saturation throughput from a closed loop, then Poisson arrivals at 0.5 and
+    0.8 of it; latency = completion - submission on the server's clock.  The
+    baseline serves the same arrival schedule one request at a time with one
+    dqmc_primes launch sequence per request."""
+    import threading
+
+    import numpy as np
+    import torch
+
+    from paper_2302_10083_amd import dqmc, inputs
+
+    specs = inputs.serving_specs(nreq, seed=seed)
+    tts = [inputs.make(s) for s in specs]
+
+    def run(srv, gaps):
+        """Submit requests 0..len(gaps)-1 with the given gaps; a consumer
+        thread waits for each in order and releases it."""
+        k = len(gaps)
+        ids, res = [], [None] * k
+
+        def consumer():
+            for i in range(k):
+                while len(ids) <= i:
+                    time.sleep(1e-4)
+                res[i] = srv.wait(ids[i])
+                srv.release(ids[i])
+
+        th = threading.Thread(target=consumer)
+        th.start()
+        t0 = time.perf_counter()
+        for s, tt, g in zip(specs[:k], tts[:k], gaps):
+            if g > 0:
+                time.sleep(g)
+            ids.append(srv.submit(s["n"], tt))
+        th.join()
+        wall = time.perf_counter() - t0
+        lat = np.array([r["t_done"] - r["t_submit"] for r in res])
+        return wall, lat
+
+    out = {"workload": "%d requests, n in {10,14,18,22,25} w.p. .4/.3/.15/.1/.05, half Bernoulli(0.5..0.95) "
+                       "half DNF (seed %d)" % (nreq, seed)}
+    print("bench: serving, %d requests generated" % nreq, file=sys.stderr, flush=True)
+    with dqmc.Server(0) as srv:
+        run(srv, [0.0] * 8)  # warm the pools and kernels
+        wall, lat = run(srv, [0.0] * nreq)
+        mu = nreq / wall
+        out["saturation_jobs_per_s"] = mu
+        print("bench: serving saturation %.1f jobs/s" % mu, file=sys.stderr, flush=True)
+        rng = np.random.default_rng(seed)
+        for frac in (0.5, 0.8):
+            lam = frac * mu
+            gaps = rng.exponential(1.0 / lam, size=nreq)
+            wall, lat = run(srv, gaps)
+            out["lambda_%.1f" % frac] = {"arrival_jobs_per_s": lam, "jobs_per_s": nreq / wall,
+                                         "p50_ms": float(np.percentile(lat, 50) * 1e3),
+                                         "p99_ms": float(np.percentile(lat, 99) * 1e3),
+                                         "mean_ms": float(lat.mean() * 1e3)}
+            print("bench: serving at %.1f of saturation done" % frac, file=sys.stderr, flush=True)
+    # baseline: one request at a time, same arrivals at 0.5 mu
+    ctx = dqmc.Context(0)
+    dev = ctx.torch_device
+    lam = 0.5 * mu
+    arr = np.cumsum(np.random.default_rng(seed).exponential(1.0 / lam, size=nreq))
+    lat = []
+    t0 = time.perf_counter()
+    for s, tt, a in zip(specs, tts, arr):
+        now = time.perf_counter() - t0
+        if now < a:
+            time.sleep(a - now)
+        n = s["n"]
+        cap = min(3**n, max(1 << 18, 3 ** max(n - 3, 0) // 16))
+        ttd = ctx.tt_to_device(tt)
+        st = ctx.new_state(n)
+        cnt = torch.zeros(1, dtype=torch.int64, device=dev)
+        lst = torch.empty(cap, dtype=torch.int64, device=dev)
+        dqmc.dqmc_primes(ctx.ctx, n, ttd, st, lst, cap, cnt)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t0 - a)
+        del st, lst
+    ctx.close()
+    torch.cuda.empty_cache()
+    lat = np.array(lat)
+    out["one_at_a_time_lambda_0.5"] = {"p50_ms": float(np.percentile(lat, 50) * 1e3),
+                                       "p99_ms": float(np.percentile(lat, 99) * 1e3),
+                                       "jobs_per_s": nreq / (time.perf_counter() - t0)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -148,6 +238,7 @@ def main():
     ap.add_argument("--cpu-threads", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -262,6 +353,13 @@ def main():
         out["batch"] = bench_batch(ctx)
         print("bench: batch %.2f ms (%.0f fns/s), per-function launches %.2f ms" % (
             out["batch"]["ms"], out["batch"]["fns_per_s"], out["batch"]["per_fn_launch_ms"]), file=sys.stderr, flush=True)
+
+    if not args.no_serving:
+        torch.cuda.empty_cache()
+        out["serving"] = bench_serving()
+        sv = out["serving"]
+        print("bench: serving saturation %.1f jobs/s; p99 %.1f ms at 0.8 of it" % (
+            sv["saturation_jobs_per_s"], sv["lambda_0.8"]["p99_ms"]), file=sys.stderr, flush=True)
 
     print(json.dumps(out), flush=True)
     ctx.close()

@@ -160,9 +160,11 @@ int dqmc_primes_batch(dqmc_ctx *ctx, dqmc_job *jobs, int32_t njobs, void *stream
  *
  * Jobs (one truth table each, copied from host memory at submission) are
  * admitted while the device-memory budget and the execution slots allow it:
- * a job's footprint is its state (dqmc_state_words(n) words), its truth
- * table, its count and a list reserve of min(3^n, max(2^18, 3^(n-3)/16))
- * entries.  Jobs with n <= 16 that are admitted together run as one batch
+ * the server reserves its whole budget as one device arena when it is
+ * created, and a job takes one block of its footprint - its state
+ * (dqmc_state_words(n) words), a list reserve of min(3^n, max(2^18,
+ * 3^(n-3)/16)) entries, its truth table and its count, each rounded up to
+ * 256 bytes.  Jobs with n <= 16 that are admitted together run as one batch
  * launch; larger jobs run on their own stream and context.  Jobs that arrive
  * while others run are admitted as memory and slots free up (continuous
  * batching), and their work overlaps on the device.  Results stay on the
@@ -170,8 +172,9 @@ int dqmc_primes_batch(dqmc_ctx *ctx, dqmc_job *jobs, int32_t njobs, void *stream
  * gives for it alone (the list holds min(count, reserve) smallest primes).
  *
  *   dqmc_server_create: budget in bytes of device memory for resident jobs
- *     (0 = 90% of the device memory free at creation), slots = number of
- *     concurrent large jobs (streams).  Starts the scheduler thread.
+ *     (0 = 90% of the device memory free at creation; allocated here),
+ *     slots = number of concurrent large jobs (streams; 0 = 4).  Starts the
+ *     scheduler thread.
  *   dqmc_server_submit: copies the table; *id receives the job id.
  *     DQMC_EINVAL for bad n / NULL, DQMC_ENOMEM if the footprint exceeds the
  *     whole budget.  Never waits for the device.

@@ -8,10 +8,12 @@
 //   3. launches: all admitted jobs with n <= kBatchMaxN go into one batch
 //      launch on a free batch slot, each larger job gets a free slot (stream
 //      + context) of its own.
-// Device memory is stream-ordered (hipMallocAsync on the launch stream, freed
-// on an idle release stream once the job is released), so jobs that arrive
-// while others run start as soon as memory and a slot are free and their
-// kernels overlap with the running ones.
+// Device memory is one arena of `budget` bytes allocated when the server is
+// created; each admitted job gets one block of its footprint from a host-side
+// first-fit allocator (large jobs from the low end, small ones from the high
+// end, freed blocks coalesce), so a job that arrives while others run starts
+// as soon as a block and a slot are free, without any device allocation, and
+// its kernels overlap with the running ones.
 #include <stdio.h>
 #include <string.h>
 
@@ -50,12 +52,69 @@ uint64_t list_reserve(int n)
 
 uint64_t tt_words_of(int n) { return n <= 5 ? 1 : (1ull << (n - 5)); }
 
+uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
+
+// Bytes of a job's arena block: state, list reserve, truth table, count.
 uint64_t footprint(int n)
 {
-    return 4 * pow3(n > 3 ? n - 3 : 0) + 4 * tt_words_of(n) + 8 * list_reserve(n) + 64;
+    return align256(4 * pow3(n > 3 ? n - 3 : 0)) + align256(8 * list_reserve(n)) + align256(4 * tt_words_of(n)) + 256;
 }
 
 enum Phase { kPending, kRunning, kDone, kReleased };
+
+// First-fit allocator over [0, size) with coalescing of freed blocks.
+class Arena {
+  public:
+    void init(uint64_t size)
+    {
+        free_.clear();
+        if (size > 0) free_[0] = size;
+    }
+    // lowest-addressed (or, from_top, highest-addressed) free block that fits
+    bool alloc(uint64_t sz, bool from_top, uint64_t *off)
+    {
+        if (!from_top) {
+            for (auto it = free_.begin(); it != free_.end(); ++it)
+                if (it->second >= sz) {
+                    *off = it->first;
+                    const uint64_t rest = it->second - sz, o = it->first + sz;
+                    free_.erase(it);
+                    if (rest) free_[o] = rest;
+                    return true;
+                }
+        } else {
+            for (auto it = free_.rbegin(); it != free_.rend(); ++it)
+                if (it->second >= sz) {
+                    const uint64_t o = it->first, len = it->second;
+                    *off = o + len - sz;
+                    if (len == sz) free_.erase(o);
+                    else free_[o] = len - sz;
+                    return true;
+                }
+        }
+        return false;
+    }
+    void release(uint64_t off, uint64_t sz)
+    {
+        auto nx = free_.lower_bound(off);
+        if (nx != free_.end() && off + sz == nx->first) {
+            sz += nx->second;
+            free_.erase(nx);
+        }
+        auto pv = free_.lower_bound(off);
+        if (pv != free_.begin()) {
+            --pv;
+            if (pv->first + pv->second == off) {
+                pv->second += sz;
+                return;
+            }
+        }
+        free_[off] = sz;
+    }
+
+  private:
+    std::map<uint64_t, uint64_t> free_;  // offset -> length
+};
 
 struct SJob {
     uint64_t id = 0;
@@ -71,6 +130,7 @@ struct SJob {
     uint64_t cap = 0;
     uint64_t count = 0;
     uint64_t fp = 0;
+    uint64_t off = 0;  // arena block
     double t_submit = 0, t_admit = 0, t_done = 0;
 };
 
@@ -93,8 +153,9 @@ struct Slot {
 struct dqmc_server {
     int device = 0;
     uint64_t budget = 0, used = 0;
+    uint8_t *arena_base = nullptr;
+    Arena arena;
     std::vector<Slot> big, small;
-    hipStream_t release_stream = nullptr;
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     std::map<uint64_t, SJob> jobs;
@@ -112,26 +173,27 @@ namespace {
 
 void free_job_device(dqmc_server *s, SJob &j)
 {
-    if (j.d_tt) (void)hipFreeAsync(j.d_tt, s->release_stream);
-    if (j.d_state) (void)hipFreeAsync(j.d_state, s->release_stream);
-    if (j.d_list) (void)hipFreeAsync(j.d_list, s->release_stream);
-    if (j.d_count) (void)hipFreeAsync(j.d_count, s->release_stream);
-    (void)hipStreamSynchronize(s->release_stream);
+    if (j.d_state != nullptr) s->arena.release(j.off, j.fp);
     j.d_tt = nullptr;
     j.d_state = nullptr;
     j.d_list = nullptr;
     j.d_count = nullptr;
 }
 
-// Allocate a job's buffers and enqueue its table upload on `st`.
-bool stage_job(SJob &j, hipStream_t st)
+// Carve a job's buffers out of its arena block and enqueue the upload of its
+// truth table on `st`.
+bool stage_job(dqmc_server *s, SJob &j, hipStream_t st)
 {
     const uint64_t nw = tt_words_of(j.n), sw = pow3(j.n > 3 ? j.n - 3 : 0);
     j.cap = list_reserve(j.n);
-    if (hipMallocAsync((void **)&j.d_tt, nw * 4, st) != hipSuccess) return false;
-    if (hipMallocAsync((void **)&j.d_state, sw * 4, st) != hipSuccess) return false;
-    if (hipMallocAsync((void **)&j.d_list, j.cap * 8, st) != hipSuccess) return false;
-    if (hipMallocAsync((void **)&j.d_count, 8, st) != hipSuccess) return false;
+    uint8_t *p = s->arena_base + j.off;
+    j.d_state = (uint32_t *)p;
+    p += align256(4 * sw);
+    j.d_list = (uint64_t *)p;
+    p += align256(8 * j.cap);
+    j.d_tt = (uint32_t *)p;
+    p += align256(4 * nw);
+    j.d_count = (uint64_t *)p;
     return hipMemcpyAsync(j.d_tt, j.h_tt, nw * 4, hipMemcpyHostToDevice, st) == hipSuccess;
 }
 
@@ -139,7 +201,7 @@ void launch_big(dqmc_server *s, Slot &sl, SJob &j)
 {
     sl.busy = true;
     sl.jobs.assign(1, j.id);
-    bool ok = stage_job(j, sl.stream);
+    bool ok = stage_job(s, j, sl.stream);
     if (ok)
         ok = dqmc_primes(sl.ctx, j.n, j.d_tt, j.d_state, j.d_list, j.cap, j.d_count, sl.stream) == DQMC_OK;
     if (ok) ok = hipMemcpyAsync(j.h_count, j.d_count, 8, hipMemcpyDeviceToHost, sl.stream) == hipSuccess;
@@ -154,7 +216,7 @@ void launch_small(dqmc_server *s, Slot &sl, const std::vector<uint64_t> &ids)
     uint32_t m = 0;
     for (uint64_t id : ids) {
         SJob &j = s->jobs[id];
-        if (!stage_job(j, sl.stream)) {
+        if (!stage_job(s, j, sl.stream)) {
             j.status = DQMC_EDEVICE;
             continue;
         }
@@ -230,17 +292,19 @@ void scheduler(dqmc_server *s)
         for (auto it = s->queue.begin(); it != s->queue.end();) {
             SJob &j = s->jobs[*it];
             const bool is_head = it == s->queue.begin();
-            const bool fits = s->used + j.fp <= s->budget;
+            const bool small = j.n <= kBatchMaxN;
             Slot *slot = nullptr;
-            if (j.n <= kBatchMaxN) {
-                if (free_small && small_ids.size() < kBatchSlotJobs && fits) slot = free_small;
-            } else if (fits) {
+            if (small) {
+                if (free_small && small_ids.size() < kBatchSlotJobs) slot = free_small;
+            } else {
                 for (Slot &sl : s->big)
                     if (!sl.busy) {
                         slot = &sl;
                         break;
                     }
             }
+            // small jobs from the top of the arena, large ones from the bottom
+            if (slot != nullptr && !s->arena.alloc(j.fp, small, &j.off)) slot = nullptr;
             if (slot == nullptr) {
                 if (is_head && now_s() - s->head_since > kAgingSeconds) break;  // let the head go first
                 ++it;
@@ -292,13 +356,7 @@ int dqmc_server_create(int device, uint64_t budget_bytes, int32_t slots, dqmc_se
         delete s;
         return DQMC_EDEVICE;
     }
-    // keep the freed blocks of the stream-ordered pool for reuse
-    hipMemPool_t pool;
-    if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess) {
-        uint64_t thr = UINT64_MAX;
-        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
-    }
-    bool ok = hipStreamCreateWithFlags(&s->release_stream, hipStreamNonBlocking) == hipSuccess;
+    bool ok = true;
     s->big.resize(slots);
     s->small.resize(2);
     for (auto *p : {&s->big, &s->small})
@@ -319,6 +377,13 @@ int dqmc_server_create(int device, uint64_t budget_bytes, int32_t slots, dqmc_se
         return DQMC_ENOMEM;
     }
     if (hipMemGetInfo(&fr, &tot) == hipSuccess && budget_bytes == 0) budget_bytes = (uint64_t)(0.9 * (double)fr);
+    budget_bytes &= ~uint64_t(255);
+    if (budget_bytes == 0 || hipMalloc((void **)&s->arena_base, budget_bytes) != hipSuccess) {
+        s->arena_base = nullptr;
+        dqmc_server_destroy(s);
+        return DQMC_ENOMEM;
+    }
+    s->arena.init(budget_bytes);
     s->budget = budget_bytes;
     s->thr = std::thread(scheduler, s);
     *out = s;
@@ -452,7 +517,7 @@ void dqmc_server_destroy(dqmc_server *s)
             if (sl.d_order) (void)hipFree(sl.d_order);
             if (sl.d_ticket) (void)hipFree(sl.d_ticket);
         }
-    if (s->release_stream) (void)hipStreamDestroy(s->release_stream);
+    if (s->arena_base) (void)hipFree(s->arena_base);
     delete s;
 }
 

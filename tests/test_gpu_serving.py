@@ -20,7 +20,8 @@ def list_reserve(n):
 
 def footprint(n):
     tt = 1 if n <= 5 else 1 << (n - 5)
-    return 4 * 3 ** max(n - 3, 0) + 4 * tt + 8 * list_reserve(n) + 64
+    a = lambda x: (x + 255) // 256 * 256
+    return a(4 * 3 ** max(n - 3, 0)) + a(8 * list_reserve(n)) + a(4 * tt) + 256
 
 
 def _hash(ctx, addr, nwords):
