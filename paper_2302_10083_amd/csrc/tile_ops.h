@@ -136,7 +136,7 @@ __device__ __forceinline__ void load_tile(uint32_t *t, const uint32_t *src, uint
     static_for<U>([&](auto ui) {
         constexpr int u = decltype(ui)::value;
         const uint32_t *su = src + u * THREADS;
-        v[u] = threadIdx.x + u * THREADS < tw ? __builtin_nontemporal_load(su + threadIdx.x) : 0u;
+        v[u] = threadIdx.x + u * THREADS < tw ? su[threadIdx.x] : 0u;
     });
     static_for<U>([&](auto ui) {
         constexpr int u = decltype(ui)::value;
@@ -156,7 +156,7 @@ __device__ __forceinline__ void store_tile(uint32_t *dst, const uint32_t *t, uin
     static_for<U>([&](auto ui) {
         constexpr int u = decltype(ui)::value;
         uint32_t *du = dst + u * THREADS;
-        if (threadIdx.x + u * THREADS < tw) __builtin_nontemporal_store(v[u], du + threadIdx.x);
+        if (threadIdx.x + u * THREADS < tw) du[threadIdx.x] = v[u];
     });
 }
 
@@ -179,7 +179,7 @@ __device__ __forceinline__ void last_round_to_hbm(uint32_t *t, uint32_t *dst, ui
         reg_reduce<3>(x);
         static_for<27>([&](auto ci) {
             constexpr int k = decltype(ci)::value;
-            __builtin_nontemporal_store(x[k], dst + q + k * S);
+            dst[q + k * S] = x[k];
             c += __popc(x[k]);
             if (x[k] != 0u) {
                 const uint32_t chunk = (q + k * S) / kChunkWords;
