@@ -101,6 +101,8 @@ def bench_batch(ctx, reps=5):
     plan = dqmc.Batch(ctx.ctx, jobs)
     plan.run()
     torch.cuda.synchronize()
+    trials = plan.autotune(reps=2)  # keeps the fastest grid / order on the plan
+    best = min(trials, key=lambda t: t["ms"])
     g = torch.cuda.CUDAGraph()
     st = torch.cuda.Stream()
     st.wait_stream(torch.cuda.current_stream())
@@ -135,7 +137,9 @@ def bench_batch(ctx, reps=5):
             "fns": len(specs), "state_GB": state_bytes / 1e9,
             "ms": ms_batch, "fns_per_s": len(specs) / (ms_batch / 1e3),
             "per_fn_launch_ms": ms_single, "per_fn_launch_fns_per_s": len(specs) / (ms_single / 1e3),
-            "speedup_vs_per_fn_launch": ms_single / ms_batch, "graph_captured": True}
+            "speedup_vs_per_fn_launch": ms_single / ms_batch, "graph_captured": True,
+            "autotune": {"grid": best["grid"], "order": best["order"],
+                         "trials": [[t["grid"], t["order"], round(t["ms"], 3)] for t in trials]}}
 
 
 def bench_serving(nreq=200, seed=25):
@@ -239,6 +243,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--tune-extra-groups", type=int, default=1,
+                    help="pass plans with up to this many groups beyond the fewest are timed (autotuner)")
+    ap.add_argument("--no-tune", action="store_true")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -267,6 +274,13 @@ def main():
     nprimes = int(count.item())
     lst = torch.empty(max(nprimes, 1), dtype=torch.int64, device=dev)
     print("bench: %d primes (list %.2f GB)" % (nprimes, nprimes * 8 / 1e9), file=sys.stderr, flush=True)
+    # the autotuner times the pass plans on this input and keeps the fastest
+    plan_trials = []
+    if not args.no_tune and n > 12:
+        plan_trials = dqmc.dqmc_plan_autotune(ctx.ctx, n, ttd, state, count, extra_groups=args.tune_extra_groups,
+                                              reps=1)
+        print("bench: plan autotune: %d plans, chosen %s" % (len(plan_trials), dqmc.dqmc_get_plan(ctx.ctx, n)),
+              file=sys.stderr, flush=True)
 
     for _ in range(args.warmup):
         dqmc.dqmc_primes(ctx.ctx, n, ttd, state, lst, nprimes, count)
@@ -328,6 +342,8 @@ def main():
         "model_bytes_per_step": total_bytes,
         "wall_s_timed": wall,
         "passes": pass_rows,
+        "plan": {"groups": dqmc.dqmc_get_plan(ctx.ctx, n), "passes_per_step": len(pass_rows),
+                 "autotune_trials": [[t["sizes"], round(t["ms"], 3)] for t in plan_trials]},
         "roofline": {"bound": "hbm", "kernel": dom["name"], "achieved": achieved, "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
                      "traffic": traffic, "model_bytes_per_launch": dom_bytes},

@@ -29,7 +29,9 @@
  *  Ownership: the caller owns and allocates every buffer argument (device
  *  memory unless stated otherwise).  The context owns small scratch memory
  *  allocated when it is created, a batch plan owns its job table allocated
- *  by dqmc_batch_create; no other entry point allocates.
+ *  by dqmc_batch_create, a server owns the arena it reserves in
+ *  dqmc_server_create; no other entry point allocates device memory (the
+ *  autotuning calls create and destroy two HIP events).
  *  Asynchrony: compute entry points only enqueue work on `stream` and return;
  *  results are valid after the stream is synchronised.  Argument errors are
  *  found on the host before anything is enqueued and return DQMC_EINVAL;
@@ -226,6 +228,51 @@ int dqmc_hash_words(dqmc_ctx *ctx, const uint32_t *d_words, uint64_t nwords, uin
  */
 int dqmc_set_plan(dqmc_ctx *ctx, int n, const int32_t *sizes, int ngroups);
 int dqmc_get_plan(const dqmc_ctx *ctx, int n, int32_t *sizes, int cap);
+
+/* ---------------------------------------------------------------------------
+ * Autotuning: measure the launch choices that leave results unchanged (the
+ * batch bit-slicing launch of Sec. 4.2, the grouping of Alg. 4's top-layer
+ * dimensions into passes) and keep the fastest.
+ *
+ * Both calls run the computation several times on the caller's buffers (the
+ * outputs end up exactly as after one normal call), time each run with HIP
+ * events on `stream`, and wait for the stream before returning.  They return
+ * DQMC_EINVAL while `stream` is being captured into a graph, and on bad
+ * arguments; a failing run's status is returned as is.  trials (host memory,
+ * may be NULL when cap == 0) receives up to cap trials; *ntrials (may be
+ * NULL) the number timed.  A trial's ms is its fastest of `reps` timed runs
+ * (reps >= 1), each after one untimed run.
+ *
+ * dqmc_batch_autotune: candidates are 1, 2 and 4 persistent workgroups per
+ * compute unit, each with order 0 and 1 (six trials); the fastest is set on
+ * the plan with dqmc_batch_config.
+ *
+ * dqmc_plan_autotune (12 < n <= 25): candidates are the plans with the
+ * fewest groups up to that number plus extra_groups (0..2): every ordered
+ * split of digits 13..n into groups of 1..6 digits, at most
+ * DQMC_MAX_PLAN_TRIALS of them, by group count, then lexicographically by
+ * sizes.  Each is timed on dqmc_primes without a list (the count goes to
+ * d_count); the fastest is set with dqmc_set_plan.  d_state holds that
+ * call's result afterwards.  If a run fails, the plan in force before the
+ * call is restored.
+ */
+typedef struct {
+    int32_t grid;
+    int32_t order;
+    float ms;
+} dqmc_batch_trial;
+int dqmc_batch_autotune(dqmc_batch *plan, int32_t reps, void *stream, dqmc_batch_trial *trials, int32_t cap,
+                        int32_t *ntrials);
+
+#define DQMC_MAX_PLAN_TRIALS 64
+typedef struct {
+    int32_t ngroups;
+    int32_t sizes[DQMC_MAX_N];
+    float ms;
+} dqmc_plan_trial;
+int dqmc_plan_autotune(dqmc_ctx *ctx, int n, const uint32_t *d_tt, uint32_t *d_state, uint64_t *d_count,
+                       int32_t extra_groups, int32_t reps, void *stream, dqmc_plan_trial *trials, int32_t cap,
+                       int32_t *ntrials);
 
 /* ---------------------------------------------------------------------------
  * Diagnostics: per-pass device timing.

@@ -18,31 +18,13 @@
 #include <cmath>
 #include <vector>
 
+#include "api_types.h"
 #include "dqmc.h"  // include/dqmc.h (the public C ABI)
 #include "launch.h"
 #include "t27.h"
 
 using namespace dqmc;
 
-struct dqmc_ctx {
-    int device;
-    // per low tile: count of set bits, non-zero chunk map, list offset
-    uint64_t tiles_cap;
-    uint32_t *counts;
-    uint32_t *chunkmap;
-    uint64_t *offs;
-    uint64_t *sums;  // per-block sums of the count scan
-    char err[512];
-    // per-pass timing (diagnostics)
-    bool prof;
-    bool events_made;
-    int nrec;
-    hipEvent_t ev[2 * DQMC_MAX_RECORDS];
-    dqmc_pass_record rec[DQMC_MAX_RECORDS];
-    // pass plan overrides: group sizes of digits 13..n (0 groups = default)
-    int plan_len[DQMC_MAX_N + 1];
-    int plan[DQMC_MAX_N + 1][DQMC_MAX_N];
-};
 
 namespace {
 
@@ -238,6 +220,8 @@ int dqmc_create(int device, dqmc_ctx **out)
     if (low_setup() != hipSuccess || col_setup() != hipSuccess || batch_setup() != hipSuccess) return DQMC_EDEVICE;
     dqmc_ctx *c = new dqmc_ctx();
     c->device = device;
+    if (hipDeviceGetAttribute(&c->ncu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || c->ncu <= 0)
+        c->ncu = 256;
     c->tiles_cap = pow3(DQMC_MAX_N - kLowDigits);
     c->counts = nullptr;
     c->chunkmap = nullptr;
@@ -351,16 +335,6 @@ int dqmc_bitmap_to_dense(dqmc_ctx *ctx, int n, const uint32_t *d_state, uint64_t
 
 }  // extern "C"
 
-struct dqmc_batch {
-    dqmc_ctx *ctx;
-    BatchJob *d_jobs;
-    uint32_t *d_order;
-    uint32_t *d_ticket;
-    std::vector<BatchJob> small;  // n <= kBatchMaxN, in job-table order
-    std::vector<BatchJob> big;    // larger functions: single-function path
-    int32_t grid;
-    int32_t order_mode;
-};
 
 namespace {
 
@@ -422,10 +396,7 @@ int dqmc_batch_create(dqmc_ctx *ctx, dqmc_job *jobs, int32_t njobs, dqmc_batch *
         BatchJob bj{j.tt, j.state, j.list, j.list ? j.list_cap : 0, j.count, j.n, 0};
         (j.n <= kBatchMaxN ? b->small : b->big).push_back(bj);
     }
-    int ncu = 0;
-    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess || ncu <= 0)
-        ncu = 256;
-    b->grid = 2 * ncu;
+    b->grid = 2 * ctx->ncu;
     const size_t m = b->small.size();
     if (hipMalloc((void **)&b->d_ticket, 256) != hipSuccess ||
         (m > 0 && (hipMalloc((void **)&b->d_jobs, m * sizeof(BatchJob)) != hipSuccess ||

@@ -1,0 +1,40 @@
+// Host-side state behind the opaque handles of the C ABI (dqmc_ctx,
+// dqmc_batch); shared by the entry points and the autotuner.
+#pragma once
+
+#include <vector>
+
+#include "dqmc.h"
+#include "launch.h"
+
+struct dqmc_ctx {
+    int device;
+    int ncu;  // compute units of the device
+    // per low tile: count of set bits, non-zero chunk map, list offset
+    uint64_t tiles_cap;
+    uint32_t *counts;
+    uint32_t *chunkmap;
+    uint64_t *offs;
+    uint64_t *sums;  // per-block sums of the count scan
+    char err[512];
+    // per-pass timing (diagnostics)
+    bool prof;
+    bool events_made;
+    int nrec;
+    hipEvent_t ev[2 * DQMC_MAX_RECORDS];
+    dqmc_pass_record rec[DQMC_MAX_RECORDS];
+    // pass plan overrides: group sizes of digits 13..n (0 groups = default)
+    int plan_len[DQMC_MAX_N + 1];
+    int plan[DQMC_MAX_N + 1][DQMC_MAX_N];
+};
+
+struct dqmc_batch {
+    dqmc_ctx *ctx;
+    dqmc::BatchJob *d_jobs;
+    uint32_t *d_order;
+    uint32_t *d_ticket;
+    std::vector<dqmc::BatchJob> small;  // n <= kBatchMaxN, in job-table order
+    std::vector<dqmc::BatchJob> big;    // larger functions: single-function path
+    int32_t grid;
+    int32_t order_mode;
+};

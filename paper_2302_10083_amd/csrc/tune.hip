@@ -1,0 +1,168 @@
+// Autotuning of the launch choices that leave results unchanged: the
+// persistent grid and job order of a batch plan, and the digit-group plan of
+// the single-function pipeline.  Candidates are timed on the caller's own
+// buffers with HIP events on the caller's stream; the fastest is applied
+// through the public configuration calls (dqmc_batch_config, dqmc_set_plan).
+#include <stdio.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "api_types.h"
+#include "dqmc.h"
+
+namespace {
+
+constexpr int kLowDigits = 12;
+constexpr int kMaxGroup = 6;
+
+int tune_fail(dqmc_ctx *ctx, int code, const char *msg)
+{
+    if (ctx) snprintf(ctx->err, sizeof(ctx->err), "%s", msg);
+    return code;
+}
+
+// Times `reps` runs of f on stream s after one untimed run; returns the
+// fastest run in milliseconds, or a negative value on a HIP error or a
+// failing run (its status in *rc).
+template <typename F>
+float time_best(hipStream_t s, int reps, int *rc, F &&f)
+{
+    *rc = f();
+    if (*rc != DQMC_OK) return -1.0f;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return -1.0f;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return -1.0f;
+    }
+    float best = -1.0f;
+    for (int r = 0; r < reps; ++r) {
+        if (hipEventRecord(e0, s) != hipSuccess) break;
+        *rc = f();
+        if (*rc != DQMC_OK) break;
+        float ms = 0.0f;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            best = -1.0f;
+            break;
+        }
+        if (best < 0.0f || ms < best) best = ms;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return *rc == DQMC_OK ? best : -1.0f;
+}
+
+// Every ordered split of h digits into k groups of 1..kMaxGroup digits, in
+// lexicographic order of the sizes.
+void splits(int h, int k, std::vector<int> &cur, std::vector<std::vector<int>> &out, size_t limit)
+{
+    if (out.size() >= limit) return;
+    if (k == 0) {
+        if (h == 0) out.push_back(cur);
+        return;
+    }
+    for (int s = 1; s <= kMaxGroup && s <= h; ++s) {
+        if (h - s > (k - 1) * kMaxGroup) continue;  // the rest cannot fit
+        cur.push_back(s);
+        splits(h - s, k - 1, cur, out, limit);
+        cur.pop_back();
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int dqmc_batch_autotune(dqmc_batch *plan, int32_t reps, void *stream, dqmc_batch_trial *trials, int32_t cap,
+                        int32_t *ntrials)
+{
+    if (ntrials != nullptr) *ntrials = 0;
+    if (plan == nullptr || reps < 1 || cap < 0 || (trials == nullptr && cap > 0)) return DQMC_EINVAL;
+    dqmc_ctx *ctx = plan->ctx;
+    ctx->err[0] = 0;
+    if (hipSetDevice(ctx->device) != hipSuccess) return tune_fail(ctx, DQMC_EDEVICE, "hipSetDevice failed");
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing((hipStream_t)stream, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
+        return tune_fail(ctx, DQMC_EINVAL, "autotuning cannot run while the stream is captured");
+    const int per_cu[] = {1, 2, 4};
+    int32_t best_grid = plan->grid, best_order = plan->order_mode, n = 0;
+    float best = -1.0f;
+    for (int order = 0; order <= 1; ++order) {
+        for (int pc : per_cu) {
+            const int32_t grid = pc * ctx->ncu;
+            int rc = dqmc_batch_config(plan, grid, order);
+            if (rc != DQMC_OK) return rc;
+            const float ms = time_best((hipStream_t)stream, reps, &rc, [&] { return dqmc_batch_run(plan, stream); });
+            if (rc != DQMC_OK) return rc;
+            if (ms < 0.0f) return tune_fail(ctx, DQMC_EDEVICE, "timing a batch candidate failed");
+            if (n < cap) trials[n] = dqmc_batch_trial{grid, order, ms};
+            ++n;
+            if (best < 0.0f || ms < best) {
+                best = ms;
+                best_grid = grid;
+                best_order = order;
+            }
+        }
+    }
+    if (ntrials != nullptr) *ntrials = n;
+    return dqmc_batch_config(plan, best_grid, best_order);
+}
+
+int dqmc_plan_autotune(dqmc_ctx *ctx, int n, const uint32_t *d_tt, uint32_t *d_state, uint64_t *d_count,
+                       int32_t extra_groups, int32_t reps, void *stream, dqmc_plan_trial *trials, int32_t cap,
+                       int32_t *ntrials)
+{
+    if (ntrials != nullptr) *ntrials = 0;
+    if (ctx == nullptr) return DQMC_EINVAL;
+    ctx->err[0] = 0;
+    if (n <= kLowDigits || n > DQMC_MAX_N) return tune_fail(ctx, DQMC_EINVAL, "plan tuning needs 12 < n <= 25");
+    if (extra_groups < 0 || extra_groups > 2 || reps < 1 || cap < 0 || (trials == nullptr && cap > 0))
+        return tune_fail(ctx, DQMC_EINVAL, "bad extra_groups, reps or trial buffer");
+    if (d_tt == nullptr || d_state == nullptr || d_count == nullptr)
+        return tune_fail(ctx, DQMC_EINVAL, "NULL truth table, state or count");
+    if (hipSetDevice(ctx->device) != hipSuccess) return tune_fail(ctx, DQMC_EDEVICE, "hipSetDevice failed");
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing((hipStream_t)stream, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
+        return tune_fail(ctx, DQMC_EINVAL, "autotuning cannot run while the stream is captured");
+    const int h = n - kLowDigits, kmin = (h + kMaxGroup - 1) / kMaxGroup;
+    std::vector<std::vector<int>> cands;
+    std::vector<int> cur;
+    for (int k = kmin; k <= std::min(h, kmin + extra_groups); ++k) splits(h, k, cur, cands, DQMC_MAX_PLAN_TRIALS);
+    // the plan in force is restored if a run fails
+    int32_t keep[DQMC_MAX_N];
+    const int nkeep = ctx->plan_len[n];
+    for (int i = 0; i < nkeep; ++i) keep[i] = ctx->plan[n][i];
+    auto restore = [&](int rc) {
+        (void)dqmc_set_plan(ctx, n, keep, nkeep);
+        return rc;
+    };
+    int best_i = -1, count = 0;
+    float best = -1.0f;
+    for (size_t i = 0; i < cands.size(); ++i) {
+        std::vector<int32_t> sz(cands[i].begin(), cands[i].end());
+        int rc = dqmc_set_plan(ctx, n, sz.data(), (int)sz.size());
+        if (rc != DQMC_OK) return restore(rc);
+        const float ms = time_best((hipStream_t)stream, reps, &rc,
+                                   [&] { return dqmc_primes(ctx, n, d_tt, d_state, nullptr, 0, d_count, stream); });
+        if (rc != DQMC_OK) return restore(rc);
+        if (ms < 0.0f) return restore(tune_fail(ctx, DQMC_EDEVICE, "timing a plan candidate failed"));
+        if (count < cap) {
+            dqmc_plan_trial &t = trials[count];
+            t.ngroups = (int32_t)sz.size();
+            for (int g = 0; g < DQMC_MAX_N; ++g) t.sizes[g] = g < (int)sz.size() ? sz[g] : 0;
+            t.ms = ms;
+        }
+        ++count;
+        if (best < 0.0f || ms < best) {
+            best = ms;
+            best_i = (int)i;
+        }
+    }
+    if (ntrials != nullptr) *ntrials = count;
+    std::vector<int32_t> win(cands[best_i].begin(), cands[best_i].end());
+    return dqmc_set_plan(ctx, n, win.data(), (int)win.size());
+}
+
+}  // extern "C"

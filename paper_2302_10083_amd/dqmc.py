@@ -44,6 +44,7 @@ class dqmc_pass_record(ctypes.Structure):
 
 
 DQMC_MAX_RECORDS = 64
+DQMC_MAX_PLAN_TRIALS = 64
 
 
 class dqmc_result(ctypes.Structure):
@@ -70,6 +71,14 @@ class dqmc_job(ctypes.Structure):
         ("list_cap", ctypes.c_uint64),
         ("count", ctypes.c_void_p),
     ]
+
+
+class dqmc_batch_trial(ctypes.Structure):
+    _fields_ = [("grid", ctypes.c_int32), ("order", ctypes.c_int32), ("ms", ctypes.c_float)]
+
+
+class dqmc_plan_trial(ctypes.Structure):
+    _fields_ = [("ngroups", ctypes.c_int32), ("sizes", ctypes.c_int32 * DQMC_MAX_N), ("ms", ctypes.c_float)]
 
 
 def load():
@@ -113,6 +122,11 @@ def load():
             "dqmc_server_destroy": (None, [vp]),
             "dqmc_get_plan": (i32, [vp, i32, ctypes.POINTER(ctypes.c_int32), i32]),
             "dqmc_profile_read": (i32, [vp, ctypes.POINTER(dqmc_pass_record), i32]),
+            "dqmc_batch_autotune": (i32, [vp, ctypes.c_int32, vp, ctypes.POINTER(dqmc_batch_trial), ctypes.c_int32,
+                                          ctypes.POINTER(ctypes.c_int32)]),
+            "dqmc_plan_autotune": (i32, [vp, i32, vp, vp, vp, ctypes.c_int32, ctypes.c_int32, vp,
+                                         ctypes.POINTER(dqmc_plan_trial), ctypes.c_int32,
+                                         ctypes.POINTER(ctypes.c_int32)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(lib, name)
@@ -286,6 +300,14 @@ class Batch:
     def run(self, stream=None):
         _check(self.ctx, load().dqmc_batch_run(self.plan, _stream(stream)))
 
+    def autotune(self, reps: int = 3, stream=None) -> list:
+        """dqmc_batch_autotune: time the grid/order candidates, keep the
+        fastest; returns the trials as dicts (grid, order, ms)."""
+        arr = (dqmc_batch_trial * 16)()
+        k = ctypes.c_int32(0)
+        _check(self.ctx, load().dqmc_batch_autotune(self.plan, reps, _stream(stream), arr, 16, ctypes.byref(k)))
+        return [dict(grid=arr[i].grid, order=arr[i].order, ms=float(arr[i].ms)) for i in range(min(k.value, 16))]
+
     def close(self):
         if self.plan is not None:
             load().dqmc_batch_destroy(self.plan)
@@ -391,6 +413,23 @@ def dqmc_get_plan(ctx, n: int) -> list:
     if k < 0:
         _check(ctx, k)
     return [int(arr[i]) for i in range(k)]
+
+
+def dqmc_plan_autotune(ctx, n: int, tt, state, count, extra_groups: int = 0, reps: int = 2, stream=None) -> list:
+    """Time the pass plans for n (see include/dqmc.h), set the fastest on
+    the context; returns the trials as dicts (sizes, ms)."""
+    import torch
+
+    cap = DQMC_MAX_PLAN_TRIALS
+    arr = (dqmc_plan_trial * cap)()
+    k = ctypes.c_int32(0)
+    rc = load().dqmc_plan_autotune(ctx, n, _ptr(tt, "tt", torch.int32, dqmc_tt_words(n)),
+                                   _ptr(state, "state", torch.int32, dqmc_state_words(n)),
+                                   _ptr(count, "count", torch.int64, 1), int(extra_groups), int(reps),
+                                   _stream(stream), arr, cap, ctypes.byref(k))
+    _check(ctx, rc)
+    return [dict(sizes=[int(arr[i].sizes[g]) for g in range(arr[i].ngroups)], ms=float(arr[i].ms))
+            for i in range(min(k.value, cap))]
 
 
 def dqmc_profile(ctx, enable: bool) -> None:
