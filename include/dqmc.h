@@ -130,11 +130,13 @@ typedef struct {
 } dqmc_job;
 
 /* Prime implicants of many independent functions (the batch bit-slicing of
- * independent executions, Sec. 4.2).  Functions with n <= 16 run in ONE
+ * independent executions, Sec. 4.2).  Functions with n <= 12 run in ONE
  * persistent launch in which each workgroup takes the next function (largest
- * first) and runs its whole pipeline; larger functions of the batch take the
- * single-function path on the same stream afterwards.  The result of each
- * job is exactly what dqmc_primes gives for it alone.
+ * first) and runs its whole pipeline; functions with 13 <= n <= 16 share
+ * five tile-parallel launches (every tile and column of every such function
+ * is one work item); larger functions of the batch take the single-function
+ * path on the same stream afterwards.  The result of each job is exactly
+ * what dqmc_primes gives for it alone.
  *
  * Plans separate the host work (checks, ordering, upload of the job table)
  * from the launch, so that dqmc_batch_run can be captured in a HIP graph and
@@ -142,10 +144,12 @@ typedef struct {
  * valid while a plan is run.
  *   dqmc_batch_create: jobs[i].status is set (DQMC_OK, or DQMC_EINVAL for a
  *     malformed job, which is left out while the others still run); the
- *     plan's device memory (job table) is allocated here.  Returns DQMC_OK,
+ *     plan's device memory (job tables, per-tile scratch of the functions
+ *     with 13..16 variables: 52 bytes per tile) is allocated here.  Returns DQMC_OK,
  *     DQMC_EINVAL for a NULL/negative job array, DQMC_ENOMEM / DQMC_EDEVICE.
- *   dqmc_batch_config: grid = number of persistent workgroups (0 = default:
- *     two per compute unit); order = 0 largest first, 1 interleaved sizes.
+ *   dqmc_batch_config: for the persistent launch of the functions with
+ *     n <= 12, grid = number of workgroups (0 = default: two per compute
+ *     unit) and order = 0 largest first, 1 interleaved sizes.
  *   dqmc_batch_run: enqueue everything on `stream`.
  *   dqmc_batch_destroy: free the plan (no run may be in flight).
  * dqmc_primes_batch = create + run + wait for the stream + destroy: it
@@ -167,7 +171,8 @@ int dqmc_primes_batch(dqmc_ctx *ctx, dqmc_job *jobs, int32_t njobs, void *stream
  * (dqmc_state_words(n) words), a list reserve of min(3^n, max(2^18,
  * 3^(n-3)/16)) entries, its truth table and its count, each rounded up to
  * 256 bytes.  Jobs with n <= 16 that are admitted together run as one batch
- * launch; larger jobs run on their own stream and context.  Jobs that arrive
+ * (the launches of dqmc_batch_run); larger jobs run on their own stream and
+ * context.  Jobs that arrive
  * while others run are admitted as memory and slots free up (continuous
  * batching), and their work overlaps on the device.  Results stay on the
  * device until released; the result of a job is exactly what dqmc_primes

@@ -371,6 +371,10 @@ void dqmc_batch_destroy(dqmc_batch *b)
     if (b->d_jobs) (void)hipFree(b->d_jobs);
     if (b->d_order) (void)hipFree(b->d_order);
     if (b->d_ticket) (void)hipFree(b->d_ticket);
+    void *tbl[] = {(void *)b->tb.jobs, (void *)b->tb.bin_job, (void *)b->tb.tile_job,
+                   (void *)b->tb.counts, (void *)b->tb.chunkmap, (void *)b->tb.offs};
+    for (void *p : tbl)
+        if (p) (void)hipFree(p);
     delete b;
 }
 
@@ -385,6 +389,7 @@ int dqmc_batch_create(dqmc_ctx *ctx, dqmc_job *jobs, int32_t njobs, dqmc_batch *
     b->d_jobs = nullptr;
     b->d_order = nullptr;
     b->d_ticket = nullptr;
+    b->tb = TileBatch{};
     b->order_mode = 0;
     for (int32_t i = 0; i < njobs; ++i) {
         dqmc_job &j = jobs[i];
@@ -394,7 +399,7 @@ int dqmc_batch_create(dqmc_ctx *ctx, dqmc_job *jobs, int32_t njobs, dqmc_batch *
         j.status = ok ? DQMC_OK : DQMC_EINVAL;
         if (!ok) continue;
         BatchJob bj{j.tt, j.state, j.list, j.list ? j.list_cap : 0, j.count, j.n, 0};
-        (j.n <= kBatchMaxN ? b->small : b->big).push_back(bj);
+        (j.n <= kBatchWholeMaxN ? b->small : j.n <= kBatchTileMaxN ? b->tiled : b->big).push_back(bj);
     }
     b->grid = 2 * ctx->ncu;
     const size_t m = b->small.size();
@@ -412,6 +417,38 @@ int dqmc_batch_create(dqmc_ctx *ctx, dqmc_job *jobs, int32_t njobs, dqmc_batch *
     if (rc != DQMC_OK) {
         dqmc_batch_destroy(b);
         return rc;
+    }
+    // tile-parallel functions: work-item tables and per-tile scratch
+    const uint32_t mt = (uint32_t)b->tiled.size();
+    if (mt > 0) {
+        if (b->tiled.size() > (1u << 24)) {
+            dqmc_batch_destroy(b);
+            return fail(ctx, DQMC_EINVAL, "%s", "too many functions with 13..16 variables in one batch");
+        }
+        std::vector<TileJob> tj(mt);
+        std::vector<uint32_t> bin_job(mt * 16), tile_job(mt * 81);
+        tile_layout(b->tiled.data(), mt, tj.data(), bin_job.data(), tile_job.data(), b->tb);
+        TileBatch &t = b->tb;
+        const uint64_t nt = t.ntiles;
+        bool ok = hipMalloc((void **)&t.jobs, mt * sizeof(TileJob)) == hipSuccess &&
+                  hipMalloc((void **)&t.bin_job, t.nbin * sizeof(uint32_t)) == hipSuccess &&
+                  hipMalloc((void **)&t.tile_job, nt * sizeof(uint32_t)) == hipSuccess &&
+                  hipMalloc((void **)&t.counts, nt * sizeof(uint32_t)) == hipSuccess &&
+                  hipMalloc((void **)&t.chunkmap, nt * kMapWords * sizeof(uint32_t)) == hipSuccess &&
+                  hipMalloc((void **)&t.offs, nt * sizeof(uint64_t)) == hipSuccess;
+        if (!ok) {
+            dqmc_batch_destroy(b);
+            return fail(ctx, DQMC_ENOMEM, "%s", "batch plan allocation failed");
+        }
+        ok = hipMemcpy((void *)t.jobs, tj.data(), mt * sizeof(TileJob), hipMemcpyHostToDevice) == hipSuccess &&
+             hipMemcpy((void *)t.bin_job, bin_job.data(), t.nbin * sizeof(uint32_t), hipMemcpyHostToDevice) ==
+                 hipSuccess &&
+             hipMemcpy((void *)t.tile_job, tile_job.data(), nt * sizeof(uint32_t), hipMemcpyHostToDevice) ==
+                 hipSuccess;
+        if (!ok) {
+            dqmc_batch_destroy(b);
+            return fail(ctx, DQMC_EDEVICE, "%s", "upload of the batch tables failed");
+        }
     }
     *out = b;
     return DQMC_OK;
@@ -443,6 +480,12 @@ int dqmc_batch_run(dqmc_batch *b, void *stream)
         return launch_batch(b->d_jobs, b->d_order, m, b->d_ticket, (uint32_t)b->grid, s);
     });
     if (rc != DQMC_OK) return rc;
+    if (!b->tiled.empty()) {
+        double tbytes = 0;
+        for (const BatchJob &j : b->tiled) tbytes += 3.0 * state_bytes(j.n);
+        rc = run_pass(ctx, s, "batch_tiles", -1, tbytes, 8, [&] { return launch_tile_batch(b->tb, s); });
+        if (rc != DQMC_OK) return rc;
+    }
     for (const BatchJob &j : b->big) {
         rc = dqmc_primes(ctx, j.n, j.tt, j.state, j.list, j.cap, j.count, stream);
         if (rc != DQMC_OK) return rc;

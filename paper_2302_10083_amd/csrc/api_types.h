@@ -33,8 +33,10 @@ struct dqmc_batch {
     dqmc::BatchJob *d_jobs;
     uint32_t *d_order;
     uint32_t *d_ticket;
-    std::vector<dqmc::BatchJob> small;  // n <= kBatchMaxN, in job-table order
+    std::vector<dqmc::BatchJob> small;  // n <= kBatchWholeMaxN, in job-table order
+    std::vector<dqmc::BatchJob> tiled;  // kBatchWholeMaxN < n <= kBatchTileMaxN
     std::vector<dqmc::BatchJob> big;    // larger functions: single-function path
+    dqmc::TileBatch tb;                 // device tables of the tiled functions
     int32_t grid;
     int32_t order_mode;
 };

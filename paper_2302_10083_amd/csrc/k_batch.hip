@@ -1,14 +1,18 @@
-// Batched prime implicants: many independent functions in one persistent
-// launch.
+// Batched prime implicants: many independent functions per launch.
 //
 // The paper notes that independent executions of one Boolean circuit can be
 // bit-sliced side by side (Sec. 4.2, batch bit-slicing).  Here the unit of
-// batching is a whole function: each workgroup takes the next function from a
-// ticket (largest first) and runs its entire pipeline on its own - low tiles
-// from the truth table, the high-digit column pass, the final reduce, the
-// bitmap and the ordered list - so workgroups never wait on each other and
-// the launch can be captured in a graph.  Functions with up to 16 variables
-// take this path (digits 13..16 form one register-resident group).
+// batching is a whole function:
+//  - functions with up to 12 variables fit one LDS tile: in one persistent
+//    launch each workgroup takes the next function from a ticket (largest
+//    first) and runs its entire pipeline on its own;
+//  - functions with 13..16 variables run tile-parallel: five launches shared
+//    by all of them (tiles of the truth table, the column of digits 13..n in
+//    registers, the final reduce of every tile with its summary, the per-
+//    function scan of the tile counts, the ordered list), each launch a flat
+//    range of work items over all the functions.
+// No workgroup ever waits on another, and every launch can be captured in a
+// graph.
 #include "launch.h"
 #include "tile_ops.h"
 
@@ -71,72 +75,25 @@ __device__ __forceinline__ void batch_column(uint32_t *state, uint32_t l)
     });
 }
 
-// Make this workgroup's state writes visible to its own later reads by other
-// threads (through L1/L2) before the next phase starts.
-__device__ __forceinline__ void phase_barrier()
-{
-    __threadfence();
-    __syncthreads();
-}
-
+// A whole function with n <= 12 in one LDS tile.
 __device__ void batch_job(const BatchJob &j, uint32_t *t, uint64_t *sh)
 {
     const int n = j.n;
-    if (n <= 12) {
-        const int lw = n <= 3 ? 0 : n - 3;
-        const uint32_t tw = (uint32_t)pow3(lw);
-        tile_from_tt(t, j.tt, n, lw, tw, 0);
-        lds_all_digits<true>(t, tw, lw);
-        for (uint32_t w = threadIdx.x; w < tw; w += blockDim.x) t[w] = inword_reduce(t[w]);
-        __syncthreads();
-        lds_all_digits<false>(t, tw, lw);
-        for (uint32_t w = threadIdx.x; w < tw; w += blockDim.x) j.state[w] = t[w];
-        const uint64_t total = tile_list(t, tw, n, 0, j.list, j.cap, 0, sh);
-        if (threadIdx.x == 0) *j.count = total;
-        return;
-    }
-    const int H = n - 12;
-    const uint32_t tw = kTileL;
-    // 1. tiles with binary digits 13..n: load and merge digits 1..12
-    for (uint64_t bh = 0; bh < (1ull << H); ++bh) {
-        tile_from_tt(t, j.tt, n, 9, tw, bh);
-        lds_all_digits<true>(t, tw, 9);
-        uint64_t tile = 0;
-        for (int q = 0; q < H; ++q)
-            if ((bh >> q) & 1) tile += pow3(q);
-        uint32_t *dst = j.state + tile * tw;
-        for (uint32_t w = threadIdx.x; w < tw; w += blockDim.x) dst[w] = t[w];
-        __syncthreads();
-    }
-    phase_barrier();
-    // 2. digits 13..n: merge, then reduce
-    for (uint32_t l0 = 0; l0 < kTileL; l0 += blockDim.x) {
-        const uint32_t l = l0 + threadIdx.x;
-        switch (H) {
-        case 1: batch_column<1>(j.state, l); break;
-        case 2: batch_column<2>(j.state, l); break;
-        case 3: batch_column<3>(j.state, l); break;
-        default: batch_column<4>(j.state, l); break;
-        }
-    }
-    phase_barrier();
-    // 3. every tile: reduce digits 1..12, write the primes, list them in order
-    uint64_t run = 0;
-    const uint64_t ntiles = pow3(H);
-    for (uint64_t tile = 0; tile < ntiles; ++tile) {
-        uint32_t *src = j.state + tile * tw;
-        load_tile<true, kBatchThreads>(t, src, tw);
-        __syncthreads();
-        lds_all_digits<false>(t, tw, 9);
-        store_tile<kBatchThreads>(src, t, tw);
-        run += tile_list(t, tw, n, tile * tw, j.list, j.cap, run, sh);
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) *j.count = run;
+    const int lw = n <= 3 ? 0 : n - 3;
+    const uint32_t tw = (uint32_t)pow3(lw);
+    tile_from_tt(t, j.tt, n, lw, tw, 0);
+    lds_all_digits<true>(t, tw, lw);
+    for (uint32_t w = threadIdx.x; w < tw; w += blockDim.x) t[w] = inword_reduce(t[w]);
+    __syncthreads();
+    lds_all_digits<false>(t, tw, lw);
+    for (uint32_t w = threadIdx.x; w < tw; w += blockDim.x) j.state[w] = t[w];
+    const uint64_t total = tile_list(t, tw, n, 0, j.list, j.cap, 0, sh);
+    if (threadIdx.x == 0) *j.count = total;
 }
 
-__global__ __launch_bounds__(kBatchThreads) void batch_kernel(const BatchJob *jobs, const uint32_t *order,
-                                                              uint32_t njobs, uint32_t *ticket)
+// Two workgroups per CU (the LDS tile allows two; registers are held to 80).
+__global__ __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per_eu(6)))
+void batch_kernel(const BatchJob *jobs, const uint32_t *order, uint32_t njobs, uint32_t *ticket)
 {
     extern __shared__ uint32_t t[];
     __shared__ uint64_t sh[kBatchThreads / 64];
@@ -152,10 +109,110 @@ __global__ __launch_bounds__(kBatchThreads) void batch_kernel(const BatchJob *jo
     }
 }
 
+// --- tile-parallel path (13 <= n <= 16) -------------------------------------
+
+constexpr uint32_t kColThreads = 256;
+constexpr uint32_t kColBlocks = (kTileL + kColThreads - 1) / kColThreads;  // per function
+
+// 1. Tiles whose digits 13..n are binary: from the truth table, merged over
+//    digits 1..12, to the state.
+__global__ __launch_bounds__(256) void tb_merge_tt_kernel(TileBatch b)
+{
+    extern __shared__ uint32_t t[];
+    const uint32_t item = blockIdx.x;
+    const TileJob &j = b.jobs[b.bin_job[item]];
+    const uint64_t bh = item - j.first_bin;
+    tile_from_tt(t, j.tt, j.n, 9, kTileL, bh);
+    lds_all_digits<true>(t, kTileL, 9);
+    uint64_t tile = 0;
+    for (int q = 0; q < j.n - 12; ++q)
+        if ((bh >> q) & 1) tile += pow3(q);
+    uint32_t *dst = j.state + tile * kTileL;
+    for (uint32_t w = threadIdx.x; w < kTileL; w += blockDim.x) dst[w] = t[w];
+}
+
+// 2. Digits 13..n of every column l (merge, then reduce, in registers).
+__global__ __launch_bounds__(kColThreads) void tb_column_kernel(TileBatch b)
+{
+    const uint32_t jid = blockIdx.x / kColBlocks;
+    const uint32_t l = (blockIdx.x % kColBlocks) * kColThreads + threadIdx.x;
+    const TileJob &j = b.jobs[jid];
+    switch (j.n - 12) {
+    case 1: batch_column<1>(j.state, l); break;
+    case 2: batch_column<2>(j.state, l); break;
+    case 3: batch_column<3>(j.state, l); break;
+    default: batch_column<4>(j.state, l); break;
+    }
+}
+
+// 3. Every tile: reduce digits 1..12 (the prime bitmap) and its summary.
+__global__ __launch_bounds__(768) void tb_reduce_kernel(TileBatch b)
+{
+    extern __shared__ uint32_t t[];
+    __shared__ uint32_t red[kMapWords + 1];
+    const uint32_t tile = blockIdx.x;
+    const TileJob &j = b.jobs[b.tile_job[tile]];
+    reduce_full_tile(t, j.state + (uint64_t)(tile - j.first_tile) * kTileL, b.counts + tile,
+                     b.chunkmap + (uint64_t)tile * kMapWords, red);
+}
+
+// 4. One wavefront per function: exclusive scan of its tile counts into list
+//    offsets, and its prime count.
+__global__ __launch_bounds__(256) void tb_scan_kernel(TileBatch b)
+{
+    const uint32_t jid = blockIdx.x * 4 + threadIdx.x / 64;
+    if (jid >= b.njobs) return;
+    const TileJob &j = b.jobs[jid];
+    const uint32_t nt = (uint32_t)pow3(j.n - 12), lane = lane_id();
+    uint64_t run = 0;
+    for (uint32_t base = 0; base < nt; base += 64) {
+        const uint32_t k = base + lane;
+        const uint32_t c = k < nt ? b.counts[j.first_tile + k] : 0u;
+        const uint32_t inc = wave_inclusive_scan32(c);
+        if (k < nt) b.offs[j.first_tile + k] = run + (inc - c);
+        run += __shfl(inc, 63, 64);
+    }
+    if (lane == 0) *j.count = run;
+}
+
+// 5. One wavefront per tile: its primes, in order, into its function's list.
+__global__ __launch_bounds__(256) void tb_list_kernel(TileBatch b)
+{
+    __shared__ uint16_t nzs[4][kTileChunks];
+    const uint32_t tile = blockIdx.x * 4 + threadIdx.x / 64;
+    if (tile >= b.ntiles) return;
+    const TileJob &j = b.jobs[b.tile_job[tile]];
+    const uint32_t c = b.counts[tile];
+    const uint64_t off = b.offs[tile];
+    if (j.list == nullptr || c == 0 || off >= j.cap) return;
+    const uint64_t local = tile - j.first_tile;
+    list_tile(j.state + local * kTileL, kTileL, true, local * kTileL, off, b.chunkmap + (uint64_t)tile * kMapWords,
+              j.list, j.cap, nzs[threadIdx.x / 64]);
+}
+
+hipError_t launch_tile_batch(const TileBatch &b, hipStream_t s)
+{
+    if (b.njobs == 0) return hipSuccess;
+    const size_t lds = kTileL * sizeof(uint32_t);
+    hipLaunchKernelGGL(tb_merge_tt_kernel, dim3(b.nbin), dim3(256), lds, s, b);
+    hipLaunchKernelGGL(tb_column_kernel, dim3(b.njobs * kColBlocks), dim3(kColThreads), 0, s, b);
+    hipLaunchKernelGGL(tb_reduce_kernel, dim3(b.ntiles), dim3(768), lds, s, b);
+    hipLaunchKernelGGL(tb_scan_kernel, dim3((b.njobs + 3) / 4), dim3(256), 0, s, b);
+    hipLaunchKernelGGL(tb_list_kernel, dim3((b.ntiles + 3) / 4), dim3(256), 0, s, b);
+    return hipGetLastError();
+}
+
 hipError_t batch_setup()
 {
-    return hipFuncSetAttribute((const void *)batch_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)(kTileL * sizeof(uint32_t)));
+    const int lds = (int)(kTileL * sizeof(uint32_t));
+    hipError_t e;
+    if ((e = hipFuncSetAttribute((const void *)batch_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, lds)) !=
+        hipSuccess)
+        return e;
+    if ((e = hipFuncSetAttribute((const void *)tb_merge_tt_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 lds)) != hipSuccess)
+        return e;
+    return hipFuncSetAttribute((const void *)tb_reduce_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
 }
 
 hipError_t launch_batch(const BatchJob *jobs, const uint32_t *order, uint32_t njobs, uint32_t *ticket,

@@ -4,6 +4,7 @@
 // into list offsets, and the list pass reads only the non-zero chunks.
 #include "launch.h"
 #include "t27.h"
+#include "tile_ops.h"
 
 namespace dqmc {
 
@@ -113,66 +114,21 @@ struct ListArgs {
 };
 
 constexpr int kListThreads = 256;
-constexpr int kListBatch = 16;  // chunks whose words are loaded together
 
-// One wavefront per tile (grid-stride over tiles).  The non-zero chunks of
-// the tile are listed in order from its chunk map; their words are loaded
-// kListBatch chunks at a time, and each chunk's set bits are written at the
-// tile offset plus the running count (word-major, then bit).
+// One wavefront per tile (grid-stride over tiles).
 __global__ __launch_bounds__(kListThreads) void list_kernel(ListArgs a)
 {
     constexpr int NW = kListThreads / 64;
     __shared__ uint16_t nzs[NW][kTileChunks];
-    const uint32_t wv = threadIdx.x / 64, lane = lane_id();
-    uint16_t *nz = nzs[wv];
+    const uint32_t wv = threadIdx.x / 64;
     const bool words = a.n >= 3;
     const uint64_t nwaves = (uint64_t)gridDim.x * NW;
     for (uint64_t tile = (uint64_t)blockIdx.x * NW + wv; tile < a.ntiles; tile += nwaves) {
         const uint32_t c = a.counts[tile];
         const uint64_t off = a.offs[tile];
         if (c == 0 || off >= a.cap) continue;
-        // ordered list of the non-zero chunks
-        const uint32_t mw = lane < (uint32_t)kMapWords ? a.chunkmap[tile * kMapWords + lane] : 0u;
-        const uint32_t pc = __popc(mw);
-        const uint32_t incl = wave_inclusive_scan32(pc);
-        const uint32_t m = __shfl(incl, 63, 64);
-        uint32_t pos = incl - pc, bits = mw;
-        while (bits != 0u) {
-            const uint32_t b = __builtin_ctz(bits);
-            bits &= bits - 1u;
-            nz[pos++] = (uint16_t)(lane * 32 + b);
-        }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        const uint32_t *src = a.state + tile * a.tw;
-        uint64_t run = off;
-        for (uint32_t r0 = 0; r0 < m && run < a.cap; r0 += kListBatch) {
-            uint32_t v[kListBatch];
-            static_for<kListBatch>([&](auto ii) {
-                constexpr int i = decltype(ii)::value;
-                const uint32_t w = (r0 + i < m) ? (uint32_t)nz[r0 + i] * kChunkWords + lane : a.tw;
-                v[i] = w < a.tw ? src[w] : 0u;
-            });
-            static_for<kListBatch>([&](auto ii) {
-                constexpr int i = decltype(ii)::value;
-                if (r0 + i < m) {
-                    uint32_t x = v[i];
-                    const uint32_t cc = __popc(x);
-                    const uint32_t inc = wave_inclusive_scan32(cc);
-                    uint64_t p = run + (inc - cc);
-                    const uint64_t w = (uint64_t)nz[r0 + i] * kChunkWords + lane;
-                    const uint64_t rbase = words ? 27ull * (tile * a.tw + w) : 0ull;
-                    while (x != 0u && p < a.cap) {
-                        const uint32_t b = __builtin_ctz(x);
-                        x &= x - 1u;
-                        a.list[p++] = rbase + b;
-                    }
-                    run += __shfl(inc, 63, 64);
-                }
-            });
-        }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        __builtin_amdgcn_wave_barrier();  // nz is reused by the next tile
+        list_tile(a.state + tile * a.tw, a.tw, words, tile * a.tw, off, a.chunkmap + tile * kMapWords, a.list, a.cap,
+                  nzs[wv]);
     }
 }
 

@@ -74,19 +74,8 @@ __global__ __launch_bounds__(low_threads<MODE>()) void low_kernel(LowArgs a)
         const uint64_t tile = blockIdx.x;
         const uint32_t *src = a.state + tile * a.tw;
         if constexpr (MODE == kLowReduceCount) {
-            // always a full tile here (n > 12): digits 4..6, 7..9 in LDS,
-            // digits 10..12 in the last round, straight to HBM
-            if (threadIdx.x < kMapWords + 1) red[threadIdx.x] = 0;
-            load_tile<true, THREADS>(t, src, a.tw);
-            __syncthreads();
-            lds_group<3, false>(t, a.tw, 1);
-            __syncthreads();
-            lds_group<3, false>(t, a.tw, 27);
-            __syncthreads();
-            last_round_to_hbm(t, a.state + tile * a.tw, red);
-            __syncthreads();
-            if (threadIdx.x == 0) a.counts[tile] = red[0];
-            if (threadIdx.x < kMapWords) a.chunkmap[tile * kMapWords + threadIdx.x] = red[1 + threadIdx.x];
+            // always a full tile here (n > 12)
+            reduce_full_tile(t, a.state + tile * a.tw, a.counts + tile, a.chunkmap + tile * kMapWords, red);
             return;
         } else {
             load_tile<false, THREADS>(t, src, a.tw);

@@ -83,12 +83,65 @@ struct BatchJob {
     int32_t pad;
 };
 
-constexpr int kBatchMaxN = 16;  // larger functions of a batch take the single-function path
+constexpr int kBatchWholeMaxN = 12;  // one workgroup runs the whole function
+constexpr int kBatchTileMaxN = 16;   // tile-parallel; larger: the single-function path
 
 hipError_t batch_setup();
-// Persistent launch over njobs jobs in the given order (ticket zeroed first).
+// Persistent launch over njobs jobs (n <= kBatchWholeMaxN) in the given
+// order (ticket zeroed first).
 hipError_t launch_batch(const BatchJob *jobs, const uint32_t *order, uint32_t njobs, uint32_t *ticket,
                         uint32_t grid, hipStream_t s);
+
+// A function with 13 <= n <= kBatchTileMaxN of a batch, run tile-parallel.
+// Its 2^(n-12) tiles with binary digits 13..n are work items first_bin..,
+// its 3^(n-12) tiles are first_tile.. in the batch's per-tile arrays.
+struct TileJob {
+    const uint32_t *tt;
+    uint32_t *state;
+    uint64_t *list;
+    uint64_t cap;
+    uint64_t *count;
+    int32_t n;
+    uint32_t first_bin;
+    uint32_t first_tile;
+    uint32_t pad;
+};
+
+struct TileBatch {
+    const TileJob *jobs;
+    const uint32_t *bin_job;   // per binary-tile work item: its function
+    const uint32_t *tile_job;  // per tile: its function
+    uint32_t *counts;          // per tile: set bits of the prime bitmap
+    uint32_t *chunkmap;        // per tile: kMapWords words of non-zero chunks
+    uint64_t *offs;            // per tile: list offset within its function
+    uint32_t njobs;
+    uint32_t nbin;
+    uint32_t ntiles;
+};
+
+// The five launches of the tile-parallel batch path.
+hipError_t launch_tile_batch(const TileBatch &b, hipStream_t s);
+
+// Host: the work items of m functions with 13 <= n <= kBatchTileMaxN: fills
+// tj[0..m), bin_job (2^(n-12) entries per function) and tile_job (3^(n-12)
+// per function) and sets b.njobs, b.nbin, b.ntiles.
+inline void tile_layout(const BatchJob *jobs, uint32_t m, TileJob *tj, uint32_t *bin_job, uint32_t *tile_job,
+                        TileBatch &b)
+{
+    uint32_t nbin = 0, ntiles = 0;
+    for (uint32_t i = 0; i < m; ++i) {
+        const BatchJob &j = jobs[i];
+        const int h = j.n - 12;
+        tj[i] = TileJob{j.tt, j.state, j.list, j.cap, j.count, j.n, nbin, ntiles, 0};
+        for (uint32_t k = 0; k < (1u << h); ++k) bin_job[nbin++] = i;
+        uint32_t nt = 1;
+        for (int q = 0; q < h; ++q) nt *= 3;
+        for (uint32_t k = 0; k < nt; ++k) tile_job[ntiles++] = i;
+    }
+    b.njobs = m;
+    b.nbin = nbin;
+    b.ntiles = ntiles;
+}
 
 hipError_t launch_fill_u64(uint64_t *p, uint64_t count, uint64_t value, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint64_t count, uint32_t value, hipStream_t s);

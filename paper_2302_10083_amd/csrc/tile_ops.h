@@ -191,4 +191,80 @@ __device__ __forceinline__ void last_round_to_hbm(uint32_t *t, uint32_t *dst, ui
     if (lane_id() == 0 && c != 0) atomicAdd(&red[0], c);
 }
 
+// Final Reduce of a full tile in HBM (3^9 words at `tile`, 768 threads):
+// digits 1..3 on the way into LDS, digits 4..6 and 7..9 in LDS, digits
+// 10..12 in the last round straight back to HBM (the prime bitmap), and the
+// tile summary: *count = its set bits, map[0..kMapWords) = its non-zero
+// 64-word chunks.  `red` is kMapWords + 1 words of LDS.
+__device__ __forceinline__ void reduce_full_tile(uint32_t *t, uint32_t *tile, uint32_t *count, uint32_t *map,
+                                                 uint32_t *red)
+{
+    if (threadIdx.x < kMapWords + 1) red[threadIdx.x] = 0;
+    load_tile<true, 768>(t, tile, kMaxTileWords);
+    __syncthreads();
+    lds_group<3, false>(t, kMaxTileWords, 1);
+    __syncthreads();
+    lds_group<3, false>(t, kMaxTileWords, 27);
+    __syncthreads();
+    last_round_to_hbm(t, tile, red);
+    __syncthreads();
+    if (threadIdx.x == 0) *count = red[0];
+    if (threadIdx.x < kMapWords) map[threadIdx.x] = red[1 + threadIdx.x];
+}
+
+// Ordered list of the set bits of one tile of a bitmap in HBM, by one
+// wavefront: the tile's non-zero chunks (bit k of map = chunk k, from the
+// tile summary) are listed in order, their words are loaded kListBatch chunks
+// at a time, and each chunk's set bits are written at `off` plus the running
+// count (word-major, then bit) as cube indices 27 * (wbase + word) + bit
+// (with words == false, a one-word state: bit b is cube b).  Entries at or
+// past cap are dropped.  nz holds kTileChunks entries private to the wave.
+constexpr int kListBatch = 16;  // chunks whose words are loaded together
+
+__device__ __forceinline__ void list_tile(const uint32_t *src, uint32_t tw, bool words, uint64_t wbase, uint64_t off,
+                                          const uint32_t *map, uint64_t *list, uint64_t cap, uint16_t *nz)
+{
+    const uint32_t lane = lane_id();
+    const uint32_t mw = lane < (uint32_t)kMapWords ? map[lane] : 0u;
+    const uint32_t pc = __popc(mw);
+    const uint32_t incl = wave_inclusive_scan32(pc);
+    const uint32_t m = __shfl(incl, 63, 64);
+    uint32_t pos = incl - pc, bits = mw;
+    while (bits != 0u) {
+        const uint32_t b = __builtin_ctz(bits);
+        bits &= bits - 1u;
+        nz[pos++] = (uint16_t)(lane * 32 + b);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    uint64_t run = off;
+    for (uint32_t r0 = 0; r0 < m && run < cap; r0 += kListBatch) {
+        uint32_t v[kListBatch];
+        static_for<kListBatch>([&](auto ii) {
+            constexpr int i = decltype(ii)::value;
+            const uint32_t w = (r0 + i < m) ? (uint32_t)nz[r0 + i] * kChunkWords + lane : tw;
+            v[i] = w < tw ? src[w] : 0u;
+        });
+        static_for<kListBatch>([&](auto ii) {
+            constexpr int i = decltype(ii)::value;
+            if (r0 + i < m) {
+                uint32_t x = v[i];
+                const uint32_t cc = __popc(x);
+                const uint32_t inc = wave_inclusive_scan32(cc);
+                uint64_t p = run + (inc - cc);
+                const uint64_t w = (uint64_t)nz[r0 + i] * kChunkWords + lane;
+                const uint64_t rbase = words ? 27ull * (wbase + w) : 0ull;
+                while (x != 0u && p < cap) {
+                    const uint32_t b = __builtin_ctz(x);
+                    x &= x - 1u;
+                    list[p++] = rbase + b;
+                }
+                run += __shfl(inc, 63, 64);
+            }
+        });
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();  // nz is reused by the wave's next tile
+}
+
 }  // namespace dqmc
