@@ -246,6 +246,7 @@ def main():
     ap.add_argument("--tune-extra-groups", type=int, default=1,
                     help="pass plans with up to this many groups beyond the fewest are timed (autotuner)")
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--no-cnf", action="store_true")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -363,6 +364,27 @@ def main():
                                "sample": "%d uniformly random cubes of the same n=%d function, per-cube "
                                          "prime test (Sec. 2 definitions), %.1f s" % (len(rhos), n, el)}
         out["sample_parity"] = {"cubes": int(len(rhos)), "primes_in_sample": int(ref.sum()), "mismatches": mism}
+    if not args.no_cnf:
+        # CNF of a sparse function: the primes of its complement, with the
+        # complement taken as the table is loaded (DQMC_NEGATE).  The sparse
+        # function here is NOT f, so its CNF clauses are f's primes.
+        sparse = ~np.asarray(tt, dtype=np.uint32)
+        sd = ctx.tt_to_device(sparse)
+        for _ in range(args.warmup):
+            dqmc.dqmc_primes_ex(ctx.ctx, n, sd, dqmc.DQMC_NEGATE, state, lst, nprimes, count)
+        torch.cuda.synchronize()
+        start.record()
+        for _ in range(args.steps):
+            dqmc.dqmc_primes_ex(ctx.ctx, n, sd, dqmc.DQMC_NEGATE, state, lst, nprimes, count)
+        end.record()
+        torch.cuda.synchronize()
+        ms_cnf = start.elapsed_time(end) / args.steps
+        out["cnf"] = {"workload": "CNF of NOT(%s) (density %.4f): primes of its complement" %
+                                  (args.workload, float(np.unpackbits(sparse.view(np.uint8)).mean())),
+                      "ms": ms_cnf, "cubes_per_s": cubes / (ms_cnf / 1e3), "clauses": int(count.item()),
+                      "clauses_equal_dnf_primes": int(count.item()) == nprimes}
+        del sd
+        print("bench: cnf %.2f ms" % ms_cnf, file=sys.stderr, flush=True)
     if not args.no_batch:
         del lst, state
         torch.cuda.empty_cache()

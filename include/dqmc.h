@@ -102,6 +102,20 @@ int dqmc_implicants(dqmc_ctx *ctx, int n, const uint32_t *d_tt, uint32_t *d_stat
 int dqmc_primes(dqmc_ctx *ctx, int n, const uint32_t *d_tt, uint32_t *d_state, uint64_t *d_list,
                 uint64_t list_cap, uint64_t *d_count, void *stream);
 
+/* Complement mode (Sec. 1, "New method": the primes of a function give its
+ * DNF, the primes of its complement give its CNF; the dense method suits the
+ * CNF of a sparse function).  With flags = DQMC_NEGATE the truth table is
+ * complemented as it is loaded: the results are those of dqmc_implicants /
+ * dqmc_primes for NOT f, without a complemented copy of the table.  Each
+ * prime implicant s of NOT f is the prime clause of f that ORs, for every
+ * digit s_i != *, the literal x_i if s_i = 0 and NOT x_i if s_i = 1.
+ * flags = 0 is the plain call.  Other bits: DQMC_EINVAL.  Arguments and
+ * errors otherwise as dqmc_implicants / dqmc_primes. */
+#define DQMC_NEGATE 1u
+int dqmc_implicants_ex(dqmc_ctx *ctx, int n, const uint32_t *d_tt, uint32_t flags, uint32_t *d_state, void *stream);
+int dqmc_primes_ex(dqmc_ctx *ctx, int n, const uint32_t *d_tt, uint32_t flags, uint32_t *d_state, uint64_t *d_list,
+                   uint64_t list_cap, uint64_t *d_count, void *stream);
+
 /* Extraction alone (Alg. 4, output step): every set bit of a state bitmap,
  * as increasing cube indices.  Same list/capacity/count rules as
  * dqmc_primes; d_state is read only. */

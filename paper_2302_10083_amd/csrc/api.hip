@@ -149,11 +149,12 @@ ColArgs col_args(uint32_t *state, int n, const Group &g, bool outer_binary)
 }
 
 // Steps 1-2 (and the top group's merge when reduce == false).
-int enqueue_merge(dqmc_ctx *ctx, int n, const uint32_t *tt, uint32_t *state, bool fuse_top_reduce,
+int enqueue_merge(dqmc_ctx *ctx, int n, const uint32_t *tt, uint32_t flip, uint32_t *state, bool fuse_top_reduce,
                   hipStream_t s)
 {
     LowArgs a = low_args(ctx, n);
     a.tt = tt;
+    a.flip = flip;
     a.state = state;
     const double S = state_bytes(n);
     const double binfrac_high = std::pow(2.0 / 3.0, n - kLowDigits);
@@ -260,26 +261,42 @@ const char *dqmc_last_error(const dqmc_ctx *ctx) { return ctx ? ctx->err : "no c
 
 int dqmc_implicants(dqmc_ctx *ctx, int n, const uint32_t *d_tt, uint32_t *d_state, void *stream)
 {
+    return dqmc_implicants_ex(ctx, n, d_tt, 0u, d_state, stream);
+}
+
+int dqmc_implicants_ex(dqmc_ctx *ctx, int n, const uint32_t *d_tt, uint32_t flags, uint32_t *d_state, void *stream)
+{
     int rc = check_common(ctx, n);
     if (rc != DQMC_OK) return rc;
+    if ((flags & ~(uint32_t)DQMC_NEGATE) != 0u) return fail(ctx, DQMC_EINVAL, "%s", "unknown flag bits");
+    const uint32_t flip = (flags & DQMC_NEGATE) ? ~0u : 0u;
     if (d_tt == nullptr || d_state == nullptr) return fail(ctx, DQMC_EINVAL, "%s", "NULL truth table or state");
     if (!aligned(d_tt, 4) || !aligned(d_state, 4)) return fail(ctx, DQMC_EINVAL, "%s", "misaligned buffer");
     hipStream_t s = (hipStream_t)stream;
     if (n <= kLowDigits) {
         LowArgs a = low_args(ctx, n);
         a.tt = d_tt;
+        a.flip = flip;
         a.state = d_state;
         return run_pass(ctx, s, "low_merge_tt", n, tt_bytes(n) + state_bytes(n), 0,
                         [&] { return launch_low(kLowMergeTT, a, 1, s); });
     }
-    return enqueue_merge(ctx, n, d_tt, d_state, false, s);
+    return enqueue_merge(ctx, n, d_tt, flip, d_state, false, s);
 }
 
 int dqmc_primes(dqmc_ctx *ctx, int n, const uint32_t *d_tt, uint32_t *d_state, uint64_t *d_list,
                 uint64_t list_cap, uint64_t *d_count, void *stream)
 {
+    return dqmc_primes_ex(ctx, n, d_tt, 0u, d_state, d_list, list_cap, d_count, stream);
+}
+
+int dqmc_primes_ex(dqmc_ctx *ctx, int n, const uint32_t *d_tt, uint32_t flags, uint32_t *d_state, uint64_t *d_list,
+                   uint64_t list_cap, uint64_t *d_count, void *stream)
+{
     int rc = check_common(ctx, n);
     if (rc != DQMC_OK) return rc;
+    if ((flags & ~(uint32_t)DQMC_NEGATE) != 0u) return fail(ctx, DQMC_EINVAL, "%s", "unknown flag bits");
+    const uint32_t flip = (flags & DQMC_NEGATE) ? ~0u : 0u;
     if (d_tt == nullptr || d_state == nullptr || d_count == nullptr)
         return fail(ctx, DQMC_EINVAL, "%s", "NULL truth table, state or count");
     if (!aligned(d_tt, 4) || !aligned(d_state, 4) || !aligned(d_count, 8) || !aligned(d_list, 8))
@@ -288,6 +305,7 @@ int dqmc_primes(dqmc_ctx *ctx, int n, const uint32_t *d_tt, uint32_t *d_state, u
     if (n <= kLowDigits) {
         LowArgs a = low_args(ctx, n);
         a.tt = d_tt;
+        a.flip = flip;
         a.state = d_state;
         a.list = d_list;
         a.cap = d_list ? list_cap : 0;
@@ -295,7 +313,7 @@ int dqmc_primes(dqmc_ctx *ctx, int n, const uint32_t *d_tt, uint32_t *d_state, u
         return run_pass(ctx, s, "low_primes_tt", n, tt_bytes(n) + state_bytes(n), d_list ? 8 : 0,
                         [&] { return launch_low(kLowPrimesTT, a, 1, s); });
     }
-    rc = enqueue_merge(ctx, n, d_tt, d_state, true, s);
+    rc = enqueue_merge(ctx, n, d_tt, flip, d_state, true, s);
     if (rc != DQMC_OK) return rc;
     const std::vector<Group> gs = groups_of(plan_sizes(ctx, n));
     for (int j = (int)gs.size() - 2; j >= 0; --j) {

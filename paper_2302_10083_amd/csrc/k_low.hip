@@ -53,7 +53,7 @@ __global__ __launch_bounds__(low_threads<MODE>()) void low_kernel(LowArgs a)
     if constexpr (MODE == kLowMergeTT || MODE == kLowPrimesTT) {
         // tile with binary digits 13..n given by the bits of blockIdx.x
         const uint64_t bh = blockIdx.x;
-        tile_from_tt(t, a.tt, a.n, a.lw, a.tw, bh);
+        tile_from_tt(t, a.tt, a.n, a.lw, a.tw, bh, a.flip);
         lds_all_digits<true>(t, a.tw, a.lw);
         uint64_t tile = 0;
         for (int j = 0, nh = a.n - 12; j < nh; ++j)

@@ -33,6 +33,7 @@ struct LowArgs {
     uint32_t tw;        // words per tile
     int n;
     int lw;             // word digits inside a tile (tw = 3^lw)
+    uint32_t flip;      // XOR applied to the truth-table words (~0u: complement)
 };
 
 constexpr int kLowThreads = 256;

@@ -65,8 +65,10 @@ __device__ __forceinline__ void lds_all_digits(uint32_t *t, uint32_t tw, int lw)
 // Fill a tile from the truth table (Alg. 4, "Load input"): the word of every
 // group of 8 minterms (word digits all binary) gets those minterms placed at
 // their cubes and merged over digits 1..3; every other word starts at 0.
-// `bh` is the binary value of digits 13..n (the tile's high digits).
-__device__ __forceinline__ void tile_from_tt(uint32_t *t, const uint32_t *tt, int n, int lw, uint32_t tw, uint64_t bh)
+// `bh` is the binary value of digits 13..n (the tile's high digits).  The
+// truth-table words are XORed with `flip` first (~0u: the complement).
+__device__ __forceinline__ void tile_from_tt(uint32_t *t, const uint32_t *tt, int n, int lw, uint32_t tw, uint64_t bh,
+                                             uint32_t flip = 0u)
 {
     for (uint32_t w = threadIdx.x; w < tw; w += blockDim.x) t[w] = 0;
     __syncthreads();
@@ -74,7 +76,7 @@ __device__ __forceinline__ void tile_from_tt(uint32_t *t, const uint32_t *tt, in
     const uint32_t bytemask = n >= 3 ? 0xFFu : ((1u << (1u << n)) - 1u);
     for (uint32_t xm = threadIdx.x; xm < nb; xm += blockDim.x) {
         const uint64_t bi = (bh << lw) + xm;  // byte index = x >> 3
-        const uint32_t byte = (tt[bi >> 2] >> ((bi & 3) * 8)) & bytemask;
+        const uint32_t byte = ((tt[bi >> 2] ^ flip) >> ((bi & 3) * 8)) & bytemask;
         uint32_t w = 0, p = 1;
         for (int j = 0; j < lw; ++j, p *= 3) w += ((xm >> j) & 1u) * p;
         t[w] = inword_merge(expand_byte(byte));

@@ -45,6 +45,7 @@ class dqmc_pass_record(ctypes.Structure):
 
 DQMC_MAX_RECORDS = 64
 DQMC_MAX_PLAN_TRIALS = 64
+DQMC_NEGATE = 1
 
 
 class dqmc_result(ctypes.Structure):
@@ -103,6 +104,8 @@ def load():
             "dqmc_dense_words": (u64, [i32]),
             "dqmc_implicants": (i32, [vp, i32, vp, vp, vp]),
             "dqmc_primes": (i32, [vp, i32, vp, vp, vp, u64, vp, vp]),
+            "dqmc_implicants_ex": (i32, [vp, i32, vp, ctypes.c_uint32, vp, vp]),
+            "dqmc_primes_ex": (i32, [vp, i32, vp, ctypes.c_uint32, vp, vp, u64, vp, vp]),
             "dqmc_extract": (i32, [vp, i32, vp, vp, u64, vp, vp]),
             "dqmc_bitmap_to_dense": (i32, [vp, i32, vp, vp, vp]),
             "dqmc_primes_batch": (i32, [vp, ctypes.POINTER(dqmc_job), ctypes.c_int32, vp]),
@@ -233,6 +236,23 @@ def dqmc_primes(ctx, n, tt, state, lst, list_cap, count, stream=None) -> None:
         _ptr(state, "state", torch.int32, dqmc_state_words(n)),
         _ptr(lst, "list", torch.int64, cap), cap,
         _ptr(count, "count", torch.int64, 1), _stream(stream)))
+
+
+def dqmc_implicants_ex(ctx, n, tt, flags, state, stream=None) -> None:
+    import torch
+
+    _check(ctx, load().dqmc_implicants_ex(ctx, n, _ptr(tt, "tt", torch.int32, dqmc_tt_words(n)), int(flags),
+                                          _ptr(state, "state", torch.int32, dqmc_state_words(n)), _stream(stream)))
+
+
+def dqmc_primes_ex(ctx, n, tt, flags, state, lst, list_cap, count, stream=None) -> None:
+    import torch
+
+    cap = 0 if lst is None else int(list_cap)
+    _check(ctx, load().dqmc_primes_ex(ctx, n, _ptr(tt, "tt", torch.int32, dqmc_tt_words(n)), int(flags),
+                                      _ptr(state, "state", torch.int32, dqmc_state_words(n)),
+                                      _ptr(lst, "list", torch.int64, cap), cap,
+                                      _ptr(count, "count", torch.int64, 1), _stream(stream)))
 
 
 def dqmc_extract(ctx, n, state, lst, list_cap, count, stream=None) -> None:
@@ -490,21 +510,22 @@ class Context:
         dqmc_implicants(self.ctx, n, tt, state, stream)
         return state
 
-    def primes(self, n, tt, state=None, list_cap=None, stream=None):
+    def primes(self, n, tt, state=None, list_cap=None, stream=None, flags=0):
         """(state, list, count) device tensors; with list_cap None the list
-        has room for every possible prime of this call's count (two passes)."""
+        has room for every possible prime of this call's count (two passes).
+        flags=DQMC_NEGATE: the primes of the complement of the table."""
         import torch
 
         state = self.new_state(n) if state is None else state
         count = torch.zeros(1, dtype=torch.int64, device=self.torch_device)
         if list_cap is None:
-            dqmc_primes(self.ctx, n, tt, state, None, 0, count, stream)
+            dqmc_primes_ex(self.ctx, n, tt, flags, state, None, 0, count, stream)
             cap = int(count.item())
             lst = torch.empty(max(cap, 1), dtype=torch.int64, device=self.torch_device)
             dqmc_extract(self.ctx, n, state, lst, cap, count, stream)
             return state, lst[:cap], count
         lst = torch.empty(max(int(list_cap), 1), dtype=torch.int64, device=self.torch_device)
-        dqmc_primes(self.ctx, n, tt, state, lst, list_cap, count, stream)
+        dqmc_primes_ex(self.ctx, n, tt, flags, state, lst, list_cap, count, stream)
         return state, lst, count
 
     def extract(self, n, state, list_cap, stream=None):

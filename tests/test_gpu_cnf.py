@@ -1,0 +1,132 @@
+"""Complement mode (DQMC_NEGATE): the results equal the oracle's for the
+complemented truth table, and the plain calls on a complemented copy, bit for
+bit, from n = 0 to the full n = 24 workload."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2302_10083_amd import inputs
+
+from _gpu_common import context, dev_to_u32, log, t27_to_dense
+
+pytestmark = pytest.mark.gpu
+
+
+def _complement(n, tt):
+    c = ~np.asarray(tt, dtype=np.uint32)
+    if n < 5:
+        c &= np.uint32((1 << (1 << n)) - 1)
+    return c
+
+
+def _negated(n, tt):
+    import torch
+
+    from paper_2302_10083_amd import dqmc
+
+    ctx = context()
+    state, lst, count = ctx.primes(n, ctx.tt_to_device(tt), flags=dqmc.DQMC_NEGATE)
+    torch.cuda.synchronize()
+    return state, lst.cpu().numpy(), int(count.item())
+
+
+@pytest.mark.parametrize("n,kind,seed", [(0, "bern", 1), (1, "bern", 2), (2, "bern", 3), (3, "bern", 4),
+                                         (4, "bern", 5), (5, "bern", 6), (8, "bern", 7), (11, "dnf", 8),
+                                         (12, "bern", 9), (13, "dnf", 10), (15, "bern", 11), (17, "bern", 12),
+                                         (19, "dnf", 13)])
+def test_negate_vs_oracle(n, kind, seed):
+    """Sparse functions (their complements are dense): the CNF use case."""
+    if kind == "bern":
+        tt = inputs.bernoulli(n, 0.15, 3100 + seed)
+    else:
+        tt = _complement(n, inputs.dnf(n, 40, max(1, n // 3), max(1, n - 2), 3100 + seed))
+    state, lst, c = _negated(n, tt)
+    _, O, ref = oracle.primes(n, _complement(n, tt))
+    assert c == len(ref)
+    assert np.array_equal(lst, ref)
+    assert np.array_equal(t27_to_dense(n, dev_to_u32(state)), O)
+
+
+@pytest.mark.parametrize("n", [6, 12, 14, 18])
+def test_implicants_negate_vs_oracle(n):
+    import torch
+
+    from paper_2302_10083_amd import dqmc
+
+    ctx = context()
+    tt = inputs.bernoulli(n, 0.1, 3300 + n)
+    state = ctx.new_state(n)
+    dqmc.dqmc_implicants_ex(ctx.ctx, n, ctx.tt_to_device(tt), dqmc.DQMC_NEGATE, state)
+    torch.cuda.synchronize()
+    M = oracle.enum_M(n, _complement(n, tt))
+    assert np.array_equal(t27_to_dense(n, dev_to_u32(state)), M)
+
+
+def test_negate_bad_flags():
+    import torch
+
+    from paper_2302_10083_amd import dqmc
+
+    ctx = context()
+    n = 10
+    ttd = ctx.tt_to_device(inputs.bernoulli(n, 0.5, 1))
+    count = torch.zeros(1, dtype=torch.int64, device=ctx.torch_device)
+    for flags in (2, 0x80000000, 3):
+        with pytest.raises(dqmc.DqmcError) as e:
+            dqmc.dqmc_primes_ex(ctx.ctx, n, ttd, flags, ctx.new_state(n), None, 0, count)
+        assert e.value.code == dqmc.DQMC_EINVAL
+        with pytest.raises(dqmc.DqmcError):
+            dqmc.dqmc_implicants_ex(ctx.ctx, n, ttd, flags, ctx.new_state(n))
+
+
+def test_negate_n24_equals_complemented_table():
+    """The n = 24 workload in complement mode against the plain call on a
+    complemented copy (state hash, count, list), plus sampled cubes against
+    the oracle's per-cube definition on the complement."""
+    import torch
+
+    from paper_2302_10083_amd import dqmc
+
+    ctx = context()
+    n = 24
+    tt = inputs.config("c3_n24_dnf2000_noise")
+    comp = _complement(n, tt)
+
+    def run(table, flags):
+        state = ctx.new_state(n)
+        count = torch.zeros(1, dtype=torch.int64, device=ctx.torch_device)
+        ttd = ctx.tt_to_device(table)
+        dqmc.dqmc_primes_ex(ctx.ctx, n, ttd, flags, state, None, 0, count)
+        torch.cuda.synchronize()
+        c = int(count.item())
+        lst = torch.empty(max(c, 1), dtype=torch.int64, device=ctx.torch_device)
+        dqmc.dqmc_primes_ex(ctx.ctx, n, ttd, flags, state, lst, c, count)
+        h = torch.zeros(1, dtype=torch.int64, device=ctx.torch_device)
+        dqmc.dqmc_hash_words(ctx.ctx, state, state.numel(), h)
+        hl = torch.zeros(1, dtype=torch.int64, device=ctx.torch_device)
+        dqmc.dqmc_hash_words(ctx.ctx, lst, 2 * c, hl)
+        torch.cuda.synchronize()
+        pick = np.random.default_rng(7).integers(0, max(c, 1), size=min(c, 4000))
+        listed = lst[torch.from_numpy(pick).to(lst.device)].cpu().numpy() if c else np.zeros(0, np.int64)
+        return state, c, int(h.item()), int(hl.item()), listed
+
+    log("n=24 negate")
+    s1, c1, h1, l1, listed = run(tt, dqmc.DQMC_NEGATE)
+    # listed cubes are primes of the complement by the per-cube definition
+    ok, _ = oracle.sample(n, comp, listed.astype(np.uint64), "prime")
+    assert c1 > 0 and ok.all()
+    rng = np.random.default_rng(2424)
+    rhos = rng.integers(0, 3**n, size=200_000, dtype=np.int64)
+    r = torch.from_numpy(rhos).to(s1.device)
+    got = ((s1[torch.div(r, 27, rounding_mode="floor")].to(torch.int64) >> torch.remainder(r, 27)) & 1)
+    got = got.cpu().numpy().astype(bool)
+    want, _ = oracle.sample(n, comp, rhos.astype(np.uint64), "prime")
+    assert np.array_equal(got, want.astype(bool))
+    del s1, r
+    torch.cuda.empty_cache()
+    log("n=24 plain on the complemented copy")
+    s2, c2, h2, l2, _ = run(comp, 0)
+    del s2
+    torch.cuda.empty_cache()
+    assert (c1, h1, l1) == (c2, h2, l2)
+    log("n=24 negate: %d primes" % c1)

@@ -356,3 +356,42 @@ def test_sample_matches_bitmaps():
     Os, Ms = oracle.bitmap_to_set(n, O), oracle.bitmap_to_set(n, M)
     assert [bool(int(r) in Os) for r in rhos] == pr.tolist()
     assert [bool(int(r) in Ms) for r in rhos] == im.tolist()
+
+
+# --- complement mode (Sec. 1, "New method": primes of NOT f give f's CNF) ---
+
+def _complement(n, tt):
+    c = ~np.asarray(tt, dtype=np.uint32)
+    if n < 5:
+        c &= np.uint32((1 << (1 << n)) - 1)
+    return c
+
+
+def test_cnf_of_and2_golden():
+    """f = x1 AND x2: NOT f = NOT x1 OR NOT x2 has the primes 0* and *0, the
+    clauses x1 and x2 of f's CNF."""
+    tt = np.array([0b1000], dtype=np.uint32)  # f(x) = 1 only at x = 3
+    _, _, lst = oracle.primes(2, _complement(2, tt))
+    assert [oracle.string_of(2, int(r)) for r in lst] == ["*0", "0*"]
+    assert list(lst) == [oracle.rho_of("*0"), oracle.rho_of("0*")] == [2, 6]
+
+
+@pytest.mark.parametrize("n,p,seed", [(3, 0.7, 1), (5, 0.8, 2), (7, 0.9, 3), (8, 0.95, 4), (9, 0.3, 5)])
+def test_cnf_clauses_reproduce_f(n, p, seed):
+    """Every prime s of NOT f gives the clause 'x is not covered by s'; f is
+    the AND of these clauses (they are implied by f, and the primes of NOT f
+    cover every zero of f)."""
+    tt = inputs.bernoulli(n, p, seed)
+    _, _, lst = oracle.primes(n, _complement(n, tt))
+    f = np.array([(int(tt[x >> 5]) >> (x & 31)) & 1 for x in range(1 << n)], dtype=bool)
+    conj = np.ones(1 << n, dtype=bool)
+    for r in lst:
+        s = oracle.string_of(n, int(r))
+        covered = np.ones(1 << n, dtype=bool)
+        xs = np.arange(1 << n)
+        for i, ch in enumerate(s):
+            if ch != "*":
+                covered &= ((xs >> i) & 1) == int(ch)
+        assert not np.any(covered & f), "a clause of f is violated by a true point"
+        conj &= ~covered
+    assert np.array_equal(conj, f)
