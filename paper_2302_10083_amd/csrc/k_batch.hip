@@ -116,7 +116,7 @@ constexpr uint32_t kColBlocks = (kTileL + kColThreads - 1) / kColThreads;  // pe
 
 // 1. Tiles whose digits 13..n are binary: from the truth table, merged over
 //    digits 1..12, to the state.
-__global__ __launch_bounds__(256) void tb_merge_tt_kernel(TileBatch b)
+__global__ __launch_bounds__(kBatchThreads) void tb_merge_tt_kernel(TileBatch b)
 {
     extern __shared__ uint32_t t[];
     const uint32_t item = blockIdx.x;
@@ -132,7 +132,7 @@ __global__ __launch_bounds__(256) void tb_merge_tt_kernel(TileBatch b)
 }
 
 // 2. Digits 13..n of every column l (merge, then reduce, in registers).
-__global__ __launch_bounds__(kColThreads) void tb_column_kernel(TileBatch b)
+__global__ __launch_bounds__(kColThreads) __attribute__((amdgpu_waves_per_eu(5))) void tb_column_kernel(TileBatch b)
 {
     const uint32_t jid = blockIdx.x / kColBlocks;
     const uint32_t l = (blockIdx.x % kColBlocks) * kColThreads + threadIdx.x;
@@ -194,7 +194,7 @@ hipError_t launch_tile_batch(const TileBatch &b, hipStream_t s)
 {
     if (b.njobs == 0) return hipSuccess;
     const size_t lds = kTileL * sizeof(uint32_t);
-    hipLaunchKernelGGL(tb_merge_tt_kernel, dim3(b.nbin), dim3(256), lds, s, b);
+    hipLaunchKernelGGL(tb_merge_tt_kernel, dim3(b.nbin), dim3(kBatchThreads), lds, s, b);
     hipLaunchKernelGGL(tb_column_kernel, dim3(b.njobs * kColBlocks), dim3(kColThreads), 0, s, b);
     hipLaunchKernelGGL(tb_reduce_kernel, dim3(b.ntiles), dim3(768), lds, s, b);
     hipLaunchKernelGGL(tb_scan_kernel, dim3((b.njobs + 3) / 4), dim3(256), 0, s, b);
