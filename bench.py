@@ -142,6 +142,66 @@ def bench_batch(ctx, reps=5):
                          "trials": [[t["grid"], t["order"], round(t["ms"], 3)] for t in trials]}}
 
 
+def bench_sparse(ctx, n=24, densities=(0.25, 0.5), reps=3):
+    """Sparse path (level-by-level QMC with hash sets) against the dense path
+    on random functions of the paper's Table 1 densities."""
+    import numpy as np
+    import torch
+
+    from paper_2302_10083_amd import dqmc, inputs
+
+    dev = ctx.torch_device
+    rows = []
+    for d in densities:
+        tt = inputs.bernoulli(n, d, 2400 + int(100 * d))
+        ttd = ctx.tt_to_device(tt)
+        count = torch.zeros(1, dtype=torch.int64, device=dev)
+        # size the workspace from a first run's report
+        work = torch.empty(8 << 30, dtype=torch.uint8, device=dev)
+        rc, lv, npr = dqmc.dqmc_sparse_primes(ctx.ctx, n, ttd, None, 0, count, work)
+        while rc != dqmc.DQMC_OK:
+            del work
+            torch.cuda.empty_cache()
+            work = torch.empty(dqmc.dqmc_sparse_workspace_bytes(n, 2 * lv, 2 * max(npr, 1)), dtype=torch.uint8,
+                               device=dev)
+            rc, lv, npr = dqmc.dqmc_sparse_primes(ctx.ctx, n, ttd, None, 0, count, work)
+        c = int(count.item())
+        lst = torch.empty(max(c, 1), dtype=torch.int64, device=dev)
+        dqmc.dqmc_sparse_primes(ctx.ctx, n, ttd, lst, c, count, work)
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            dqmc.dqmc_sparse_primes(ctx.ctx, n, ttd, lst, c, count, work)  # synchronous
+            times.append(time.perf_counter() - t0)
+        ms_sparse = 1e3 * min(times)
+        sh = torch.zeros(1, dtype=torch.int64, device=dev)
+        dqmc.dqmc_hash_words(ctx.ctx, lst, 2 * c, sh)
+        del work
+        torch.cuda.empty_cache()
+        # the dense path on the same function
+        state = ctx.new_state(n)
+        dl = torch.empty(max(c, 1), dtype=torch.int64, device=dev)
+        dqmc.dqmc_primes(ctx.ctx, n, ttd, state, dl, c, count)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            dqmc.dqmc_primes(ctx.ctx, n, ttd, state, dl, c, count)
+        b.record()
+        torch.cuda.synchronize()
+        ms_dense = a.elapsed_time(b) / reps
+        dh = torch.zeros(1, dtype=torch.int64, device=dev)
+        dqmc.dqmc_hash_words(ctx.ctx, dl, 2 * c, dh)
+        torch.cuda.synchronize()
+        rows.append({"density": d, "primes": c, "largest_level": lv, "ms_sparse": ms_sparse, "ms_dense": ms_dense,
+                     "same_list": int(sh.item()) == int(dh.item()) and int(count.item()) == c})
+        del state, dl, lst
+        torch.cuda.empty_cache()
+    return {"workload": "n=%d Bernoulli(d) truth tables (seeds 2400+100d), the paper's Table 1 densities" % n,
+            "rows": rows}
+
+
 def bench_serving(nreq=200, seed=25):
     """Serving mix (n in {10,14,18,22,25} with weights .4/.3/.15/.1/.05):
     saturation throughput from a closed loop, then Poisson arrivals at 0.5 and
@@ -247,6 +307,7 @@ def main():
                     help="pass plans with up to this many groups beyond the fewest are timed (autotuner)")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-cnf", action="store_true")
+    ap.add_argument("--no-sparse", action="store_true")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -385,9 +446,15 @@ def main():
                       "clauses_equal_dnf_primes": int(count.item()) == nprimes}
         del sd
         print("bench: cnf %.2f ms" % ms_cnf, file=sys.stderr, flush=True)
-    if not args.no_batch:
+    if not args.no_batch or not args.no_sparse:
         del lst, state
         torch.cuda.empty_cache()
+    if not args.no_sparse:
+        out["sparse"] = bench_sparse(ctx)
+        print("bench: sparse %s" % ", ".join("d=%.2f %.1f ms (dense %.1f ms)" % (r["density"], r["ms_sparse"],
+                                                                              r["ms_dense"])
+                                              for r in out["sparse"]["rows"]), file=sys.stderr, flush=True)
+    if not args.no_batch:
         out["batch"] = bench_batch(ctx)
         print("bench: batch %.2f ms (%.0f fns/s), per-function launches %.2f ms" % (
             out["batch"]["ms"], out["batch"]["fns_per_s"], out["batch"]["per_fn_launch_ms"]), file=sys.stderr, flush=True)

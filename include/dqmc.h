@@ -116,6 +116,33 @@ int dqmc_implicants_ex(dqmc_ctx *ctx, int n, const uint32_t *d_tt, uint32_t flag
 int dqmc_primes_ex(dqmc_ctx *ctx, int n, const uint32_t *d_tt, uint32_t flags, uint32_t *d_state, uint64_t *d_list,
                    uint64_t list_cap, uint64_t *d_count, void *stream);
 
+/* Sparse path (Sec. 5): the classic level-by-level Quine-McCluskey method
+ * (Alg. 1) with hash-based neighbour search, for functions of low density,
+ * where the number of implicants is far below 3^n.  Cubes are 2n-bit keys
+ * (Sec. 5, bit-based representation); each implicant is generated once, at
+ * its first star (Sec. 5, avoiding repeated generation); every level is a
+ * linear-probing hash set whose redundant entries are marked, never removed
+ * (Sec. 5, two-stage custom hash set).  The output is the same as
+ * dqmc_primes's list and count (no bitmap), for 0 <= n <= DQMC_SPARSE_MAX_N.
+ *   d_tt      device, dqmc_tt_words(n) words (2^(n-5) for n > 25 too).
+ *   d_list    device, room for list_cap uint64; may be NULL (count only).
+ *   d_count   device, one uint64.
+ *   d_work    device workspace of work_bytes (256-byte aligned), owned by the
+ *             caller: two levels (list + set), the prime keys and their
+ *             sorted copy, and the sort's scratch.
+ *   h_need    host uint64[2] or NULL: receives the largest level and the
+ *             number of primes seen, also when the workspace was too small;
+ *             dqmc_sparse_workspace_bytes(n, h_need[0], h_need[1]) is then
+ *             enough for a second call.
+ * The call is synchronous: it waits for the stream after every level (the
+ * level sizes decide the next launches).  Errors: DQMC_EINVAL (n, NULL,
+ * alignment), DQMC_ENOMEM (workspace too small; nothing is written to
+ * d_list/d_count), DQMC_EDEVICE. */
+#define DQMC_SPARSE_MAX_N 31
+uint64_t dqmc_sparse_workspace_bytes(int n, uint64_t max_level, uint64_t max_primes);
+int dqmc_sparse_primes(dqmc_ctx *ctx, int n, const uint32_t *d_tt, uint64_t *d_list, uint64_t list_cap,
+                       uint64_t *d_count, void *d_work, uint64_t work_bytes, uint64_t *h_need, void *stream);
+
 /* Extraction alone (Alg. 4, output step): every set bit of a state bitmap,
  * as increasing cube indices.  Same list/capacity/count rules as
  * dqmc_primes; d_state is read only. */

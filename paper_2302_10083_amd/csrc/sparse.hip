@@ -1,0 +1,419 @@
+// Sparse path: the classic level-by-level Quine-McCluskey algorithm with the
+// optimisations of Sec. 5 (Alg. 1 driven by hash-based neighbour search).
+//
+// A cube is a 2n-bit key, two bits per variable in string order (variable
+// x_{i+1} at bits 2i, 2i+1): 00 = 0, 01 = 1, 10 = * (Sec. 5, bit-based
+// representation).  Level w holds every implicant with w stars, as a compact
+// list (for sequential sweeps) and an open-addressing hash set with linear
+// probing (for neighbour lookups).  Step w:
+//   1. generation: an implicant c of level w-1 whose first star is at
+//      position f is merged only on positions p < f where c_p = 0, with its
+//      partner c[p <- 1] looked up in the set; u = c[p <- *] is appended to
+//      level w.  Every implicant of level w arises exactly once this way (at
+//      its first star), so the list needs no deduplication (Sec. 5, avoiding
+//      repeated implicant generation);
+//   2. the hash set of level w is built from the list;
+//   3. marking: for every u of level w and every star q of u, both halves
+//      u[q <- 0] and u[q <- 1] get the redundant control bit in the set of
+//      level w-1 (the extra pass over the new implicants of Sec. 5);
+//   4. the unmarked entries of level w-1 are its prime implicants
+//      (Sec. 5, two-stage custom hash set: elements are marked, never removed).
+// The primes are finally converted to cube indices rho and sorted, so the
+// output is the same list as the dense path's.
+#include <stdio.h>
+
+#include <algorithm>
+#include <rocprim/device/device_radix_sort.hpp>
+#include <vector>
+
+#include "api_types.h"
+#include "dqmc.h"
+#include "t27.h"
+
+namespace dqmc {
+
+constexpr uint64_t kEmpty = ~0ull;          // never a key: 11 is not a symbol
+constexpr uint64_t kRedundant = 1ull << 63;  // control bit of a stored key
+constexpr int kSpThreads = 256;
+
+__device__ __forceinline__ uint64_t sp_hash(uint64_t k)
+{
+    k = (k ^ (k >> 31)) * 0x7FB5D329728EA185ULL;
+    k = (k ^ (k >> 27)) * 0x81DADEF4BC2DD44DULL;
+    return k ^ (k >> 33);
+}
+
+// Minterm x (n <= 31 bits) -> key with pair 0b0v at each position.
+__device__ __forceinline__ uint64_t sp_spread(uint64_t x)
+{
+    x &= 0xFFFFFFFFull;
+    x = (x | (x << 16)) & 0x0000FFFF0000FFFFull;
+    x = (x | (x << 8)) & 0x00FF00FF00FF00FFull;
+    x = (x | (x << 4)) & 0x0F0F0F0F0F0F0F0Full;
+    x = (x | (x << 2)) & 0x3333333333333333ull;
+    x = (x | (x << 1)) & 0x5555555555555555ull;
+    return x;
+}
+
+__device__ __forceinline__ bool sp_find(const uint64_t *table, uint64_t mask, uint64_t key, uint64_t *slot)
+{
+    uint64_t h = sp_hash(key) & mask;
+    for (;;) {
+        const uint64_t v = table[h];
+        if (v == kEmpty) return false;
+        if ((v & ~kRedundant) == key) {
+            *slot = h;
+            return true;
+        }
+        h = (h + 1) & mask;
+    }
+}
+
+// Space for `mine` entries per thread, reserved with one atomic per
+// workgroup: returns this thread's first position.  Every thread of the
+// workgroup must call it (loops have workgroup-uniform trip counts).
+__device__ __forceinline__ uint64_t block_reserve(uint32_t mine, unsigned long long *counter)
+{
+    __shared__ uint32_t wsum[kSpThreads / 64];
+    __shared__ unsigned long long bbase;
+    const uint32_t wv = threadIdx.x / 64, lane = lane_id();
+    const uint32_t incl = wave_inclusive_scan32(mine);
+    if (lane == 63) wsum[wv] = incl;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t tot = 0;
+        for (int k = 0; k < kSpThreads / 64; ++k) tot += wsum[k];
+        bbase = tot ? atomicAdd(counter, (unsigned long long)tot) : 0ull;
+    }
+    __syncthreads();
+    uint64_t off = bbase + (incl - mine);
+    for (uint32_t k = 0; k < wv; ++k) off += wsum[k];
+    __syncthreads();  // wsum / bbase are reused by the next call
+    return off;
+}
+
+__device__ __forceinline__ void sp_put(uint64_t *out, uint64_t pos, uint64_t cap, uint64_t value,
+                                       unsigned int *overflow)
+{
+    if (pos < cap) out[pos] = value;
+    else atomicOr(overflow, 1u);
+}
+
+// Level 0: the support as keys.
+__global__ __launch_bounds__(kSpThreads) void sp_minterms_kernel(const uint32_t *tt, int n, uint64_t *out,
+                                                                 unsigned long long *counter, uint64_t cap,
+                                                                 unsigned int *overflow)
+{
+    const uint64_t nmin = 1ull << n;
+    const uint64_t nwords = (nmin + 31) / 32;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t total = (nwords + kSpThreads - 1) / kSpThreads * kSpThreads;  // workgroup-uniform trips
+    for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < total; w += stride) {
+        uint32_t bits = w < nwords ? tt[w] : 0u;
+        if (n < 5) bits &= (uint32_t)((1ull << nmin) - 1ull);
+        uint64_t pos = block_reserve((uint32_t)__popc(bits), counter);
+        while (bits != 0u) {
+            const uint32_t b = __builtin_ctz(bits);
+            bits &= bits - 1u;
+            sp_put(out, pos++, cap, sp_spread(w * 32 + b), overflow);
+        }
+    }
+}
+
+__global__ __launch_bounds__(kSpThreads) void sp_fill_kernel(uint64_t *p, uint64_t count)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) p[i] = kEmpty;
+}
+
+__global__ __launch_bounds__(kSpThreads) void sp_insert_kernel(const uint64_t *keys, uint64_t count,
+                                                               uint64_t *table, uint64_t mask)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) {
+        const uint64_t key = keys[i];
+        uint64_t h = sp_hash(key) & mask;
+        for (;;) {
+            const unsigned long long old =
+                atomicCAS((unsigned long long *)&table[h], (unsigned long long)kEmpty, (unsigned long long)key);
+            if (old == kEmpty || old == key) break;
+            h = (h + 1) & mask;
+        }
+    }
+}
+
+// Step 1: implicants of level w from the list of level w-1 (one thread per
+// implicant).
+__global__ __launch_bounds__(kSpThreads) void sp_generate_kernel(const uint64_t *prev, uint64_t count,
+                                                                 const uint64_t *table, uint64_t mask, int n,
+                                                                 uint64_t *out, unsigned long long *counter,
+                                                                 uint64_t cap, unsigned int *overflow)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t total = (count + kSpThreads - 1) / kSpThreads * kSpThreads;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+        const bool live = i < count;
+        const uint64_t c = live ? prev[i] : 0ull;
+        // first star: lowest position whose pair has its high bit set
+        const uint64_t stars = c & 0xAAAAAAAAAAAAAAAAull;
+        const int f = live ? (stars == 0 ? n : (__builtin_ctzll(stars) >> 1)) : 0;
+        uint32_t takes = 0;
+        for (int p = 0; p < f; ++p) {
+            uint64_t slot;
+            if (((c >> (2 * p)) & 3ull) == 0ull && sp_find(table, mask, c | (1ull << (2 * p)), &slot))
+                takes |= 1u << p;
+        }
+        uint64_t pos = block_reserve((uint32_t)__popc(takes), counter);
+        while (takes != 0u) {
+            const int p = __builtin_ctz(takes);
+            takes &= takes - 1u;
+            sp_put(out, pos++, cap, c | (2ull << (2 * p)), overflow);
+        }
+    }
+}
+
+// Step 3: both halves of every star of every new implicant are redundant.
+__global__ __launch_bounds__(kSpThreads) void sp_mark_kernel(const uint64_t *cur, uint64_t count, uint64_t *table,
+                                                             uint64_t mask, unsigned int *missing)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) {
+        const uint64_t u = cur[i];
+        uint64_t stars = u & 0xAAAAAAAAAAAAAAAAull;
+        while (stars != 0) {
+            const int q = __builtin_ctzll(stars) >> 1;
+            stars &= stars - 1ull;
+            const uint64_t h0 = u & ~(3ull << (2 * q)), h1 = h0 | (1ull << (2 * q));
+            uint64_t s0, s1;
+            if (sp_find(table, mask, h0, &s0)) atomicOr((unsigned long long *)&table[s0], (unsigned long long)kRedundant);
+            else atomicOr(missing, 1u);
+            if (sp_find(table, mask, h1, &s1)) atomicOr((unsigned long long *)&table[s1], (unsigned long long)kRedundant);
+            else atomicOr(missing, 1u);
+        }
+    }
+}
+
+// Step 4: unmarked entries of a level's set are prime.
+__global__ __launch_bounds__(kSpThreads) void sp_collect_kernel(const uint64_t *table, uint64_t size, uint64_t *out,
+                                                                unsigned long long *counter, uint64_t cap,
+                                                                unsigned int *overflow)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t total = (size + kSpThreads - 1) / kSpThreads * kSpThreads;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+        const uint64_t v = i < size ? table[i] : kEmpty;
+        const bool prime = v != kEmpty && (v & kRedundant) == 0ull;
+        const uint64_t pos = block_reserve(prime ? 1u : 0u, counter);
+        if (prime) sp_put(out, pos, cap, v, overflow);
+    }
+}
+
+// key -> rho = sum 3^i * symbol_i
+__global__ __launch_bounds__(kSpThreads) void sp_to_rho_kernel(uint64_t *keys, uint64_t count, int n)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) {
+        const uint64_t k = keys[i];
+        uint64_t r = 0;
+        for (int p = n - 1; p >= 0; --p) r = r * 3 + ((k >> (2 * p)) & 3ull);
+        keys[i] = r;
+    }
+}
+
+static uint32_t sp_grid(uint64_t items)
+{
+    uint64_t g = (items + kSpThreads - 1) / kSpThreads;
+    if (g > 16384) g = 16384;
+    return (uint32_t)(g == 0 ? 1 : g);
+}
+
+static uint64_t pow2_at_least(uint64_t x)
+{
+    uint64_t p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+}  // namespace dqmc
+
+using namespace dqmc;
+
+namespace {
+
+// Device counters of one call: [0] level count, [1] prime count,
+// [2] overflow flag, [3] missing-half flag (an internal error).
+struct SpCounters {
+    unsigned long long level;
+    unsigned long long primes;
+    unsigned int overflow;
+    unsigned int missing;
+};
+
+int sp_fail(dqmc_ctx *ctx, int code, const char *msg)
+{
+    snprintf(ctx->err, sizeof(ctx->err), "%s", msg);
+    return code;
+}
+
+}  // namespace
+
+extern "C" {
+
+uint64_t dqmc_sparse_workspace_bytes(int n, uint64_t max_level, uint64_t max_primes)
+{
+    if (n < 0 || n > DQMC_SPARSE_MAX_N) return 0;
+    // dqmc_sparse_primes splits what follows its 4 KiB of counters and
+    // alignment 3/8 : 3/8 : 1/4 into the two level regions (a list entry and
+    // at most four set slots per implicant, 40 bytes) and the prime region
+    // (keys and their sorted copy, 16 bytes per prime); the sort's scratch
+    // reuses the level regions.
+    const uint64_t lv = std::max<uint64_t>(max_level, 1), np = std::max<uint64_t>(max_primes, 1);
+    size_t sort_tmp = 0;
+    (void)rocprim::radix_sort_keys(nullptr, sort_tmp, (uint64_t *)nullptr, (uint64_t *)nullptr, (size_t)np, 0, 64);
+    const uint64_t for_levels = (40 * lv + 1024) * 8 / 3 + 8;
+    const uint64_t for_primes = (16 * np + 1024) * 4 + 8;
+    const uint64_t for_sort = ((uint64_t)sort_tmp + 1024) * 4 / 3 + 8;
+    return 4096 + std::max(for_levels, std::max(for_primes, for_sort));
+}
+
+int dqmc_sparse_primes(dqmc_ctx *ctx, int n, const uint32_t *d_tt, uint64_t *d_list, uint64_t list_cap,
+                       uint64_t *d_count, void *d_work, uint64_t work_bytes, uint64_t *h_need, void *stream)
+{
+    if (ctx == nullptr) return DQMC_EINVAL;
+    ctx->err[0] = 0;
+    if (n < 0 || n > DQMC_SPARSE_MAX_N) return sp_fail(ctx, DQMC_EINVAL, "sparse path needs 0 <= n <= 31");
+    if (d_tt == nullptr || d_count == nullptr || d_work == nullptr)
+        return sp_fail(ctx, DQMC_EINVAL, "NULL truth table, count or workspace");
+    if (((uintptr_t)d_tt & 3) || ((uintptr_t)d_count & 7) || ((uintptr_t)d_list & 7) || ((uintptr_t)d_work & 255))
+        return sp_fail(ctx, DQMC_EINVAL, "misaligned buffer (workspace: 256 bytes)");
+    if (hipSetDevice(ctx->device) != hipSuccess) return sp_fail(ctx, DQMC_EDEVICE, "hipSetDevice failed");
+    hipStream_t s = (hipStream_t)stream;
+    if (h_need) h_need[0] = h_need[1] = 0;
+    // workspace: counters | level A (list, set) | level B (list, set) | primes
+    // (keys) | sorted primes | sort scratch, with the level regions and the
+    // prime region sized from what is left: 3/8 each level, 1/4 primes
+    uint8_t *base = (uint8_t *)d_work;
+    const uint64_t avail = work_bytes > 4096 ? work_bytes - 4096 : 0;
+    SpCounters *cnt = (SpCounters *)base;
+    uint8_t *p = base + 256;
+    const uint64_t region = (avail * 3 / 8) & ~uint64_t(255);
+    uint8_t *levA = p, *levB = p + region;
+    uint8_t *prim = p + 2 * region;
+    const uint64_t prim_bytes = (avail - 2 * region) & ~uint64_t(255);
+    const uint64_t prim_cap = prim_bytes / 16;  // keys + sorted copy
+    uint64_t *pkeys = (uint64_t *)prim, *psorted = pkeys + prim_cap;
+    if (region < 1024 || prim_cap < 1) return sp_fail(ctx, DQMC_ENOMEM, "workspace too small");
+    // a level region holds its list (lcap entries, rounded up to 256 bytes)
+    // and a set of pow2 >= 2m <= 4m slots: at most 8 + 32 bytes per entry
+    const uint64_t lcap = (region - 256) / 40;
+    auto hip_ok = [&](hipError_t e) { return e == hipSuccess; };
+    SpCounters h{};
+    auto read_counters = [&]() {
+        return hip_ok(hipMemcpyAsync(&h, cnt, sizeof(SpCounters), hipMemcpyDeviceToHost, s)) &&
+               hip_ok(hipStreamSynchronize(s));
+    };
+    auto clear_counters = [&](bool keep_primes) {
+        SpCounters z{};
+        if (keep_primes) z.primes = h.primes;
+        return hip_ok(hipMemcpyAsync(cnt, &z, sizeof(SpCounters), hipMemcpyHostToDevice, s)) &&
+               hip_ok(hipStreamSynchronize(s));
+    };
+    if (!clear_counters(false)) return sp_fail(ctx, DQMC_EDEVICE, "counter upload failed");
+    // level 0: the support
+    uint64_t *L0 = (uint64_t *)levA;
+    hipLaunchKernelGGL(sp_minterms_kernel, dim3(sp_grid(((1ull << n) + 31) / 32)), dim3(kSpThreads), 0, s, d_tt, n,
+                       L0, &cnt->level, lcap, &cnt->overflow);
+    if (!hip_ok(hipGetLastError()) || !read_counters()) return sp_fail(ctx, DQMC_EDEVICE, "level 0 failed");
+    uint64_t need_level = h.level, need_primes = 0;
+    if (h.overflow) {
+        if (h_need) h_need[0] = need_level;
+        return sp_fail(ctx, DQMC_ENOMEM, "workspace too small for level 0");
+    }
+    uint64_t m_prev = h.level;
+    uint8_t *cur = levA, *nxt = levB;
+    auto build_set = [&](uint8_t *reg, uint64_t m, uint64_t **list, uint64_t **set, uint64_t *size) {
+        *list = (uint64_t *)reg;
+        *size = pow2_at_least(2 * std::max<uint64_t>(m, 1));
+        *set = (uint64_t *)(reg + ((8 * lcap + 255) & ~uint64_t(255)));
+        hipLaunchKernelGGL(sp_fill_kernel, dim3(sp_grid(*size)), dim3(kSpThreads), 0, s, *set, *size);
+        hipLaunchKernelGGL(sp_insert_kernel, dim3(sp_grid(m)), dim3(kSpThreads), 0, s, *list, m, *set, *size - 1);
+        return hip_ok(hipGetLastError());
+    };
+    uint64_t *list_prev, *set_prev, size_prev;
+    if (!build_set(cur, m_prev, &list_prev, &set_prev, &size_prev))
+        return sp_fail(ctx, DQMC_EDEVICE, "set construction failed");
+    if (!clear_counters(false)) return sp_fail(ctx, DQMC_EDEVICE, "counter upload failed");
+    for (int w = 1; m_prev > 0; ++w) {
+        uint64_t m = 0;
+        uint64_t *list_cur = nullptr, *set_cur = nullptr, size_cur = 0;
+        if (w <= n) {
+            hipLaunchKernelGGL(sp_generate_kernel, dim3(sp_grid(m_prev)), dim3(kSpThreads), 0, s, list_prev, m_prev,
+                               set_prev, size_prev - 1, n, (uint64_t *)nxt, &cnt->level, lcap, &cnt->overflow);
+            if (!hip_ok(hipGetLastError()) || !read_counters())
+                return sp_fail(ctx, DQMC_EDEVICE, "generation failed");
+            need_level = std::max<uint64_t>(need_level, h.level);
+            if (h.overflow) {
+                if (h_need) h_need[0] = need_level;
+                return sp_fail(ctx, DQMC_ENOMEM, "workspace too small for a level");
+            }
+            m = h.level;
+            if (m > 0) {
+                if (!build_set(nxt, m, &list_cur, &set_cur, &size_cur))
+                    return sp_fail(ctx, DQMC_EDEVICE, "set construction failed");
+                hipLaunchKernelGGL(sp_mark_kernel, dim3(sp_grid(m)), dim3(kSpThreads), 0, s, list_cur, m, set_prev,
+                                   size_prev - 1, &cnt->missing);
+            }
+        }
+        hipLaunchKernelGGL(sp_collect_kernel, dim3(sp_grid(size_prev)), dim3(kSpThreads), 0, s, set_prev, size_prev,
+                           pkeys, &cnt->primes, prim_cap, &cnt->overflow);
+        if (!hip_ok(hipGetLastError()) || !read_counters()) return sp_fail(ctx, DQMC_EDEVICE, "collection failed");
+        need_primes = h.primes;
+        if (h.missing) return sp_fail(ctx, DQMC_EDEVICE, "internal error: a merged half is missing");
+        if (h.overflow) {
+            if (h_need) {
+                h_need[0] = need_level;
+                h_need[1] = need_primes;
+            }
+            return sp_fail(ctx, DQMC_ENOMEM, "workspace too small for the primes");
+        }
+        // next level: reset the level counter, keep the prime count
+        h.level = 0;
+        if (!clear_counters(true)) return sp_fail(ctx, DQMC_EDEVICE, "counter upload failed");
+        std::swap(cur, nxt);
+        list_prev = list_cur;
+        set_prev = set_cur;
+        size_prev = size_cur;
+        m_prev = m;
+    }
+    const uint64_t np = h.primes;
+    if (h_need) {
+        h_need[0] = need_level;
+        h_need[1] = np;
+    }
+    // rho order
+    if (np > 0) {
+        hipLaunchKernelGGL(sp_to_rho_kernel, dim3(sp_grid(np)), dim3(kSpThreads), 0, s, pkeys, np, n);
+        size_t tmp_bytes = 0;
+        int end_bit = 1;
+        {
+            uint64_t top = 1;
+            for (int i = 0; i < n; ++i) top *= 3;
+            while (end_bit < 64 && (1ull << end_bit) < top) ++end_bit;
+        }
+        if (!hip_ok(rocprim::radix_sort_keys(nullptr, tmp_bytes, pkeys, psorted, (size_t)np, 0, end_bit, s)))
+            return sp_fail(ctx, DQMC_EDEVICE, "sort size query failed");
+        // the sort's scratch reuses the level regions (free by now)
+        if (tmp_bytes > 2 * region) return sp_fail(ctx, DQMC_ENOMEM, "workspace too small for the sort");
+        if (!hip_ok(rocprim::radix_sort_keys((void *)levA, tmp_bytes, pkeys, psorted, (size_t)np, 0, end_bit, s)))
+            return sp_fail(ctx, DQMC_EDEVICE, "sort failed");
+        const uint64_t k = std::min(np, d_list ? list_cap : 0);
+        if (k > 0 && !hip_ok(hipMemcpyAsync(d_list, psorted, k * 8, hipMemcpyDeviceToDevice, s)))
+            return sp_fail(ctx, DQMC_EDEVICE, "list copy failed");
+    }
+    uint64_t npv = np;
+    if (!hip_ok(hipMemcpyAsync(d_count, &npv, 8, hipMemcpyHostToDevice, s)) || !hip_ok(hipStreamSynchronize(s)))
+        return sp_fail(ctx, DQMC_EDEVICE, "count upload failed");
+    return DQMC_OK;
+}
+
+}  // extern "C"

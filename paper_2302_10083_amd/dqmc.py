@@ -46,6 +46,7 @@ class dqmc_pass_record(ctypes.Structure):
 DQMC_MAX_RECORDS = 64
 DQMC_MAX_PLAN_TRIALS = 64
 DQMC_NEGATE = 1
+DQMC_SPARSE_MAX_N = 31
 
 
 class dqmc_result(ctypes.Structure):
@@ -105,6 +106,8 @@ def load():
             "dqmc_implicants": (i32, [vp, i32, vp, vp, vp]),
             "dqmc_primes": (i32, [vp, i32, vp, vp, vp, u64, vp, vp]),
             "dqmc_implicants_ex": (i32, [vp, i32, vp, ctypes.c_uint32, vp, vp]),
+            "dqmc_sparse_workspace_bytes": (u64, [i32, u64, u64]),
+            "dqmc_sparse_primes": (i32, [vp, i32, vp, vp, u64, vp, vp, u64, ctypes.POINTER(ctypes.c_uint64), vp]),
             "dqmc_primes_ex": (i32, [vp, i32, vp, ctypes.c_uint32, vp, vp, u64, vp, vp]),
             "dqmc_extract": (i32, [vp, i32, vp, vp, u64, vp, vp]),
             "dqmc_bitmap_to_dense": (i32, [vp, i32, vp, vp, vp]),
@@ -253,6 +256,29 @@ def dqmc_primes_ex(ctx, n, tt, flags, state, lst, list_cap, count, stream=None) 
                                       _ptr(state, "state", torch.int32, dqmc_state_words(n)),
                                       _ptr(lst, "list", torch.int64, cap), cap,
                                       _ptr(count, "count", torch.int64, 1), _stream(stream)))
+
+
+def dqmc_sparse_workspace_bytes(n: int, max_level: int, max_primes: int) -> int:
+    return int(load().dqmc_sparse_workspace_bytes(n, int(max_level), int(max_primes)))
+
+
+def dqmc_sparse_primes(ctx, n, tt, lst, list_cap, count, work, stream=None):
+    """Sparse path (see include/dqmc.h).  `work` is a uint8 device tensor.
+    Returns (status, largest level, primes seen); status DQMC_ENOMEM means
+    the workspace was too small (nothing written), other errors raise."""
+    import torch
+
+    if not isinstance(work, torch.Tensor) or work.device.type != "cuda" or work.dtype != torch.uint8:
+        raise TypeError("work must be a uint8 device tensor")
+    need = (ctypes.c_uint64 * 2)()
+    cap = 0 if lst is None else int(list_cap)
+    nw = max(1, (1 << n) // 32) if 0 <= n <= DQMC_SPARSE_MAX_N else 1  # the library rejects other n
+    rc = load().dqmc_sparse_primes(ctx, n, _ptr(tt, "tt", torch.int32, nw), _ptr(lst, "list", torch.int64, cap), cap,
+                                   _ptr(count, "count", torch.int64, 1), ctypes.c_void_p(work.data_ptr()),
+                                   work.numel(), need, _stream(stream))
+    if rc != DQMC_ENOMEM:
+        _check(ctx, rc)
+    return rc, int(need[0]), int(need[1])
 
 
 def dqmc_extract(ctx, n, state, lst, list_cap, count, stream=None) -> None:
@@ -527,6 +553,33 @@ class Context:
         lst = torch.empty(max(int(list_cap), 1), dtype=torch.int64, device=self.torch_device)
         dqmc_primes_ex(self.ctx, n, tt, flags, state, lst, list_cap, count, stream)
         return state, lst, count
+
+    def sparse_primes(self, n, tt, work_bytes=None, stream=None):
+        """(list, count) of the sparse path; the workspace grows as needed
+        (one retry with the sizes the first attempt reports)."""
+        import torch
+
+        count = torch.zeros(1, dtype=torch.int64, device=self.torch_device)
+        if work_bytes is None:
+            work_bytes = 256 << 20
+        lv = npr = 0
+        for _ in range(8):
+            work = torch.empty(int(work_bytes), dtype=torch.uint8, device=self.torch_device)
+            rc, lv2, npr2 = dqmc_sparse_primes(self.ctx, n, tt, None, 0, count, work, stream)
+            if rc == DQMC_OK:
+                break
+            # a failed attempt only saw the levels up to the one that overflowed
+            lv, npr = max(lv, lv2) * 2, max(npr, npr2, 1) * 2
+            work_bytes = max(dqmc_sparse_workspace_bytes(n, lv, npr), 2 * int(work_bytes))
+            del work
+        else:
+            raise DqmcError(DQMC_ENOMEM, "sparse workspace still too small")
+        c = int(count.item())
+        lst = torch.empty(max(c, 1), dtype=torch.int64, device=self.torch_device)
+        rc, _, _ = dqmc_sparse_primes(self.ctx, n, tt, lst, c, count, work, stream)
+        if rc != DQMC_OK:
+            raise DqmcError(rc, "sparse path failed on the second run")
+        return lst[:c], count
 
     def extract(self, n, state, list_cap, stream=None):
         import torch
