@@ -160,8 +160,17 @@ __global__ __launch_bounds__(kSpThreads) void sp_generate_kernel(const uint64_t 
         uint32_t takes = 0;
         for (int p = 0; p < f; ++p) {
             uint64_t slot;
-            if (((c >> (2 * p)) & 3ull) == 0ull && sp_find(table, mask, c | (1ull << (2 * p)), &slot))
+            if (((c >> (2 * p)) & 3ull) == 0ull && sp_find(table, mask, c | (1ull << (2 * p)), &slot)) {
                 takes |= 1u << p;
+                // the pair of u's first star is marked here (the partner's
+                // slot is at hand); sp_mark_kernel covers the other stars
+                atomicOr((unsigned long long *)&table[slot], (unsigned long long)kRedundant);
+            }
+        }
+        if (takes != 0u) {
+            uint64_t slot;
+            if (sp_find(table, mask, c, &slot))
+                atomicOr((unsigned long long *)&table[slot], (unsigned long long)kRedundant);
         }
         uint64_t pos = block_reserve((uint32_t)__popc(takes), counter);
         while (takes != 0u) {
@@ -172,7 +181,8 @@ __global__ __launch_bounds__(kSpThreads) void sp_generate_kernel(const uint64_t 
     }
 }
 
-// Step 3: both halves of every star of every new implicant are redundant.
+// Step 3: both halves of every star of every new implicant are redundant
+// (the first star's pair was marked during generation).
 __global__ __launch_bounds__(kSpThreads) void sp_mark_kernel(const uint64_t *cur, uint64_t count, uint64_t *table,
                                                              uint64_t mask, unsigned int *missing)
 {
@@ -180,6 +190,7 @@ __global__ __launch_bounds__(kSpThreads) void sp_mark_kernel(const uint64_t *cur
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) {
         const uint64_t u = cur[i];
         uint64_t stars = u & 0xAAAAAAAAAAAAAAAAull;
+        stars &= stars - 1ull;  // all but the first star
         while (stars != 0) {
             const int q = __builtin_ctzll(stars) >> 1;
             stars &= stars - 1ull;
@@ -193,18 +204,31 @@ __global__ __launch_bounds__(kSpThreads) void sp_mark_kernel(const uint64_t *cur
     }
 }
 
-// Step 4: unmarked entries of a level's set are prime.
+// Step 4: unmarked entries of a level's set are prime.  Each thread looks at
+// kCollect slots (a workgroup covers kCollect * 256 consecutive slots, loads
+// coalesced) per reservation.
+constexpr int kCollect = 8;
+
 __global__ __launch_bounds__(kSpThreads) void sp_collect_kernel(const uint64_t *table, uint64_t size, uint64_t *out,
                                                                 unsigned long long *counter, uint64_t cap,
                                                                 unsigned int *overflow)
 {
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    const uint64_t total = (size + kSpThreads - 1) / kSpThreads * kSpThreads;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
-        const uint64_t v = i < size ? table[i] : kEmpty;
-        const bool prime = v != kEmpty && (v & kRedundant) == 0ull;
-        const uint64_t pos = block_reserve(prime ? 1u : 0u, counter);
-        if (prime) sp_put(out, pos, cap, v, overflow);
+    constexpr uint64_t kSpan = (uint64_t)kCollect * kSpThreads;
+    const uint64_t stride = (uint64_t)gridDim.x * kSpan;
+    for (uint64_t b0 = (uint64_t)blockIdx.x * kSpan; b0 < size; b0 += stride) {
+        uint64_t v[kCollect];
+        uint32_t mine = 0;
+        static_for<kCollect>([&](auto ji) {
+            constexpr int j = decltype(ji)::value;
+            const uint64_t i = b0 + (uint64_t)j * kSpThreads + threadIdx.x;
+            v[j] = i < size ? table[i] : kEmpty;
+            mine += (v[j] != kEmpty && (v[j] & kRedundant) == 0ull) ? 1u : 0u;
+        });
+        uint64_t pos = block_reserve(mine, counter);
+        static_for<kCollect>([&](auto ji) {
+            constexpr int j = decltype(ji)::value;
+            if (v[j] != kEmpty && (v[j] & kRedundant) == 0ull) sp_put(out, pos++, cap, v[j], overflow);
+        });
     }
 }
 
@@ -360,11 +384,13 @@ int dqmc_sparse_primes(dqmc_ctx *ctx, int n, const uint32_t *d_tt, uint64_t *d_l
             if (m > 0) {
                 if (!build_set(nxt, m, &list_cur, &set_cur, &size_cur))
                     return sp_fail(ctx, DQMC_EDEVICE, "set construction failed");
-                hipLaunchKernelGGL(sp_mark_kernel, dim3(sp_grid(m)), dim3(kSpThreads), 0, s, list_cur, m, set_prev,
-                                   size_prev - 1, &cnt->missing);
+                if (w >= 2)
+                    hipLaunchKernelGGL(sp_mark_kernel, dim3(sp_grid(m)), dim3(kSpThreads), 0, s, list_cur, m,
+                                       set_prev, size_prev - 1, &cnt->missing);
             }
         }
-        hipLaunchKernelGGL(sp_collect_kernel, dim3(sp_grid(size_prev)), dim3(kSpThreads), 0, s, set_prev, size_prev,
+        hipLaunchKernelGGL(sp_collect_kernel, dim3(sp_grid((size_prev + kCollect - 1) / kCollect)), dim3(kSpThreads), 0,
+                           s, set_prev, size_prev,
                            pkeys, &cnt->primes, prim_cap, &cnt->overflow);
         if (!hip_ok(hipGetLastError()) || !read_counters()) return sp_fail(ctx, DQMC_EDEVICE, "collection failed");
         need_primes = h.primes;
