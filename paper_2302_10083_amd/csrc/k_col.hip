@@ -13,30 +13,11 @@
 // lane's registers; cw (GW digits) is the wavefront within the workgroup;
 // o is the combination of the digits above the group.  Digits of cr are
 // transformed in registers, digits of cw through LDS.
+#include "col_common.h"
 #include "launch.h"
 #include "t27.h"
 
 namespace dqmc {
-
-// Position of wave combination cw among the non-binary combinations.
-template <int GW>
-__device__ __forceinline__ int star_slot(int cw)
-{
-    int k = 0;
-    for (int c = 0; c < cw; ++c) {
-        int q = c;
-        bool b = true;
-        for (int r = 0; r < GW; ++r, q /= 3) b = b && (q % 3 != 2);
-        k += b ? 0 : 1;
-    }
-    return k;
-}
-
-template <int GW>
-__host__ __device__ constexpr int col_threads()
-{
-    return GW == 0 ? 256 : 64 * (int)pow3(GW);
-}
 
 template <int GR, int GW, int MODE>
 __global__ __launch_bounds__(col_threads<GW>()) void col_kernel(ColArgs a)
@@ -130,10 +111,18 @@ __global__ __launch_bounds__(col_threads<GW>()) void col_kernel(ColArgs a)
         // 3. register digits
         reg_merge<GR>(x);
         if constexpr (MODE == kColMerge) {
-            if (active) {
+            // one branch per wave kind, none per row: per-row conditions on
+            // cw_binary let the compiler merge stores of different rows into
+            // one indexed load, which moves x to scratch memory
+            if (active && cw_binary) {
                 static_for<CR>([&](auto ci) {
                     constexpr int c = decltype(ci)::value;
-                    if (!cw_binary || !all_binary(c, GR)) ROW(c)[l] = x[c];
+                    if constexpr (!all_binary(c, GR)) ROW(c)[l] = x[c];
+                });
+            } else if (active) {
+                static_for<CR>([&](auto ci) {
+                    constexpr int c = decltype(ci)::value;
+                    ROW(c)[l] = x[c];
                 });
             }
             return;
@@ -201,13 +190,10 @@ static hipError_t launch_col_gw(int mode, const ColArgs &a, hipStream_t s)
 
 hipError_t launch_col(int gr, int gw, int mode, const ColArgs &a, hipStream_t s)
 {
+    // groups with at most one wave digit use the chunked kernel (k_col_chunk.hip)
+    if (gw <= 1) return launch_col_chunked(gr, gw, mode, a, s);
 #define DQMC_COL(R, W) \
     if (gr == R && gw == W) return launch_col_gw<R, W>(mode, a, s);
-    DQMC_COL(1, 0)
-    DQMC_COL(2, 0)
-    DQMC_COL(3, 0)
-    DQMC_COL(4, 0)
-    DQMC_COL(4, 1)
     DQMC_COL(4, 2)
 #undef DQMC_COL
     return hipErrorInvalidValue;

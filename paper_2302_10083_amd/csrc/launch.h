@@ -71,6 +71,8 @@ struct ColArgs {
 
 hipError_t col_setup();
 hipError_t launch_col(int gr, int gw, int mode, const ColArgs &a, hipStream_t s);
+// The chunked form (groups with at most one wave digit; launch_col picks it).
+hipError_t launch_col_chunked(int gr, int gw, int mode, const ColArgs &a, hipStream_t s);
 int col_lanes_per_block(int gw);  // l values per workgroup
 
 // One function of a batch as the batch kernel sees it (device memory).

@@ -152,6 +152,17 @@ __device__ __forceinline__ void reg_reduce(uint32_t (&x)[pow3(K)])
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
+// Workgroup barrier that orders LDS accesses only.  __syncthreads() also
+// orders global memory, which makes every wave wait for all of its
+// outstanding global loads and stores first; where a barrier only guards LDS
+// that wait would expose the latency of stores issued just before it.
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 __device__ __forceinline__ uint64_t wave_inclusive_scan(uint64_t v)
 {
     const uint32_t lane = lane_id();
