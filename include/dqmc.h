@@ -233,7 +233,9 @@ int dqmc_primes_batch(dqmc_ctx *ctx, dqmc_job *jobs, int32_t njobs, void *stream
  *   dqmc_server_release: frees a finished job's device memory.
  *   dqmc_server_read: copies a finished job's list (up to cap entries) into
  *     host memory and returns the number copied (negative on error).
- *   dqmc_server_destroy: waits for running jobs, frees everything.
+ *   dqmc_server_destroy: waits for running jobs, drops jobs that are
+ *     still queued, frees everything; no other call on the server may be
+ *     in progress.
  * Times are seconds on one monotonic host clock. */
 typedef struct dqmc_server dqmc_server;
 

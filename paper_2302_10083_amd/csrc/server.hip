@@ -299,7 +299,13 @@ void scheduler(dqmc_server *s)
                 }
             }
         if (retired) s->cv_done.notify_all();
-        if (s->stop && s->queue.empty() && !any_running) break;
+        // on destruction: let running work finish, admit nothing more (a
+        // queued job may wait for results that nobody will release)
+        if (s->stop) {
+            if (!any_running) break;
+            s->cv_work.wait_for(lk, std::chrono::microseconds(20));
+            continue;
+        }
         // admission, first fit in arrival order (with aging of the head)
         std::vector<uint64_t> small_ids;
         Slot *free_small = nullptr;

@@ -156,3 +156,19 @@ def test_bad_requests_fail_alone():
             srv.release(jid)
         with pytest.raises(dqmc.DqmcError):
             srv.poll(123456)
+
+
+def test_destroy_with_blocked_queue():
+    """Closing a server whose queue cannot move (its budget is held by an
+    unreleased result) returns, dropping the queued job."""
+    import time as _time
+
+    from paper_2302_10083_amd import dqmc
+
+    srv = dqmc.Server(0, budget=footprint(18) + footprint(16))
+    a = srv.submit(18, inputs.bernoulli(18, 0.9, 11))
+    srv.submit(18, inputs.bernoulli(18, 0.9, 12))
+    srv.wait(a)
+    t0 = _time.perf_counter()
+    srv.close()
+    assert _time.perf_counter() - t0 < 5.0
