@@ -202,6 +202,57 @@ def bench_sparse(ctx, n=24, densities=(0.25, 0.5), reps=3):
             "rows": rows}
 
 
+def bench_sliced(ctx, workload="c3x_n26_dnf2000_noise", ts=(2, 1), reps=2):
+    """Functions past one state in HBM: the sliced path on the n = 26 version
+    of the benchmark workload (two slice states of n - t variables)."""
+    import numpy as np
+    import torch
+
+    from paper_2302_10083_amd import dqmc, inputs
+
+    spec = inputs.CONFIGS[workload]
+    n = spec["n"]
+    tt = inputs.make(spec)
+    dev = ctx.torch_device
+    ttd = ctx.tt_to_device(tt)
+    count = torch.zeros(1, dtype=torch.int64, device=dev)
+    out = {"workload": workload, "n": n, "cubes": 3**n, "truth_table": spec,
+           "single_state_GB": 4 * 3 ** (n - 3) / 1e9, "rows": []}
+    lst = None
+    for t in ts:
+        need = 2 * 4 * 3 ** (n - t - 3)
+        free = torch.cuda.mem_get_info()[0]
+        if need + (16 << 30) > free:
+            out["rows"].append({"t": t, "skipped": "needs %.1f GB of slice states, %.1f GB free" % (need / 1e9,
+                                                                                                 free / 1e9)})
+            continue
+        o, m = ctx.new_state(n - t), ctx.new_state(n - t)
+        if lst is None:
+            dqmc.dqmc_primes_sliced(ctx.ctx, n, t, ttd, 0, o, m, None, 0, count)
+            torch.cuda.synchronize()
+            nprimes = int(count.item())
+            lst = torch.empty(max(nprimes, 1), dtype=torch.int64, device=dev)
+            out["primes"] = nprimes
+        dqmc.dqmc_primes_sliced(ctx.ctx, n, t, ttd, 0, o, m, lst, nprimes, count)  # warm-up
+        torch.cuda.synchronize()
+        start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        start.record()
+        for _ in range(reps):
+            dqmc.dqmc_primes_sliced(ctx.ctx, n, t, ttd, 0, o, m, lst, nprimes, count)
+        end.record()
+        torch.cuda.synchronize()
+        assert int(count.item()) == nprimes
+        ms = start.elapsed_time(end) / reps
+        out["rows"].append({"t": t, "slices": 3**t, "slice_states_GB": need / 1e9, "ms": ms,
+                            "cubes_per_s": 3**n / (ms / 1e3)})
+        print("bench: sliced n=%d t=%d %.1f ms" % (n, t, ms), file=sys.stderr, flush=True)
+        del o, m
+        torch.cuda.empty_cache()
+    del lst, ttd
+    torch.cuda.empty_cache()
+    return out
+
+
 def bench_serving(nreq=200, seed=25):
     """Serving mix (n in {10,14,18,22,25} with weights .4/.3/.15/.1/.05):
     saturation throughput from a closed loop, then Poisson arrivals at 0.5 and
@@ -308,6 +359,7 @@ def main():
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-cnf", action="store_true")
     ap.add_argument("--no-sparse", action="store_true")
+    ap.add_argument("--no-sliced", action="store_true")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -446,9 +498,11 @@ def main():
                       "clauses_equal_dnf_primes": int(count.item()) == nprimes}
         del sd
         print("bench: cnf %.2f ms" % ms_cnf, file=sys.stderr, flush=True)
-    if not args.no_batch or not args.no_sparse:
+    if not args.no_batch or not args.no_sparse or not args.no_sliced:
         del lst, state
         torch.cuda.empty_cache()
+    if not args.no_sliced:
+        out["sliced"] = bench_sliced(ctx)
     if not args.no_sparse:
         out["sparse"] = bench_sparse(ctx)
         print("bench: sparse %s" % ", ".join("d=%.2f %.1f ms (dense %.1f ms)" % (r["density"], r["ms_sparse"],

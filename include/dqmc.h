@@ -60,8 +60,9 @@ typedef enum {
 
 typedef struct dqmc_ctx dqmc_ctx;
 
-/* Create a context on HIP device `device` and allocate its scratch (a few
- * tens of MB at most).  Returns DQMC_ENOMEM / DQMC_EDEVICE on failure, with
+/* Create a context on HIP device `device` and allocate its scratch (under
+ * 100 MB: per-tile summaries and offsets for n = DQMC_MAX_N, and one slice
+ * truth table of the sliced path).  Returns DQMC_ENOMEM / DQMC_EDEVICE on failure, with
  * *out set to NULL. */
 int dqmc_create(int device, dqmc_ctx **out);
 
@@ -142,6 +143,37 @@ int dqmc_primes_ex(dqmc_ctx *ctx, int n, const uint32_t *d_tt, uint32_t flags, u
 uint64_t dqmc_sparse_workspace_bytes(int n, uint64_t max_level, uint64_t max_primes);
 int dqmc_sparse_primes(dqmc_ctx *ctx, int n, const uint32_t *d_tt, uint64_t *d_list, uint64_t list_cap,
                        uint64_t *d_count, void *d_work, uint64_t work_bytes, uint64_t *h_need, void *stream);
+
+/* Sliced path: functions with more variables than one state can hold
+ * (n up to DQMC_SLICED_MAX_N), cut along their top t variables into 3^t
+ * slices of m = n - t variables, m <= DQMC_MAX_N.
+ * For a cube a over x_{m+1..n} (digit j of a is the literal on x_{m+1+j}),
+ * f_a is the function of x_1..x_m that ANDs f over the minterms of a.  The
+ * cube s.a (digits 1..m from s, m+1..n from a) is an implicant of f iff s is
+ * an implicant of f_a, so MergeAll (Sec. 4.1) of slice a is MergeAll of f_a.
+ * Reduce along a top digit j with a_j binary (Sec. 4.1, Def. of Reduce)
+ * removes s.a when s is also an implicant of f_a' (a' = a with digit j
+ * flipped 0 <-> 1).  Hence
+ *     s.a is prime  <=>  s is a prime of f_a and, for every binary digit j
+ *                        of a, s is not an implicant of f_a'.
+ * Per slice, in increasing order of a (as a base-3 number, * = 2): the primes
+ * of f_a into d_o, for every binary digit j the implicants of f_a' into d_m
+ * and d_o &= ~d_m, then the slice's primes are appended to the list.
+ *   d_tt      device, the n-variable truth table: 2^(n-5) words (1 for n < 5).
+ *   flags     0 or DQMC_NEGATE (the primes of NOT f).
+ *   d_o, d_m  device, dqmc_state_words(n - t) words each: slice states, used
+ *             as scratch; their contents afterwards are unspecified.  They
+ *             must not overlap.
+ *   d_list    device, room for list_cap uint64 (may be NULL: count only).
+ *   d_count   device, one uint64: the number of primes of f.
+ * The list and capacity rules are those of dqmc_primes: the list_cap smallest
+ * indices rho over all n digits, in increasing order.  Unlike dqmc_primes
+ * there is no n-variable bitmap, so a list that was too small needs a second
+ * call.  Errors: DQMC_EINVAL (n, t, NULL, alignment, flags), DQMC_EDEVICE. */
+#define DQMC_SLICED_MAX_N 30
+#define DQMC_SLICED_MAX_T 8
+int dqmc_primes_sliced(dqmc_ctx *ctx, int n, int t, const uint32_t *d_tt, uint32_t flags, uint32_t *d_o,
+                       uint32_t *d_m, uint64_t *d_list, uint64_t list_cap, uint64_t *d_count, void *stream);
 
 /* Extraction alone (Alg. 4, output step): every set bit of a state bitmap,
  * as increasing cube indices.  Same list/capacity/count rules as

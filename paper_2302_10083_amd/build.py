@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libdqmc.so")
-SOURCES = ["api.hip", "server.hip", "k_low.hip", "k_col.hip", "k_col_chunk.hip", "k_list.hip", "k_batch.hip", "k_misc.hip", "tune.hip", "sparse.hip"]
+SOURCES = ["api.hip", "server.hip", "k_low.hip", "k_col.hip", "k_col_chunk.hip", "k_list.hip", "k_batch.hip", "k_misc.hip", "tune.hip", "sparse.hip", "k_slice.hip"]
 ARCH = os.environ.get("DQMC_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

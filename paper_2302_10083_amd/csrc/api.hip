@@ -178,28 +178,65 @@ int enqueue_merge(dqmc_ctx *ctx, int n, const uint32_t *tt, uint32_t flip, uint3
     return DQMC_OK;
 }
 
-// Final low-tile pass (reduce or plain count), scan of the tile counts, and
-// the list pass.
-int enqueue_extract_tiles(dqmc_ctx *ctx, int n, int mode, uint32_t *state, uint64_t *list, uint64_t cap,
-                          uint64_t *count, hipStream_t s)
+// The low-tile pass that ends a prime bitmap: reduce of digits 1..12 with the
+// tile summaries, or the summaries alone.
+int enqueue_summary(dqmc_ctx *ctx, int n, int mode, uint32_t *state, hipStream_t s)
 {
     LowArgs a = low_args(ctx, n);
     a.state = state;
     const double S = state_bytes(n);
     const bool reduce = mode == kLowReduceCount;
-    int rc = run_pass(ctx, s, reduce ? "low_reduce_count" : "low_count", n,
-                      (reduce ? 2 * S : S) + a.ntiles * 4.0 * (1 + kMapWords), 0,
-                      [&] { return launch_low(mode, a, a.ntiles, s); });
-    if (rc != DQMC_OK) return rc;
-    rc = run_pass(ctx, s, "scan_counts", n, a.ntiles * 12.0, 0,
-                  [&] { return launch_scan_counts(ctx->counts, a.ntiles, ctx->offs, count, ctx->sums, s); });
+    return run_pass(ctx, s, reduce ? "low_reduce_count" : "low_count", n,
+                    (reduce ? 2 * S : S) + a.ntiles * 4.0 * (1 + kMapWords), 0,
+                    [&] { return launch_low(mode, a, a.ntiles, s); });
+}
+
+// Scan of the tile counts (starting at *base when base is given) and the
+// list pass (cube indices offset by rho0).
+int enqueue_scan_list(dqmc_ctx *ctx, int n, const uint32_t *state, uint64_t *list, uint64_t cap, uint64_t *count,
+                      const uint64_t *base, uint64_t rho0, hipStream_t s)
+{
+    const LowArgs a = low_args(ctx, n);
+    int rc = run_pass(ctx, s, "scan_counts", n, a.ntiles * 12.0, 0, [&] {
+        return launch_scan_counts(ctx->counts, a.ntiles, ctx->offs, count, ctx->sums, s, base);
+    });
     if (rc != DQMC_OK || list == nullptr) return rc;
     // the list pass reads the summaries and the non-zero chunks (data
     // dependent, so only the summaries are in the model) and writes 8 bytes
     // per listed prime
     return run_pass(ctx, s, "list", n, a.ntiles * 4.0 * (3 + kMapWords), 8, [&] {
-        return launch_list(n, state, a.tw, a.ntiles, ctx->counts, ctx->chunkmap, ctx->offs, list, cap, s);
+        return launch_list(n, state, a.tw, a.ntiles, ctx->counts, ctx->chunkmap, ctx->offs, list, cap, s, rho0);
     });
+}
+
+// Final low-tile pass (reduce or plain count), scan of the tile counts, and
+// the list pass.
+int enqueue_extract_tiles(dqmc_ctx *ctx, int n, int mode, uint32_t *state, uint64_t *list, uint64_t cap,
+                          uint64_t *count, hipStream_t s)
+{
+    const int rc = enqueue_summary(ctx, n, mode, state, s);
+    if (rc != DQMC_OK) return rc;
+    return enqueue_scan_list(ctx, n, state, list, cap, count, nullptr, 0, s);
+}
+
+// Steps 1-4 for n > 12: merges, the top group's merge and reduce, and the
+// reduces of the other high groups (the low digits are reduced by the
+// summary pass).
+int enqueue_reduce_high(dqmc_ctx *ctx, int n, const uint32_t *tt, uint32_t flip, uint32_t *state, hipStream_t s)
+{
+    int rc = enqueue_merge(ctx, n, tt, flip, state, true, s);
+    if (rc != DQMC_OK) return rc;
+    const std::vector<Group> gs = groups_of(plan_sizes(ctx, n));
+    for (int j = (int)gs.size() - 2; j >= 0; --j) {
+        const ColArgs c = col_args(state, n, gs[j], false);
+        const double S = state_bytes(n);
+        char name[40];
+        snprintf(name, sizeof(name), "col_reduce_g%d_%d", gs[j].g0, gs[j].size());
+        rc = run_pass(ctx, s, name, n, S * (2.0 - std::pow(3.0, -gs[j].size())), 0,
+                      [&] { return launch_col(gs[j].gr, gs[j].gw, kColReduce, c, s); });
+        if (rc != DQMC_OK) return rc;
+    }
+    return DQMC_OK;
 }
 
 }  // namespace
@@ -228,6 +265,8 @@ int dqmc_create(int device, dqmc_ctx **out)
     c->chunkmap = nullptr;
     c->offs = nullptr;
     c->sums = nullptr;
+    c->slice_tt = nullptr;
+    c->run = nullptr;
     c->err[0] = 0;
     c->prof = false;
     c->events_made = false;
@@ -236,7 +275,9 @@ int dqmc_create(int device, dqmc_ctx **out)
     if (hipMalloc((void **)&c->counts, c->tiles_cap * sizeof(uint32_t)) != hipSuccess ||
         hipMalloc((void **)&c->chunkmap, c->tiles_cap * kMapWords * sizeof(uint32_t)) != hipSuccess ||
         hipMalloc((void **)&c->offs, c->tiles_cap * sizeof(uint64_t)) != hipSuccess ||
-        hipMalloc((void **)&c->sums, scan_scratch_words(c->tiles_cap) * sizeof(uint64_t)) != hipSuccess) {
+        hipMalloc((void **)&c->sums, scan_scratch_words(c->tiles_cap) * sizeof(uint64_t)) != hipSuccess ||
+        hipMalloc((void **)&c->slice_tt, dqmc_tt_words(DQMC_MAX_N) * sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc((void **)&c->run, 2 * sizeof(uint64_t)) != hipSuccess) {
         dqmc_destroy(c);
         return DQMC_ENOMEM;
     }
@@ -254,6 +295,8 @@ void dqmc_destroy(dqmc_ctx *ctx)
     if (ctx->chunkmap) (void)hipFree(ctx->chunkmap);
     if (ctx->offs) (void)hipFree(ctx->offs);
     if (ctx->sums) (void)hipFree(ctx->sums);
+    if (ctx->slice_tt) (void)hipFree(ctx->slice_tt);
+    if (ctx->run) (void)hipFree(ctx->run);
     delete ctx;
 }
 
@@ -313,19 +356,92 @@ int dqmc_primes_ex(dqmc_ctx *ctx, int n, const uint32_t *d_tt, uint32_t flags, u
         return run_pass(ctx, s, "low_primes_tt", n, tt_bytes(n) + state_bytes(n), d_list ? 8 : 0,
                         [&] { return launch_low(kLowPrimesTT, a, 1, s); });
     }
-    rc = enqueue_merge(ctx, n, d_tt, flip, d_state, true, s);
+    rc = enqueue_reduce_high(ctx, n, d_tt, flip, d_state, s);
     if (rc != DQMC_OK) return rc;
-    const std::vector<Group> gs = groups_of(plan_sizes(ctx, n));
-    for (int j = (int)gs.size() - 2; j >= 0; --j) {
-        const ColArgs c = col_args(d_state, n, gs[j], false);
-        const double S = state_bytes(n);
-        char name[40];
-        snprintf(name, sizeof(name), "col_reduce_g%d_%d", gs[j].g0, gs[j].size());
-        rc = run_pass(ctx, s, name, n, S * (2.0 - std::pow(3.0, -gs[j].size())), 0,
-                      [&] { return launch_col(gs[j].gr, gs[j].gw, kColReduce, c, s); });
+    return enqueue_extract_tiles(ctx, n, kLowReduceCount, d_state, d_list, list_cap, d_count, s);
+}
+
+int dqmc_primes_sliced(dqmc_ctx *ctx, int n, int t, const uint32_t *d_tt, uint32_t flags, uint32_t *d_o,
+                       uint32_t *d_m, uint64_t *d_list, uint64_t list_cap, uint64_t *d_count, void *stream)
+{
+    if (ctx == nullptr) return DQMC_EINVAL;
+    ctx->err[0] = 0;
+    if (n < 1 || n > DQMC_SLICED_MAX_N || t < 1 || t > DQMC_SLICED_MAX_T || t > n || n - t > DQMC_MAX_N) {
+        char buf[64];
+        snprintf(buf, sizeof(buf), "n = %d, t = %d", n, t);
+        return fail(ctx, DQMC_EINVAL, "%s: need 1 <= t <= 8, t <= n <= 30 and n - t <= 25", buf);
+    }
+    const int m = n - t;
+    int rc = check_common(ctx, m);
+    if (rc != DQMC_OK) return rc;
+    if ((flags & ~(uint32_t)DQMC_NEGATE) != 0u) return fail(ctx, DQMC_EINVAL, "%s", "unknown flag bits");
+    const uint32_t flip = (flags & DQMC_NEGATE) ? ~0u : 0u;
+    if (d_tt == nullptr || d_o == nullptr || d_m == nullptr || d_count == nullptr)
+        return fail(ctx, DQMC_EINVAL, "%s", "NULL truth table, slice state or count");
+    if (!aligned(d_tt, 4) || !aligned(d_o, 4) || !aligned(d_m, 4) || !aligned(d_count, 8) || !aligned(d_list, 8))
+        return fail(ctx, DQMC_EINVAL, "%s", "misaligned buffer");
+    const uint64_t sw = dqmc_state_words(m);
+    if (d_o < d_m + sw && d_m < d_o + sw) return fail(ctx, DQMC_EINVAL, "%s", "the slice states overlap");
+    hipStream_t s = (hipStream_t)stream;
+    const LowArgs la = low_args(ctx, m);
+    const uint64_t nslices = pow3(t), slice_cubes = pow3(m);
+    const double ttb = tt_bytes(m);
+    for (uint64_t idx = 0; idx < nslices; ++idx) {
+        uint32_t fixed = 0, stars = 0;
+        uint64_t r = idx;
+        for (int j = 0; j < t; ++j, r /= 3) {
+            if (r % 3 == 1) fixed |= 1u << j;
+            if (r % 3 == 2) stars |= 1u << j;
+        }
+        const double sub = (double)(1u << __builtin_popcount(stars));
+        // primes of f_a into d_o, with the tile summaries
+        rc = run_pass(ctx, s, "slice_tt", m, ttb * (sub + 1.0), 0,
+                      [&] { return launch_slice_tt(d_tt, m, fixed, stars, flip, ctx->slice_tt, s); });
+        if (rc != DQMC_OK) return rc;
+        if (m <= kLowDigits) {
+            LowArgs a = la;
+            a.tt = ctx->slice_tt;
+            a.state = d_o;
+            rc = run_pass(ctx, s, "low_primes_tt", m, ttb + state_bytes(m), 0,
+                          [&] { return launch_low(kLowPrimesTT, a, 1, s); });
+            if (rc == DQMC_OK) rc = enqueue_summary(ctx, m, kLowCount, d_o, s);
+        } else {
+            rc = enqueue_reduce_high(ctx, m, ctx->slice_tt, 0u, d_o, s);
+            if (rc == DQMC_OK) rc = enqueue_summary(ctx, m, kLowReduceCount, d_o, s);
+        }
+        if (rc != DQMC_OK) return rc;
+        // Reduce along each binary top digit: drop what f_a' also implies
+        for (int j = 0; j < t; ++j) {
+            if ((stars >> j) & 1u) continue;
+            const uint32_t fx = fixed ^ (1u << j);
+            rc = run_pass(ctx, s, "slice_tt", m, ttb * (sub + 1.0), 0,
+                          [&] { return launch_slice_tt(d_tt, m, fx, stars, flip, ctx->slice_tt, s); });
+            if (rc != DQMC_OK) return rc;
+            if (m <= kLowDigits) {
+                LowArgs a = la;
+                a.tt = ctx->slice_tt;
+                a.state = d_m;
+                rc = run_pass(ctx, s, "low_merge_tt", m, ttb + state_bytes(m), 0,
+                              [&] { return launch_low(kLowMergeTT, a, 1, s); });
+            } else {
+                rc = enqueue_merge(ctx, m, ctx->slice_tt, 0u, d_m, false, s);
+            }
+            if (rc != DQMC_OK) return rc;
+            // data dependent (only the marked chunks are read); the model
+            // counts the summaries
+            rc = run_pass(ctx, s, "andnot_map", m, la.ntiles * 8.0 * (1 + kMapWords), 0, [&] {
+                return launch_andnot_map(d_o, d_m, ctx->counts, ctx->chunkmap, la.ntiles, la.tw, s);
+            });
+            if (rc != DQMC_OK) return rc;
+        }
+        // append the slice's primes: offsets continue from the previous
+        // slices' total (two running counters, used alternately)
+        uint64_t *total = idx + 1 == nslices ? d_count : ctx->run + (idx & 1);
+        const uint64_t *base = idx == 0 ? nullptr : ctx->run + ((idx - 1) & 1);
+        rc = enqueue_scan_list(ctx, m, d_o, d_list, d_list ? list_cap : 0, total, base, idx * slice_cubes, s);
         if (rc != DQMC_OK) return rc;
     }
-    return enqueue_extract_tiles(ctx, n, kLowReduceCount, d_state, d_list, list_cap, d_count, s);
+    return DQMC_OK;
 }
 
 int dqmc_extract(dqmc_ctx *ctx, int n, const uint32_t *d_state, uint64_t *d_list, uint64_t list_cap,

@@ -16,6 +16,8 @@ struct dqmc_ctx {
     uint32_t *chunkmap;
     uint64_t *offs;
     uint64_t *sums;  // per-block sums of the count scan
+    uint32_t *slice_tt;  // sliced path: truth table of one slice (2^20 words)
+    uint64_t *run;       // sliced path: running prime counts (2)
     char err[512];
     // per-pass timing (diagnostics)
     bool prof;

@@ -37,7 +37,8 @@ __global__ __launch_bounds__(kScanThreads) void block_sums_kernel(const uint32_t
 
 __global__ __launch_bounds__(kScanThreads) void scan_apply_kernel(const uint32_t *counts, uint64_t ntiles,
                                                                   const uint64_t *sums, uint64_t nblocks,
-                                                                  uint64_t *offs, uint64_t *total)
+                                                                  uint64_t *offs, uint64_t *total,
+                                                                  const uint64_t *base_in)
 {
     __shared__ uint64_t wsum[kScanThreads / 64];
     __shared__ uint64_t base_sh;
@@ -58,14 +59,15 @@ __global__ __launch_bounds__(kScanThreads) void scan_apply_kernel(const uint32_t
         base_sh = x;
     }
     __syncthreads();
-    const uint64_t base = base_sh;
+    const uint64_t b0 = base_in != nullptr ? *base_in : 0ull;
+    const uint64_t base = b0 + base_sh;
     __syncthreads();
     if (lane == 0) wsum[wv] = all;
     __syncthreads();
     if (blockIdx.x == 0 && threadIdx.x == 0 && total != nullptr) {
         uint64_t x = 0;
         for (int w = 0; w < kScanThreads / 64; ++w) x += wsum[w];
-        *total = x;
+        *total = b0 + x;
     }
     __syncthreads();
     // this thread's kScanPerThread consecutive counts
@@ -88,14 +90,14 @@ __global__ __launch_bounds__(kScanThreads) void scan_apply_kernel(const uint32_t
 }
 
 hipError_t launch_scan_counts(const uint32_t *counts, uint64_t ntiles, uint64_t *offs, uint64_t *count,
-                              uint64_t *sums, hipStream_t s)
+                              uint64_t *sums, hipStream_t s, const uint64_t *base)
 {
     const uint64_t nb = (ntiles + kScanBlock - 1) / kScanBlock;
     hipLaunchKernelGGL(block_sums_kernel, dim3((uint32_t)nb), dim3(kScanThreads), 0, s, counts, ntiles, sums);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(scan_apply_kernel, dim3((uint32_t)nb), dim3(kScanThreads), 0, s, counts, ntiles, sums, nb,
-                       offs, count);
+                       offs, count, base);
     return hipGetLastError();
 }
 
@@ -109,6 +111,7 @@ struct ListArgs {
     uint64_t *list;
     uint64_t cap;
     uint64_t ntiles;
+    uint64_t rho0;
     uint32_t tw;
     int n;
 };
@@ -128,14 +131,15 @@ __global__ __launch_bounds__(kListThreads) void list_kernel(ListArgs a)
         const uint64_t off = a.offs[tile];
         if (c == 0 || off >= a.cap) continue;
         list_tile(a.state + tile * a.tw, a.tw, words, tile * a.tw, off, a.chunkmap + tile * kMapWords, a.list, a.cap,
-                  nzs[wv]);
+                  nzs[wv], a.rho0);
     }
 }
 
 hipError_t launch_list(int n, const uint32_t *state, uint32_t tw, uint64_t ntiles, const uint32_t *counts,
-                       const uint32_t *chunkmap, const uint64_t *offs, uint64_t *list, uint64_t cap, hipStream_t s)
+                       const uint32_t *chunkmap, const uint64_t *offs, uint64_t *list, uint64_t cap, hipStream_t s,
+                       uint64_t rho0)
 {
-    ListArgs a{state, counts, chunkmap, offs, list, cap, ntiles, tw, n};
+    ListArgs a{state, counts, chunkmap, offs, list, cap, ntiles, rho0, tw, n};
     const uint64_t waves = (ntiles + 3) / 4;
     uint64_t g = waves < 8192 ? waves : 8192;
     hipLaunchKernelGGL(list_kernel, dim3((uint32_t)(g == 0 ? 1 : g)), dim3(kListThreads), 0, s, a);

@@ -41,14 +41,18 @@ constexpr int kLowThreads = 256;
 hipError_t low_setup();
 
 // Exclusive scan of the tile counts into offs (uint64, one per tile) and the
-// total into *count.
+// total into *count.  With base != nullptr every offset and the total start
+// at *base (a list continued from an earlier call; base != count).
 hipError_t launch_scan_counts(const uint32_t *counts, uint64_t ntiles, uint64_t *offs, uint64_t *count,
-                              uint64_t *sums, hipStream_t s);
+                              uint64_t *sums, hipStream_t s, const uint64_t *base = nullptr);
 uint64_t scan_scratch_words(uint64_t ntiles);  // size of `sums`
 // List of the set bits of the tiles in increasing cube index, using the tile
 // summaries and offsets (only chunks marked non-zero are read).
+// rho0 is added to every listed cube index (a slice's place in a larger
+// function).
 hipError_t launch_list(int n, const uint32_t *state, uint32_t tw, uint64_t ntiles, const uint32_t *counts,
-                       const uint32_t *chunkmap, const uint64_t *offs, uint64_t *list, uint64_t cap, hipStream_t s);
+                       const uint32_t *chunkmap, const uint64_t *offs, uint64_t *list, uint64_t cap, hipStream_t s,
+                       uint64_t rho0 = 0);
 hipError_t launch_low(int mode, const LowArgs &a, uint64_t nblocks, hipStream_t s);
 
 // High-digit groups: one pass applies Merge and/or Reduce for a group of
@@ -145,6 +149,15 @@ inline void tile_layout(const BatchJob *jobs, uint32_t m, TileJob *tj, uint32_t 
     b.nbin = nbin;
     b.ntiles = ntiles;
 }
+
+// Sliced path (k_slice.hip): the truth table of the restriction of f to the
+// cube of its top variables given by fixed (bits equal to 1) and stars (bits
+// that are *), on its lower m variables; and o &= ~mask on the chunks of each
+// tile that the tile summary marks, with a new summary.
+hipError_t launch_slice_tt(const uint32_t *tt, int m, uint32_t fixed, uint32_t stars, uint32_t flip, uint32_t *out,
+                           hipStream_t s);
+hipError_t launch_andnot_map(uint32_t *o, const uint32_t *mask, uint32_t *counts, uint32_t *chunkmap, uint64_t ntiles,
+                             uint32_t tw, hipStream_t s);
 
 hipError_t launch_fill_u64(uint64_t *p, uint64_t count, uint64_t value, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint64_t count, uint32_t value, hipStream_t s);

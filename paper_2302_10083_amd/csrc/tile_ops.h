@@ -224,7 +224,8 @@ __device__ __forceinline__ void reduce_full_tile(uint32_t *t, uint32_t *tile, ui
 constexpr int kListBatch = 16;  // chunks whose words are loaded together
 
 __device__ __forceinline__ void list_tile(const uint32_t *src, uint32_t tw, bool words, uint64_t wbase, uint64_t off,
-                                          const uint32_t *map, uint64_t *list, uint64_t cap, uint16_t *nz)
+                                          const uint32_t *map, uint64_t *list, uint64_t cap, uint16_t *nz,
+                                          uint64_t rho0 = 0)
 {
     const uint32_t lane = lane_id();
     const uint32_t mw = lane < (uint32_t)kMapWords ? map[lane] : 0u;
@@ -255,7 +256,7 @@ __device__ __forceinline__ void list_tile(const uint32_t *src, uint32_t tw, bool
                 const uint32_t inc = wave_inclusive_scan32(cc);
                 uint64_t p = run + (inc - cc);
                 const uint64_t w = (uint64_t)nz[r0 + i] * kChunkWords + lane;
-                const uint64_t rbase = words ? 27ull * (wbase + w) : 0ull;
+                const uint64_t rbase = rho0 + (words ? 27ull * (wbase + w) : 0ull);
                 while (x != 0u && p < cap) {
                     const uint32_t b = __builtin_ctz(x);
                     x &= x - 1u;

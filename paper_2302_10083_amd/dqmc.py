@@ -47,6 +47,8 @@ DQMC_MAX_RECORDS = 64
 DQMC_MAX_PLAN_TRIALS = 64
 DQMC_NEGATE = 1
 DQMC_SPARSE_MAX_N = 31
+DQMC_SLICED_MAX_N = 30
+DQMC_SLICED_MAX_T = 8
 
 
 class dqmc_result(ctypes.Structure):
@@ -110,6 +112,7 @@ def load():
             "dqmc_sparse_primes": (i32, [vp, i32, vp, vp, u64, vp, vp, u64, ctypes.POINTER(ctypes.c_uint64), vp]),
             "dqmc_primes_ex": (i32, [vp, i32, vp, ctypes.c_uint32, vp, vp, u64, vp, vp]),
             "dqmc_extract": (i32, [vp, i32, vp, vp, u64, vp, vp]),
+            "dqmc_primes_sliced": (i32, [vp, i32, i32, vp, ctypes.c_uint32, vp, vp, vp, u64, vp, vp]),
             "dqmc_bitmap_to_dense": (i32, [vp, i32, vp, vp, vp]),
             "dqmc_primes_batch": (i32, [vp, ctypes.POINTER(dqmc_job), ctypes.c_int32, vp]),
             "dqmc_profile": (i32, [vp, i32]),
@@ -279,6 +282,21 @@ def dqmc_sparse_primes(ctx, n, tt, lst, list_cap, count, work, stream=None):
     if rc != DQMC_ENOMEM:
         _check(ctx, rc)
     return rc, int(need[0]), int(need[1])
+
+
+def dqmc_primes_sliced(ctx, n, t, tt, flags, o_state, m_state, lst, list_cap, count, stream=None) -> None:
+    """Sliced path (see include/dqmc.h): o_state and m_state each hold
+    dqmc_state_words(n - t) words."""
+    import torch
+
+    cap = 0 if lst is None else int(list_cap)
+    ok = 1 <= t <= DQMC_SLICED_MAX_T and t <= n <= DQMC_SLICED_MAX_N and n - t <= DQMC_MAX_N
+    nw = max(1, (1 << n) // 32) if ok else 1  # the library rejects other n, t
+    sw = dqmc_state_words(n - t) if ok else 1
+    _check(ctx, load().dqmc_primes_sliced(
+        ctx, n, t, _ptr(tt, "tt", torch.int32, nw), int(flags), _ptr(o_state, "o_state", torch.int32, sw),
+        _ptr(m_state, "m_state", torch.int32, sw), _ptr(lst, "list", torch.int64, cap), cap,
+        _ptr(count, "count", torch.int64, 1), _stream(stream)))
 
 
 def dqmc_extract(ctx, n, state, lst, list_cap, count, stream=None) -> None:
@@ -580,6 +598,22 @@ class Context:
         if rc != DQMC_OK:
             raise DqmcError(rc, "sparse path failed on the second run")
         return lst[:c], count
+
+    def sliced_primes(self, n, t, tt, list_cap=None, flags=0, states=None, stream=None):
+        """(list, count) of the sliced path with slices of n - t variables.
+        states: (o_state, m_state), else allocated here.  With list_cap None
+        a count-only call sizes the list first (the work runs twice)."""
+        import torch
+
+        if states is None:
+            states = (self.new_state(n - t), self.new_state(n - t))
+        count = torch.zeros(1, dtype=torch.int64, device=self.torch_device)
+        if list_cap is None:
+            dqmc_primes_sliced(self.ctx, n, t, tt, flags, states[0], states[1], None, 0, count, stream)
+            list_cap = int(count.item())
+        lst = torch.empty(max(int(list_cap), 1), dtype=torch.int64, device=self.torch_device)
+        dqmc_primes_sliced(self.ctx, n, t, tt, flags, states[0], states[1], lst, list_cap, count, stream)
+        return lst[:int(list_cap)], count
 
     def extract(self, n, state, list_cap, stream=None):
         import torch

@@ -395,3 +395,42 @@ def test_cnf_clauses_reproduce_f(n, p, seed):
         assert not np.any(covered & f), "a clause of f is violated by a true point"
         conj &= ~covered
     assert np.array_equal(conj, f)
+
+
+def _restrict(n, t, tt, a_digits):
+    """Truth table (bool array over x_1..x_m) of f_a: the AND of f over the
+    minterms of the cube a on the top t variables."""
+    m = n - t
+    bits = np.unpackbits(np.asarray(tt, dtype=np.uint32).view(np.uint8), bitorder="little")[: 1 << n].astype(bool)
+    out = np.ones(1 << m, dtype=bool)
+    for xt in range(1 << t):
+        if all(d == 2 or ((xt >> j) & 1) == d for j, d in enumerate(a_digits)):
+            out &= bits[xt << m: (xt + 1) << m]
+    return inputs.from_bits(m, out)
+
+
+@pytest.mark.parametrize("n,t,p,seed", [(5, 1, 0.7, 1), (6, 2, 0.8, 2), (7, 3, 0.9, 3), (8, 2, 0.6, 4),
+                                        (8, 4, 0.95, 5), (9, 1, 0.85, 6)])
+def test_top_digit_slicing_identity(n, t, p, seed):
+    """The decomposition the sliced GPU path relies on, checked with whole
+    bitmaps: cube s.a (a on the top t variables) is prime for f exactly when
+    s is prime for f_a and, for every binary digit j of a, s is not an
+    implicant of f_a' (a with digit j flipped)."""
+    tt = inputs.bernoulli(n, p, 9100 + seed)
+    _, O, _ = oracle.primes(n, tt)
+    full = oracle.bitmap_to_set(n, O)
+    m = n - t
+    got = set()
+    for idx in range(3**t):
+        a = [(idx // 3**j) % 3 for j in range(t)]
+        _, Oa, _ = oracle.primes(m, _restrict(n, t, tt, a))
+        keep = oracle.bitmap_to_set(m, Oa)
+        for j, d in enumerate(a):
+            if d != 2:
+                flipped = list(a)
+                flipped[j] = 1 - d
+                Mj = oracle.enum_M(m, _restrict(n, t, tt, flipped))
+                keep -= oracle.bitmap_to_set(m, Mj)
+        got |= {s + idx * 3**m for s in keep}
+    assert got == full
+    assert len(full) > 0
