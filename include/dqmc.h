@@ -151,14 +151,14 @@ int dqmc_sparse_primes(dqmc_ctx *ctx, int n, const uint32_t *d_tt, uint64_t *d_l
  * f_a is the function of x_1..x_m that ANDs f over the minterms of a.  The
  * cube s.a (digits 1..m from s, m+1..n from a) is an implicant of f iff s is
  * an implicant of f_a, so MergeAll (Sec. 4.1) of slice a is MergeAll of f_a.
- * Reduce along a top digit j with a_j binary (Sec. 4.1, Def. of Reduce)
- * removes s.a when s is also an implicant of f_a' (a' = a with digit j
- * flipped 0 <-> 1).  Hence
+ * The one-step form of ReduceAll (Sec. 4.1, Lemma) splits into the low
+ * digits, which give the primes of f_a, and the top digits:
  *     s.a is prime  <=>  s is a prime of f_a and, for every binary digit j
- *                        of a, s is not an implicant of f_a'.
+ *                        of a, s is not an implicant of f_{a[j <- *]}.
  * Per slice, in increasing order of a (as a base-3 number, * = 2): the primes
- * of f_a into d_o, for every binary digit j the implicants of f_a' into d_m
- * and d_o &= ~d_m, then the slice's primes are appended to the list.
+ * of f_a into d_o; for every binary digit j the implicants of f_{a[j <- *]}
+ * into d_m (kept from the previous slice when it is the same function) and
+ * d_o &= ~d_m; then the slice's primes are appended to the list.
  *   d_tt      device, the n-variable truth table: 2^(n-5) words (1 for n < 5).
  *   flags     0 or DQMC_NEGATE (the primes of NOT f).
  *   d_o, d_m  device, dqmc_state_words(n - t) words each: slice states, used

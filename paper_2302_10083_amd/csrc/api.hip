@@ -239,6 +239,35 @@ int enqueue_reduce_high(dqmc_ctx *ctx, int n, const uint32_t *tt, uint32_t flip,
     return DQMC_OK;
 }
 
+// A cube on the top t variables of the sliced path: bits where it is 1, and
+// bits where it is *.
+struct SliceKey {
+    uint32_t fixed;
+    uint32_t stars;
+    bool operator==(const SliceKey &o) const { return fixed == o.fixed && stars == o.stars; }
+};
+
+// Slice idx (its digits in base 3, * = 2) as a key.
+SliceKey slice_key(uint64_t idx, int t)
+{
+    SliceKey k{0u, 0u};
+    for (int j = 0; j < t; ++j, idx /= 3) {
+        if (idx % 3 == 1) k.fixed |= 1u << j;
+        if (idx % 3 == 2) k.stars |= 1u << j;
+    }
+    return k;
+}
+
+// The slices a[j <- *] for the binary digits j of slice idx.
+std::vector<SliceKey> star_neighbours(uint64_t idx, int t)
+{
+    const SliceKey a = slice_key(idx, t);
+    std::vector<SliceKey> out;
+    for (int j = 0; j < t; ++j)
+        if (((a.stars >> j) & 1u) == 0u) out.push_back(SliceKey{a.fixed & ~(1u << j), a.stars | (1u << j)});
+    return out;
+}
+
 }  // namespace
 
 extern "C" {
@@ -386,13 +415,11 @@ int dqmc_primes_sliced(dqmc_ctx *ctx, int n, int t, const uint32_t *d_tt, uint32
     const LowArgs la = low_args(ctx, m);
     const uint64_t nslices = pow3(t), slice_cubes = pow3(m);
     const double ttb = tt_bytes(m);
+    SliceKey m_key{0u, 0u};  // the function whose implicants d_m holds
+    bool m_valid = false;
     for (uint64_t idx = 0; idx < nslices; ++idx) {
-        uint32_t fixed = 0, stars = 0;
-        uint64_t r = idx;
-        for (int j = 0; j < t; ++j, r /= 3) {
-            if (r % 3 == 1) fixed |= 1u << j;
-            if (r % 3 == 2) stars |= 1u << j;
-        }
+        const SliceKey a_key = slice_key(idx, t);
+        const uint32_t fixed = a_key.fixed, stars = a_key.stars;
         const double sub = (double)(1u << __builtin_popcount(stars));
         // primes of f_a into d_o, with the tile summaries
         rc = run_pass(ctx, s, "slice_tt", m, ttb * (sub + 1.0), 0,
@@ -410,23 +437,47 @@ int dqmc_primes_sliced(dqmc_ctx *ctx, int n, int t, const uint32_t *d_tt, uint32
             if (rc == DQMC_OK) rc = enqueue_summary(ctx, m, kLowReduceCount, d_o, s);
         }
         if (rc != DQMC_OK) return rc;
-        // Reduce along each binary top digit: drop what f_a' also implies
-        for (int j = 0; j < t; ++j) {
-            if ((stars >> j) & 1u) continue;
-            const uint32_t fx = fixed ^ (1u << j);
-            rc = run_pass(ctx, s, "slice_tt", m, ttb * (sub + 1.0), 0,
-                          [&] { return launch_slice_tt(d_tt, m, fx, stars, flip, ctx->slice_tt, s); });
-            if (rc != DQMC_OK) return rc;
-            if (m <= kLowDigits) {
-                LowArgs a = la;
-                a.tt = ctx->slice_tt;
-                a.state = d_m;
-                rc = run_pass(ctx, s, "low_merge_tt", m, ttb + state_bytes(m), 0,
-                              [&] { return launch_low(kLowMergeTT, a, 1, s); });
-            } else {
-                rc = enqueue_merge(ctx, m, ctx->slice_tt, 0u, d_m, false, s);
+        // Reduce along each binary top digit j: drop s where s.a[j <- *] is
+        // an implicant, i.e. where M of the star neighbour's function is set.
+        // That bitmap stays in d_m, so the neighbours are ordered to reuse it:
+        // first the one already there, last one that the next slice needs.
+        std::vector<SliceKey> need = star_neighbours(idx, t);
+        size_t lo = 0;  // need[0..lo) keeps its place
+        for (size_t i = 0; m_valid && i < need.size(); ++i) {
+            if (need[i] == m_key) {
+                std::swap(need[0], need[i]);
+                lo = 1;
+                break;
             }
-            if (rc != DQMC_OK) return rc;
+        }
+        if (need.size() > lo + 1 && idx + 1 < nslices) {
+            const std::vector<SliceKey> next = star_neighbours(idx + 1, t);
+            for (size_t i = lo; i + 1 < need.size(); ++i) {
+                if (std::find(next.begin(), next.end(), need[i]) != next.end()) {
+                    std::swap(need[i], need.back());
+                    break;
+                }
+            }
+        }
+        for (const SliceKey &k : need) {
+            if (!m_valid || !(k == m_key)) {
+                const double ksub = (double)(1u << __builtin_popcount(k.stars));
+                rc = run_pass(ctx, s, "slice_tt", m, ttb * (ksub + 1.0), 0,
+                              [&] { return launch_slice_tt(d_tt, m, k.fixed, k.stars, flip, ctx->slice_tt, s); });
+                if (rc != DQMC_OK) return rc;
+                if (m <= kLowDigits) {
+                    LowArgs a = la;
+                    a.tt = ctx->slice_tt;
+                    a.state = d_m;
+                    rc = run_pass(ctx, s, "low_merge_tt", m, ttb + state_bytes(m), 0,
+                                  [&] { return launch_low(kLowMergeTT, a, 1, s); });
+                } else {
+                    rc = enqueue_merge(ctx, m, ctx->slice_tt, 0u, d_m, false, s);
+                }
+                if (rc != DQMC_OK) return rc;
+                m_key = k;
+                m_valid = true;
+            }
             // data dependent (only the marked chunks are read); the model
             // counts the summaries
             rc = run_pass(ctx, s, "andnot_map", m, la.ntiles * 8.0 * (1 + kMapWords), 0, [&] {

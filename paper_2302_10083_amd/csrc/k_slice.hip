@@ -5,12 +5,11 @@
 // the function of the lower m = n - t variables that is the AND of f over the
 // minterms of a.  A cube (s, a) is an implicant of f exactly when s is an
 // implicant of f_a, so the Merge transform of Sec. 4.1 restricted to slice a
-// is the whole MergeAll of f_a.  Reduce on a top digit j with a_j binary
-// removes (s, a) when (s, a[j <- *]) is an implicant, i.e. when s is an
-// implicant of f_a AND f_a' (a' = a with a_j flipped); on a prime of f_a that
-// is the same as s being an implicant of f_a'.  So
-//     O(f)[s, a] = O(f_a)[s] AND NOT OR_{j: a_j binary} M(f_a')[s],
-// which needs two slice-sized states at a time: O(f_a) and one M(f_a').
+// is the whole MergeAll of f_a.  In the one-step form of ReduceAll (Sec. 4.1,
+// Lemma) the low digits give the primes of f_a, and a top digit j with a_j
+// binary removes (s, a) when (s, a[j <- *]) is an implicant.  So
+//     O(f)[s, a] = O(f_a)[s] AND NOT OR_{j: a_j binary} M(f_{a[j <- *]})[s],
+// which needs two slice-sized states at a time: O(f_a) and one M.
 #include <algorithm>
 
 #include "launch.h"

@@ -415,7 +415,7 @@ def test_top_digit_slicing_identity(n, t, p, seed):
     """The decomposition the sliced GPU path relies on, checked with whole
     bitmaps: cube s.a (a on the top t variables) is prime for f exactly when
     s is prime for f_a and, for every binary digit j of a, s is not an
-    implicant of f_a' (a with digit j flipped)."""
+    implicant of f_{a[j <- *]}."""
     tt = inputs.bernoulli(n, p, 9100 + seed)
     _, O, _ = oracle.primes(n, tt)
     full = oracle.bitmap_to_set(n, O)
@@ -427,9 +427,9 @@ def test_top_digit_slicing_identity(n, t, p, seed):
         keep = oracle.bitmap_to_set(m, Oa)
         for j, d in enumerate(a):
             if d != 2:
-                flipped = list(a)
-                flipped[j] = 1 - d
-                Mj = oracle.enum_M(m, _restrict(n, t, tt, flipped))
+                starred = list(a)
+                starred[j] = 2
+                Mj = oracle.enum_M(m, _restrict(n, t, tt, starred))
                 keep -= oracle.bitmap_to_set(m, Mj)
         got |= {s + idx * 3**m for s in keep}
     assert got == full
