@@ -253,6 +253,71 @@ def bench_sliced(ctx, workload="c3x_n26_dnf2000_noise", ts=(2, 1), reps=2):
     return out
 
 
+def bench_configs(ctx, n24_tt=None, n24_list=None):
+    """The smaller named workloads: n = 12 latency (median of 1000 calls) and
+    n = 20 (median of 5), plus the host transfers the main step leaves out
+    (truth table in, prime list out, pinned host memory)."""
+    import numpy as np
+    import torch
+
+    from paper_2302_10083_amd import dqmc, inputs
+
+    dev = ctx.torch_device
+    out = {}
+    for name, reps in (("c1_n12_bern05", 1000), ("c2a_n20_bern09", 5), ("c2b_n20_dnf200", 5)):
+        spec = inputs.CONFIGS[name]
+        n = spec["n"]
+        ttd = ctx.tt_to_device(inputs.make(spec))
+        state = ctx.new_state(n)
+        count = torch.zeros(1, dtype=torch.int64, device=dev)
+        dqmc.dqmc_primes(ctx.ctx, n, ttd, state, None, 0, count)
+        torch.cuda.synchronize()
+        c = int(count.item())
+        lst = torch.empty(max(c, 1), dtype=torch.int64, device=dev)
+        dqmc.dqmc_primes(ctx.ctx, n, ttd, state, lst, c, count)  # warm-up
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for a, b in ev:
+            a.record()
+            dqmc.dqmc_primes(ctx.ctx, n, ttd, state, lst, c, count)
+            b.record()
+        torch.cuda.synchronize()
+        ms = np.array([a.elapsed_time(b) for a, b in ev])
+        med = float(np.median(ms))
+        row = {"n": n, "primes": c, "reps": reps, "median_ms": med, "p90_ms": float(np.percentile(ms, 90)),
+               "cubes_per_s": 3**n / (med / 1e3)}
+        if n == 12:
+            row["median_us"] = med * 1e3
+        out[name] = row
+        print("bench: %s median %.4f ms" % (name, med), file=sys.stderr, flush=True)
+        del state, lst
+    if n24_tt is not None:
+        # PCIe legs of the n = 24 workload, outside the timed step
+        h_tt = torch.from_numpy(np.asarray(n24_tt, dtype=np.uint32).view(np.int32)).pin_memory()
+        d_tt = torch.empty_like(h_tt, device=dev)
+        h_list = torch.empty(n24_list.numel(), dtype=torch.int64, pin_memory=True)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        d_tt.copy_(h_tt, non_blocking=True)
+        h_list.copy_(n24_list, non_blocking=True)
+        torch.cuda.synchronize()
+        a.record()
+        d_tt.copy_(h_tt, non_blocking=True)
+        b.record()
+        torch.cuda.synchronize()
+        ms_in = a.elapsed_time(b)
+        a.record()
+        h_list.copy_(n24_list, non_blocking=True)
+        b.record()
+        torch.cuda.synchronize()
+        ms_out = a.elapsed_time(b)
+        out["n24_host_transfers"] = {"tt_h2d_ms": ms_in, "tt_bytes": h_tt.numel() * 4, "list_d2h_ms": ms_out,
+                                     "list_bytes": h_list.numel() * 8,
+                                     "list_d2h_GBps": h_list.numel() * 8 / (ms_out / 1e3) / 1e9}
+        print("bench: n=24 truth table in %.3f ms, list out %.2f ms" % (ms_in, ms_out), file=sys.stderr, flush=True)
+        del d_tt, h_tt, h_list
+    torch.cuda.empty_cache()
+    return out
+
+
 def bench_serving(nreq=200, seed=25):
     """Serving mix (n in {10,14,18,22,25} with weights .4/.3/.15/.1/.05):
     saturation throughput from a closed loop, then Poisson arrivals at 0.5 and
@@ -360,6 +425,7 @@ def main():
     ap.add_argument("--no-cnf", action="store_true")
     ap.add_argument("--no-sparse", action="store_true")
     ap.add_argument("--no-sliced", action="store_true")
+    ap.add_argument("--no-configs", action="store_true")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -498,6 +564,8 @@ def main():
                       "clauses_equal_dnf_primes": int(count.item()) == nprimes}
         del sd
         print("bench: cnf %.2f ms" % ms_cnf, file=sys.stderr, flush=True)
+    if not args.no_configs:
+        out["configs"] = bench_configs(ctx, tt if n == 24 else None, lst[:nprimes] if n == 24 else None)
     if not args.no_batch or not args.no_sparse or not args.no_sliced:
         del lst, state
         torch.cuda.empty_cache()

@@ -26,4 +26,32 @@ __host__ __device__ constexpr int col_threads()
     return GW == 0 ? 256 : 64 * (int)pow3(GW);
 }
 
+// Occupancy caps.  A column pass writes 256-byte row segments that start at
+// multiples of 3^(g0-4) words, off the 128-byte lines, so the lines at their
+// edges are shared with the neighbouring blocks.  Stores of that shape run
+// faster with few workgroups per CU (a store-only probe on MI355X: 4.9 TB/s
+// at one workgroup per CU, 2.6 TB/s at full occupancy), and so do several of
+// the passes, with fewer workgroups than registers and LDS would allow.  A
+// launch enforces its cap by asking for unused dynamic LDS: at most `wgs`
+// workgroups of (static + dynamic) LDS fit in the 160 KB of a CU.
+inline size_t lds_bytes_for_cap(int wgs)
+{
+    return wgs <= 1 ? 88 * 1024 : wgs == 2 ? 64 * 1024 : 48 * 1024;
+}
+
+// Dynamic LDS that caps `kernel` at `wgs` workgroups per CU (0: no cap),
+// with the kernel's dynamic-LDS limit raised to match.
+inline hipError_t occupancy_cap(const void *kernel, int wgs, size_t *pad)
+{
+    *pad = 0;
+    if (wgs <= 0) return hipSuccess;
+    hipFuncAttributes fa;
+    hipError_t e = hipFuncGetAttributes(&fa, kernel);
+    if (e != hipSuccess) return e;
+    const size_t want = lds_bytes_for_cap(wgs);
+    if (fa.sharedSizeBytes >= want) return hipSuccess;
+    *pad = want - fa.sharedSizeBytes;
+    return hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)*pad);
+}
+
 }  // namespace dqmc

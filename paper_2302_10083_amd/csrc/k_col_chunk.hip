@@ -10,10 +10,11 @@ namespace dqmc {
 
 // The same passes with the column processed in three chunks over its top
 // register digit (27 rows in flight instead of 81): used for groups with at
-// most one wave digit, where it needs far fewer registers (n = 25: the
-// merge of digits 18..21 runs in 6.5 ms instead of 9.3 ms).  With two wave
-// digits the whole-column kernel of k_col.hip is faster (n = 24: 10.3 ms
-// against 12.8 ms for the top group), so it keeps those groups.
+// most one wave digit, where it needs far fewer registers (n = 25, without
+// occupancy caps: the merge of digits 18..21 in 6.5 ms instead of 9.3 ms).
+// With two wave digits the whole-column kernel of k_col.hip is faster
+// (n = 24: 10.3 ms against 12.8 ms for the top group), so it keeps those
+// groups.
 template <int GR, int GW, int MODE>
 __global__ __launch_bounds__(col_threads<GW>()) void col_chunk_kernel(ColArgs a)
 {
@@ -209,17 +210,49 @@ __global__ __launch_bounds__(col_threads<GW>()) void col_chunk_kernel(ColArgs a)
 
 #undef ROW
 
+// Dynamic LDS per mode for the four-register-digit groups (the large ones),
+// set by chunk_setup to cap the workgroups per CU.  Measured at n = 25
+// (state 125.5 GB): with no wave digit, two workgroups per CU (merge+reduce
+// of digits 22..25 37.4 -> 28.6 ms, reduce of 18..21 45.7 -> 42.9 ms, merge
+// of 18..21 6.5 -> 5.1 ms); with one wave digit, two per CU for the merge
+// modes (1.41 -> 0.99 ms for digits 13..17) and three for the reduce
+// (44.9 -> 43.1 ms).
+static size_t g_pad40[3] = {0, 0, 0};
+static size_t g_pad41[3] = {0, 0, 0};
+
 template <int GR, int GW>
 static hipError_t launch_chunk_gw(int mode, const ColArgs &a, hipStream_t s)
 {
     const dim3 grid((uint32_t)a.nblocks), block(col_threads<GW>());
+    const size_t pad = GR != 4 ? 0 : GW == 0 ? g_pad40[mode] : g_pad41[mode];
     switch (mode) {
-    case kColMerge: hipLaunchKernelGGL((col_chunk_kernel<GR, GW, kColMerge>), grid, block, 0, s, a); break;
-    case kColMergeReduce: hipLaunchKernelGGL((col_chunk_kernel<GR, GW, kColMergeReduce>), grid, block, 0, s, a); break;
-    case kColReduce: hipLaunchKernelGGL((col_chunk_kernel<GR, GW, kColReduce>), grid, block, 0, s, a); break;
+    case kColMerge: hipLaunchKernelGGL((col_chunk_kernel<GR, GW, kColMerge>), grid, block, pad, s, a); break;
+    case kColMergeReduce: hipLaunchKernelGGL((col_chunk_kernel<GR, GW, kColMergeReduce>), grid, block, pad, s, a); break;
+    case kColReduce: hipLaunchKernelGGL((col_chunk_kernel<GR, GW, kColReduce>), grid, block, pad, s, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+hipError_t chunk_setup()
+{
+    const struct {
+        const void *k;
+        int wgs;
+        size_t *pad;
+    } caps[] = {
+        {(const void *)col_chunk_kernel<4, 0, kColMerge>, 2, &g_pad40[kColMerge]},
+        {(const void *)col_chunk_kernel<4, 0, kColMergeReduce>, 2, &g_pad40[kColMergeReduce]},
+        {(const void *)col_chunk_kernel<4, 0, kColReduce>, 2, &g_pad40[kColReduce]},
+        {(const void *)col_chunk_kernel<4, 1, kColMerge>, 2, &g_pad41[kColMerge]},
+        {(const void *)col_chunk_kernel<4, 1, kColMergeReduce>, 2, &g_pad41[kColMergeReduce]},
+        {(const void *)col_chunk_kernel<4, 1, kColReduce>, 3, &g_pad41[kColReduce]},
+    };
+    for (const auto &c : caps) {
+        const hipError_t e = occupancy_cap(c.k, c.wgs, c.pad);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_col_chunked(int gr, int gw, int mode, const ColArgs &a, hipStream_t s)

@@ -73,7 +73,8 @@ struct ColArgs {
     int outer_binary;    // 1: outer index enumerates binary digit combos
 };
 
-hipError_t col_setup();
+hipError_t col_setup();    // also runs chunk_setup
+hipError_t chunk_setup();  // occupancy caps of the chunked column kernel
 hipError_t launch_col(int gr, int gw, int mode, const ColArgs &a, hipStream_t s);
 // The chunked form (groups with at most one wave digit; launch_col picks it).
 hipError_t launch_col_chunked(int gr, int gw, int mode, const ColArgs &a, hipStream_t s);

@@ -95,6 +95,12 @@ def load():
             from . import build as _build
 
             _build.build()
+        # torch ships its own HIP runtime under the same soname as the
+        # system one.  Loaded first, it also serves libdqmc.so, so that the
+        # library and the tensors it is given share one runtime; loaded
+        # after the library, a second runtime would come up beside it.
+        import torch  # noqa: F401
+
         lib = ctypes.CDLL(LIB_PATH)
         u64, i32, vp = ctypes.c_uint64, ctypes.c_int, ctypes.c_void_p
         sig = {

@@ -70,3 +70,20 @@ def test_create_without_device_fails_cleanly():
     rc = lib.dqmc_create(0, ctypes.byref(out))
     assert rc in (dqmc.DQMC_EDEVICE, dqmc.DQMC_ENOMEM)
     assert not out.value
+
+
+def test_binding_shares_torchs_hip_runtime():
+    """Loading the library before torch is imported must not bring up a
+    second HIP runtime next to torch's own copy."""
+    import subprocess
+    import sys
+
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_2302_10083_amd import dqmc\n"
+            "dqmc.load()\n"
+            "import torch\n"
+            "maps = open('/proc/self/maps').read().splitlines()\n"
+            "print(len({l.split()[-1] for l in maps if 'libamdhip64' in l}))\n" % ROOT)
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip().splitlines()[-1] == "1"
