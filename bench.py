@@ -221,18 +221,21 @@ def bench_sliced(ctx, workload="c3x_n26_dnf2000_noise", ts=(2, 1), reps=2):
     lst = None
     for t in ts:
         need = 2 * 4 * 3 ** (n - t - 3)
-        free = torch.cuda.mem_get_info()[0]
-        if need + (16 << 30) > free:
-            out["rows"].append({"t": t, "skipped": "needs %.1f GB of slice states, %.1f GB free" % (need / 1e9,
-                                                                                                 free / 1e9)})
+        try:
+            o, m = ctx.new_state(n - t), ctx.new_state(n - t)
+            if lst is None:
+                dqmc.dqmc_primes_sliced(ctx.ctx, n, t, ttd, 0, o, m, None, 0, count)
+                torch.cuda.synchronize()
+                nprimes = int(count.item())
+                lst = torch.empty(max(nprimes, 1), dtype=torch.int64, device=dev)
+                out["primes"] = nprimes
+        except torch.cuda.OutOfMemoryError:
+            o = m = None
+            torch.cuda.empty_cache()
+            out["rows"].append({"t": t, "skipped": "%.1f GB of slice states (and the list) do not fit; %.1f GB "
+                                "free, %.1f GB held by torch" % (need / 1e9, torch.cuda.mem_get_info()[0] / 1e9,
+                                                                 torch.cuda.memory_reserved() / 1e9)})
             continue
-        o, m = ctx.new_state(n - t), ctx.new_state(n - t)
-        if lst is None:
-            dqmc.dqmc_primes_sliced(ctx.ctx, n, t, ttd, 0, o, m, None, 0, count)
-            torch.cuda.synchronize()
-            nprimes = int(count.item())
-            lst = torch.empty(max(nprimes, 1), dtype=torch.int64, device=dev)
-            out["primes"] = nprimes
         dqmc.dqmc_primes_sliced(ctx.ctx, n, t, ttd, 0, o, m, lst, nprimes, count)  # warm-up
         torch.cuda.synchronize()
         start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

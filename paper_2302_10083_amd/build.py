@@ -38,7 +38,28 @@ def build(verbose: bool = False) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
+    build_example(verbose)
     return LIB
+
+
+EXAMPLE_SRC = os.path.join(HERE, "examples", "c_primes.c")
+EXAMPLE_BIN = os.path.join(HERE, "examples", "c_primes")
+
+
+def build_example(verbose: bool = False) -> str:
+    """The plain-C user of the ABI (host code only, linked against libdqmc.so
+    and the system HIP runtime)."""
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    tmp = EXAMPLE_BIN + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(rocm, "include"),
+           "-I", os.path.join(ROOT, "include"), "-o", tmp, EXAMPLE_SRC, "-L", HERE, "-ldqmc",
+           "-L", os.path.join(rocm, "lib"), "-lamdhip64", "-Wl,-rpath,$ORIGIN/..",
+           "-Wl,-rpath," + os.path.join(rocm, "lib")]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    os.replace(tmp, EXAMPLE_BIN)
+    return EXAMPLE_BIN
 
 
 if __name__ == "__main__":
