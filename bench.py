@@ -462,7 +462,9 @@ def main():
     if not args.no_tune and n > 12:
         plan_trials = dqmc.dqmc_plan_autotune(ctx.ctx, n, ttd, state, count, extra_groups=args.tune_extra_groups,
                                               reps=1)
-        print("bench: plan autotune: %d plans, chosen %s" % (len(plan_trials), dqmc.dqmc_get_plan(ctx.ctx, n)),
+        print("bench: plan autotune: %d trials, chosen %s%s" % (len(plan_trials), dqmc.dqmc_get_plan(ctx.ctx, n),
+                                                                 " with the top-digit split"
+                                                                 if dqmc.dqmc_get_split(ctx.ctx, n) else ""),
               file=sys.stderr, flush=True)
 
     for _ in range(args.warmup):
@@ -526,7 +528,9 @@ def main():
         "wall_s_timed": wall,
         "passes": pass_rows,
         "plan": {"groups": dqmc.dqmc_get_plan(ctx.ctx, n), "passes_per_step": len(pass_rows),
-                 "autotune_trials": [[t["sizes"], round(t["ms"], 3)] for t in plan_trials]},
+                 "split_top_digit": dqmc.dqmc_get_split(ctx.ctx, n),
+                 "autotune_trials": [["split" if t["split"] else t["sizes"], round(t["ms"], 3)]
+                                     for t in plan_trials]},
         "roofline": {"bound": "hbm", "kernel": dom["name"], "achieved": achieved, "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
                      "traffic": traffic, "model_bytes_per_launch": dom_bytes},

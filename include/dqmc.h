@@ -309,6 +309,21 @@ int dqmc_hash_words(dqmc_ctx *ctx, const uint32_t *d_words, uint64_t nwords, uin
 int dqmc_set_plan(dqmc_ctx *ctx, int n, const int32_t *sizes, int ngroups);
 int dqmc_get_plan(const dqmc_ctx *ctx, int n, int32_t *sizes, int cap);
 
+/* Top-digit split of dqmc_primes / dqmc_primes_ex (12 < n <= 25): the
+ * n-variable state is computed as its three consecutive thirds, the slices
+ * of digit n = 0, 1, * (each an (n-1)-variable state of the same T27 layout),
+ * by the identity of dqmc_primes_sliced with t = 1: slice a holds the primes
+ * of f_a, and slices 0 and 1 lose the cubes that are implicants of
+ * f_* = f_0 AND f_1 (the Lemma of Sec. 4.1, one-step form, on digit n).
+ * While slices 0 and 1 are filtered, the * third holds those implicants.  The
+ * bitmap, list and count are the same as without the split; only the passes
+ * differ (those of n - 1 variables).  mode 1: split, 0: whole-state passes,
+ * -1: the default, which splits n = 25 only.  dqmc_get_split returns 1 if
+ * the split is in use for n, else 0.  Errors: DQMC_EINVAL for a bad n or
+ * mode. */
+int dqmc_set_split(dqmc_ctx *ctx, int n, int mode);
+int dqmc_get_split(const dqmc_ctx *ctx, int n);
+
 /* ---------------------------------------------------------------------------
  * Autotuning: measure the launch choices that leave results unchanged (the
  * batch bit-slicing launch of Sec. 4.2, the grouping of Alg. 4's top-layer
@@ -331,10 +346,13 @@ int dqmc_get_plan(const dqmc_ctx *ctx, int n, int32_t *sizes, int cap);
  * fewest groups up to that number plus extra_groups (0..2): every ordered
  * split of digits 13..n into groups of 1..6 digits, at most
  * DQMC_MAX_PLAN_TRIALS of them, by group count, then lexicographically by
- * sizes.  Each is timed on dqmc_primes without a list (the count goes to
- * d_count); the fastest is set with dqmc_set_plan.  d_state holds that
- * call's result afterwards.  If a run fails, the plan in force before the
- * call is restored.
+ * sizes; then the top-digit split (dqmc_set_split), reported as a trial with
+ * ngroups == 0.  Each is timed on dqmc_primes without a list (the count goes
+ * to d_count); the fastest group plan is set with dqmc_set_plan, and the
+ * split is switched on (1) if it beat that plan, off (0) otherwise.  d_state
+ * holds the last call's result afterwards.  If a run fails, the plan and
+ * split mode in force before the call are restored.  cap should leave room
+ * for the split trial: DQMC_MAX_PLAN_TRIALS + 1.
  */
 typedef struct {
     int32_t grid;

@@ -29,6 +29,10 @@ using namespace dqmc;
 namespace {
 
 constexpr int kLowDigits = 12;  // digits 1..12 live in one low tile
+// n at which dqmc_primes splits the top digit by default: its three
+// 24-variable slices take the two-group plan, which moves fewer bytes per
+// cube than any plan for 25 digits
+constexpr int kSplitDefaultN = 25;
 
 struct Group {
     int g0;  // first digit (1-based)
@@ -180,10 +184,12 @@ int enqueue_merge(dqmc_ctx *ctx, int n, const uint32_t *tt, uint32_t flip, uint3
 
 // The low-tile pass that ends a prime bitmap: reduce of digits 1..12 with the
 // tile summaries, or the summaries alone.
-int enqueue_summary(dqmc_ctx *ctx, int n, int mode, uint32_t *state, hipStream_t s)
+int enqueue_summary(dqmc_ctx *ctx, int n, int mode, uint32_t *state, hipStream_t s, uint64_t tile0 = 0)
 {
     LowArgs a = low_args(ctx, n);
     a.state = state;
+    a.counts += tile0;  // the summaries of a slice start at tile0 of a larger state
+    a.chunkmap += tile0 * kMapWords;
     const double S = state_bytes(n);
     const bool reduce = mode == kLowReduceCount;
     return run_pass(ctx, s, reduce ? "low_reduce_count" : "low_count", n,
@@ -237,6 +243,91 @@ int enqueue_reduce_high(dqmc_ctx *ctx, int n, const uint32_t *tt, uint32_t flip,
         if (rc != DQMC_OK) return rc;
     }
     return DQMC_OK;
+}
+
+// Slices of a function along its top variables (the sliced path and the
+// top-digit split) run the passes of an m-variable function on a restricted
+// truth table.  The tile summaries of the slice go to tiles tile0.. of the
+// context's summary arrays.
+
+// Primes of the m-variable function `tt` into `state`, with the summaries.
+int enqueue_slice_primes(dqmc_ctx *ctx, int m, const uint32_t *tt, uint32_t *state, uint64_t tile0, hipStream_t s)
+{
+    if (m <= kLowDigits) {
+        LowArgs a = low_args(ctx, m);
+        a.tt = tt;
+        a.state = state;
+        const int rc = run_pass(ctx, s, "low_primes_tt", m, tt_bytes(m) + state_bytes(m), 0,
+                                [&] { return launch_low(kLowPrimesTT, a, 1, s); });
+        return rc != DQMC_OK ? rc : enqueue_summary(ctx, m, kLowCount, state, s, tile0);
+    }
+    const int rc = enqueue_reduce_high(ctx, m, tt, 0u, state, s);
+    return rc != DQMC_OK ? rc : enqueue_summary(ctx, m, kLowReduceCount, state, s, tile0);
+}
+
+// Implicants of the m-variable function `tt` into `state`.
+int enqueue_slice_implicants(dqmc_ctx *ctx, int m, const uint32_t *tt, uint32_t *state, hipStream_t s)
+{
+    if (m <= kLowDigits) {
+        LowArgs a = low_args(ctx, m);
+        a.tt = tt;
+        a.state = state;
+        return run_pass(ctx, s, "low_merge_tt", m, tt_bytes(m) + state_bytes(m), 0,
+                        [&] { return launch_low(kLowMergeTT, a, 1, s); });
+    }
+    return enqueue_merge(ctx, m, tt, 0u, state, false, s);
+}
+
+// o &= ~mask on the marked chunks of a slice, with new summaries.
+int enqueue_slice_filter(dqmc_ctx *ctx, int m, uint32_t *o, const uint32_t *mask, uint64_t tile0, hipStream_t s)
+{
+    const LowArgs la = low_args(ctx, m);
+    // data dependent (only the marked chunks are read); the model counts the
+    // summaries
+    return run_pass(ctx, s, "andnot_map", m, la.ntiles * 8.0 * (1 + kMapWords), 0, [&] {
+        return launch_andnot_map(o, mask, ctx->counts + tile0, ctx->chunkmap + tile0 * kMapWords, la.ntiles, la.tw,
+                                 s);
+    });
+}
+
+// The truth table of slice (fixed, stars) of the top variables into the
+// context's slice buffer.
+int enqueue_slice_tt(dqmc_ctx *ctx, int m, const uint32_t *tt, uint32_t fixed, uint32_t stars, uint32_t flip,
+                     hipStream_t s)
+{
+    const double sub = (double)(1u << __builtin_popcount(stars));
+    return run_pass(ctx, s, "slice_tt", m, tt_bytes(m) * (sub + 1.0), 0,
+                    [&] { return launch_slice_tt(tt, m, fixed, stars, flip, ctx->slice_tt, s); });
+}
+
+// Top-digit split of dqmc_primes (n > 12): the state of n variables is three
+// consecutive slice states of m = n - 1 variables (digit n = 0, 1, *), and
+// its tiles are the slices' tiles in order.  Slices 0 and 1 are their
+// functions' primes minus the implicants of f_* = f_0 AND f_1 (the star
+// neighbour of both, held meanwhile in the * third); the * slice is the
+// primes of f_*.  One scan and list over all tiles follow.
+int enqueue_primes_split(dqmc_ctx *ctx, int n, const uint32_t *tt, uint32_t flip, uint32_t *state, uint64_t *list,
+                         uint64_t cap, uint64_t *count, hipStream_t s)
+{
+    const int m = n - 1;
+    const uint64_t third = dqmc_state_words(m), tiles = low_args(ctx, m).ntiles;
+    uint32_t *star = state + 2 * third;
+    int rc = enqueue_slice_tt(ctx, m, tt, 0u, 1u, flip, s);
+    if (rc == DQMC_OK) rc = enqueue_slice_implicants(ctx, m, ctx->slice_tt, star, s);
+    for (uint32_t a = 0; a < 3 && rc == DQMC_OK; ++a) {
+        uint32_t *o = state + a * third;
+        rc = enqueue_slice_tt(ctx, m, tt, a == 1 ? 1u : 0u, a == 2 ? 1u : 0u, flip, s);
+        if (rc == DQMC_OK) rc = enqueue_slice_primes(ctx, m, ctx->slice_tt, o, a * tiles, s);
+        if (rc == DQMC_OK && a < 2) rc = enqueue_slice_filter(ctx, m, o, star, a * tiles, s);
+    }
+    return rc != DQMC_OK ? rc : enqueue_scan_list(ctx, n, state, list, cap, count, nullptr, 0, s);
+}
+
+bool use_split(const dqmc_ctx *ctx, int n)
+{
+    if (n <= kLowDigits || n > DQMC_MAX_N) return false;
+    if (ctx->split[n] >= 0) return ctx->split[n] == 1;
+    return n == kSplitDefaultN;
 }
 
 // A cube on the top t variables of the sliced path: bits where it is 1, and
@@ -300,7 +391,10 @@ int dqmc_create(int device, dqmc_ctx **out)
     c->prof = false;
     c->events_made = false;
     c->nrec = 0;
-    for (int i = 0; i <= DQMC_MAX_N; ++i) c->plan_len[i] = 0;
+    for (int i = 0; i <= DQMC_MAX_N; ++i) {
+        c->plan_len[i] = 0;
+        c->split[i] = -1;
+    }
     if (hipMalloc((void **)&c->counts, c->tiles_cap * sizeof(uint32_t)) != hipSuccess ||
         hipMalloc((void **)&c->chunkmap, c->tiles_cap * kMapWords * sizeof(uint32_t)) != hipSuccess ||
         hipMalloc((void **)&c->offs, c->tiles_cap * sizeof(uint64_t)) != hipSuccess ||
@@ -385,9 +479,26 @@ int dqmc_primes_ex(dqmc_ctx *ctx, int n, const uint32_t *d_tt, uint32_t flags, u
         return run_pass(ctx, s, "low_primes_tt", n, tt_bytes(n) + state_bytes(n), d_list ? 8 : 0,
                         [&] { return launch_low(kLowPrimesTT, a, 1, s); });
     }
+    if (use_split(ctx, n)) return enqueue_primes_split(ctx, n, d_tt, flip, d_state, d_list, list_cap, d_count, s);
     rc = enqueue_reduce_high(ctx, n, d_tt, flip, d_state, s);
     if (rc != DQMC_OK) return rc;
     return enqueue_extract_tiles(ctx, n, kLowReduceCount, d_state, d_list, list_cap, d_count, s);
+}
+
+int dqmc_set_split(dqmc_ctx *ctx, int n, int mode)
+{
+    if (ctx == nullptr) return DQMC_EINVAL;
+    ctx->err[0] = 0;
+    if (n <= kLowDigits || n > DQMC_MAX_N || mode < -1 || mode > 1)
+        return fail(ctx, DQMC_EINVAL, "%s", "the split needs 12 < n <= 25 and mode -1, 0 or 1");
+    ctx->split[n] = mode;
+    return DQMC_OK;
+}
+
+int dqmc_get_split(const dqmc_ctx *ctx, int n)
+{
+    if (ctx == nullptr) return DQMC_EINVAL;
+    return use_split(ctx, n) ? 1 : 0;
 }
 
 int dqmc_primes_sliced(dqmc_ctx *ctx, int n, int t, const uint32_t *d_tt, uint32_t flags, uint32_t *d_o,
@@ -412,30 +523,15 @@ int dqmc_primes_sliced(dqmc_ctx *ctx, int n, int t, const uint32_t *d_tt, uint32
     const uint64_t sw = dqmc_state_words(m);
     if (d_o < d_m + sw && d_m < d_o + sw) return fail(ctx, DQMC_EINVAL, "%s", "the slice states overlap");
     hipStream_t s = (hipStream_t)stream;
-    const LowArgs la = low_args(ctx, m);
     const uint64_t nslices = pow3(t), slice_cubes = pow3(m);
-    const double ttb = tt_bytes(m);
     SliceKey m_key{0u, 0u};  // the function whose implicants d_m holds
     bool m_valid = false;
     for (uint64_t idx = 0; idx < nslices; ++idx) {
         const SliceKey a_key = slice_key(idx, t);
         const uint32_t fixed = a_key.fixed, stars = a_key.stars;
-        const double sub = (double)(1u << __builtin_popcount(stars));
         // primes of f_a into d_o, with the tile summaries
-        rc = run_pass(ctx, s, "slice_tt", m, ttb * (sub + 1.0), 0,
-                      [&] { return launch_slice_tt(d_tt, m, fixed, stars, flip, ctx->slice_tt, s); });
-        if (rc != DQMC_OK) return rc;
-        if (m <= kLowDigits) {
-            LowArgs a = la;
-            a.tt = ctx->slice_tt;
-            a.state = d_o;
-            rc = run_pass(ctx, s, "low_primes_tt", m, ttb + state_bytes(m), 0,
-                          [&] { return launch_low(kLowPrimesTT, a, 1, s); });
-            if (rc == DQMC_OK) rc = enqueue_summary(ctx, m, kLowCount, d_o, s);
-        } else {
-            rc = enqueue_reduce_high(ctx, m, ctx->slice_tt, 0u, d_o, s);
-            if (rc == DQMC_OK) rc = enqueue_summary(ctx, m, kLowReduceCount, d_o, s);
-        }
+        rc = enqueue_slice_tt(ctx, m, d_tt, fixed, stars, flip, s);
+        if (rc == DQMC_OK) rc = enqueue_slice_primes(ctx, m, ctx->slice_tt, d_o, 0, s);
         if (rc != DQMC_OK) return rc;
         // Reduce along each binary top digit j: drop s where s.a[j <- *] is
         // an implicant, i.e. where M of the star neighbour's function is set.
@@ -461,28 +557,13 @@ int dqmc_primes_sliced(dqmc_ctx *ctx, int n, int t, const uint32_t *d_tt, uint32
         }
         for (const SliceKey &k : need) {
             if (!m_valid || !(k == m_key)) {
-                const double ksub = (double)(1u << __builtin_popcount(k.stars));
-                rc = run_pass(ctx, s, "slice_tt", m, ttb * (ksub + 1.0), 0,
-                              [&] { return launch_slice_tt(d_tt, m, k.fixed, k.stars, flip, ctx->slice_tt, s); });
-                if (rc != DQMC_OK) return rc;
-                if (m <= kLowDigits) {
-                    LowArgs a = la;
-                    a.tt = ctx->slice_tt;
-                    a.state = d_m;
-                    rc = run_pass(ctx, s, "low_merge_tt", m, ttb + state_bytes(m), 0,
-                                  [&] { return launch_low(kLowMergeTT, a, 1, s); });
-                } else {
-                    rc = enqueue_merge(ctx, m, ctx->slice_tt, 0u, d_m, false, s);
-                }
+                rc = enqueue_slice_tt(ctx, m, d_tt, k.fixed, k.stars, flip, s);
+                if (rc == DQMC_OK) rc = enqueue_slice_implicants(ctx, m, ctx->slice_tt, d_m, s);
                 if (rc != DQMC_OK) return rc;
                 m_key = k;
                 m_valid = true;
             }
-            // data dependent (only the marked chunks are read); the model
-            // counts the summaries
-            rc = run_pass(ctx, s, "andnot_map", m, la.ntiles * 8.0 * (1 + kMapWords), 0, [&] {
-                return launch_andnot_map(d_o, d_m, ctx->counts, ctx->chunkmap, la.ntiles, la.tw, s);
-            });
+            rc = enqueue_slice_filter(ctx, m, d_o, d_m, 0, s);
             if (rc != DQMC_OK) return rc;
         }
         // append the slice's primes: offsets continue from the previous

@@ -27,6 +27,8 @@ struct dqmc_ctx {
     dqmc_pass_record rec[DQMC_MAX_RECORDS];
     // pass plan overrides: group sizes of digits 13..n (0 groups = default)
     int plan_len[DQMC_MAX_N + 1];
+    // top-digit split of dqmc_primes per n: -1 default, 0 off, 1 on
+    int split[DQMC_MAX_N + 1];
     int plan[DQMC_MAX_N + 1][DQMC_MAX_N];
 };
 

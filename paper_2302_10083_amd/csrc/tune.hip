@@ -130,14 +130,16 @@ int dqmc_plan_autotune(dqmc_ctx *ctx, int n, const uint32_t *d_tt, uint32_t *d_s
     std::vector<std::vector<int>> cands;
     std::vector<int> cur;
     for (int k = kmin; k <= std::min(h, kmin + extra_groups); ++k) splits(h, k, cur, cands, DQMC_MAX_PLAN_TRIALS);
-    // the plan in force is restored if a run fails
+    // the plan and split mode in force are restored if a run fails
     int32_t keep[DQMC_MAX_N];
-    const int nkeep = ctx->plan_len[n];
+    const int nkeep = ctx->plan_len[n], keep_split = ctx->split[n];
     for (int i = 0; i < nkeep; ++i) keep[i] = ctx->plan[n][i];
     auto restore = [&](int rc) {
         (void)dqmc_set_plan(ctx, n, keep, nkeep);
+        ctx->split[n] = keep_split;
         return rc;
     };
+    ctx->split[n] = 0;  // the group plans are timed on the whole-state passes
     int best_i = -1, count = 0;
     float best = -1.0f;
     for (size_t i = 0; i < cands.size(); ++i) {
@@ -160,7 +162,22 @@ int dqmc_plan_autotune(dqmc_ctx *ctx, int n, const uint32_t *d_tt, uint32_t *d_s
             best_i = (int)i;
         }
     }
+    // the top-digit split (three (n-1)-variable slices) as one more candidate
+    ctx->split[n] = 1;
+    int rc = DQMC_OK;
+    const float ms_split = time_best((hipStream_t)stream, reps, &rc,
+                                     [&] { return dqmc_primes(ctx, n, d_tt, d_state, nullptr, 0, d_count, stream); });
+    if (rc != DQMC_OK) return restore(rc);
+    if (ms_split < 0.0f) return restore(tune_fail(ctx, DQMC_EDEVICE, "timing the split candidate failed"));
+    if (count < cap) {
+        dqmc_plan_trial &t = trials[count];
+        t.ngroups = 0;
+        for (int g = 0; g < DQMC_MAX_N; ++g) t.sizes[g] = 0;
+        t.ms = ms_split;
+    }
+    ++count;
     if (ntrials != nullptr) *ntrials = count;
+    ctx->split[n] = ms_split < best ? 1 : 0;
     std::vector<int32_t> win(cands[best_i].begin(), cands[best_i].end());
     return dqmc_set_plan(ctx, n, win.data(), (int)win.size());
 }

@@ -136,6 +136,8 @@ def load():
             "dqmc_server_read": (ctypes.c_int64, [vp, ctypes.c_uint64, vp, ctypes.c_uint64]),
             "dqmc_server_destroy": (None, [vp]),
             "dqmc_get_plan": (i32, [vp, i32, ctypes.POINTER(ctypes.c_int32), i32]),
+            "dqmc_set_split": (i32, [vp, i32, i32]),
+            "dqmc_get_split": (i32, [vp, i32]),
             "dqmc_profile_read": (i32, [vp, ctypes.POINTER(dqmc_pass_record), i32]),
             "dqmc_batch_autotune": (i32, [vp, ctypes.c_int32, vp, ctypes.POINTER(dqmc_batch_trial), ctypes.c_int32,
                                           ctypes.POINTER(ctypes.c_int32)]),
@@ -490,7 +492,7 @@ def dqmc_plan_autotune(ctx, n: int, tt, state, count, extra_groups: int = 0, rep
     the context; returns the trials as dicts (sizes, ms)."""
     import torch
 
-    cap = DQMC_MAX_PLAN_TRIALS
+    cap = DQMC_MAX_PLAN_TRIALS + 1  # the group plans and the top-digit split
     arr = (dqmc_plan_trial * cap)()
     k = ctypes.c_int32(0)
     rc = load().dqmc_plan_autotune(ctx, n, _ptr(tt, "tt", torch.int32, dqmc_tt_words(n)),
@@ -498,8 +500,17 @@ def dqmc_plan_autotune(ctx, n: int, tt, state, count, extra_groups: int = 0, rep
                                    _ptr(count, "count", torch.int64, 1), int(extra_groups), int(reps),
                                    _stream(stream), arr, cap, ctypes.byref(k))
     _check(ctx, rc)
-    return [dict(sizes=[int(arr[i].sizes[g]) for g in range(arr[i].ngroups)], ms=float(arr[i].ms))
-            for i in range(min(k.value, cap))]
+    return [dict(sizes=[int(arr[i].sizes[g]) for g in range(arr[i].ngroups)], ms=float(arr[i].ms),
+                 split=arr[i].ngroups == 0) for i in range(min(k.value, cap))]
+
+
+def dqmc_set_split(ctx, n: int, mode: int) -> None:
+    """Top-digit split of dqmc_primes for n: 1 on, 0 off, -1 default."""
+    _check(ctx, load().dqmc_set_split(ctx, n, int(mode)))
+
+
+def dqmc_get_split(ctx, n: int) -> bool:
+    return load().dqmc_get_split(ctx, n) == 1
 
 
 def dqmc_profile(ctx, enable: bool) -> None:

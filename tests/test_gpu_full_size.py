@@ -183,3 +183,45 @@ def test_interval_symmetric_n24_count_and_sample():
     assert np.array_equal(_bits_at(state, n, rhos), expect)
     del state
     torch.cuda.empty_cache()
+
+
+def test_n25_split_equals_whole_state_passes():
+    """n = 25 runs the top-digit split by default; the whole-state passes
+    (plan [5, 4, 4]) give the same bitmap, list and count."""
+    import torch
+
+    from paper_2302_10083_amd import dqmc
+
+    n = 25
+    ctx = context()
+    tt = inputs.make(dict(n=25, kind="dnf+noise", terms=2000, wlo=6, whi=14, p=0.02, seed=25))
+    ttd = ctx.tt_to_device(tt)
+    state = ctx.new_state(n)
+    count = torch.zeros(1, dtype=torch.int64, device=ctx.torch_device)
+    h = torch.zeros(1, dtype=torch.int64, device=ctx.torch_device)
+    results = []
+    try:
+        for mode in (1, 0):
+            dqmc.dqmc_set_split(ctx.ctx, n, mode)
+            dqmc.dqmc_primes(ctx.ctx, n, ttd, state, None, 0, count)
+            torch.cuda.synchronize()
+            c = int(count.item())
+            lst = torch.empty(max(c, 1), dtype=torch.int64, device=ctx.torch_device)
+            dqmc.dqmc_primes(ctx.ctx, n, ttd, state, lst, c, count)
+            dqmc.dqmc_hash_words(ctx.ctx, state, state.numel(), h)
+            lh = torch.zeros(1, dtype=torch.int64, device=ctx.torch_device)
+            dqmc.dqmc_hash_words(ctx.ctx, lst, 2 * c, lh)
+            torch.cuda.synchronize()
+            log("n=25 split=%d: %d primes" % (mode, c))
+            results.append((c, int(h.item()), int(lh.item())))
+            del lst
+    finally:
+        dqmc.dqmc_set_split(ctx.ctx, n, -1)
+    assert results[0] == results[1]
+    # and sampled cubes agree with the per-cube definition
+    rng = np.random.default_rng(2525)
+    rhos = rng.integers(0, 3**n, size=100_000, dtype=np.int64)
+    ref, _ = oracle.sample(n, tt, rhos.astype(np.uint64), "prime", 16)
+    assert np.array_equal(_bits_at(state, n, rhos), ref)
+    del state
+    torch.cuda.empty_cache()

@@ -209,3 +209,34 @@ def test_plan_validation():
 def test_config_n20_full_parity(name):
     tt = inputs.config(name)
     check_against_oracle(20, tt, name)
+
+
+# the top-digit split of dqmc_primes: three (n-1)-variable slices in the
+# thirds of the state, against the oracle at sizes it handles
+@pytest.mark.parametrize("n", [13, 14, 15, 16, 17, 18, 19])
+def test_top_digit_split_vs_oracle(n):
+    from paper_2302_10083_amd import dqmc
+
+    ctx = context()
+    dqmc.dqmc_set_split(ctx.ctx, n, 1)
+    try:
+        assert dqmc.dqmc_get_split(ctx.ctx, n)
+        kinds = ("bern0.9", "dnf40", "const1", "const0", "parity") if n <= 15 else ("bern0.93", "dnf60")
+        for k, kind in enumerate(kinds):
+            check_against_oracle(n, make_tt(n, kind, 9500 + 13 * n + k), "split " + kind)
+    finally:
+        dqmc.dqmc_set_split(ctx.ctx, n, -1)
+
+
+def test_top_digit_split_settings():
+    from paper_2302_10083_amd import dqmc
+
+    ctx = context()
+    assert dqmc.dqmc_get_split(ctx.ctx, 25) and not dqmc.dqmc_get_split(ctx.ctx, 24)
+    for n, mode in ((12, 1), (26, 1), (20, 2), (20, -2)):
+        with pytest.raises(dqmc.DqmcError):
+            dqmc.dqmc_set_split(ctx.ctx, n, mode)
+    dqmc.dqmc_set_split(ctx.ctx, 25, 0)
+    assert not dqmc.dqmc_get_split(ctx.ctx, 25)
+    dqmc.dqmc_set_split(ctx.ctx, 25, -1)
+    assert dqmc.dqmc_get_split(ctx.ctx, 25)

@@ -53,11 +53,15 @@ def test_plan_autotune(n, extra):
         h = n - 12
         kmin = (h + 5) // 6
         want = [s for k in range(kmin, min(h, kmin + extra) + 1) for s in _splits(h, k)][:64]
-        assert [t["sizes"] for t in trials] == want
+        # the group plans, then the top-digit split
+        assert [t["sizes"] for t in trials[:-1]] == want
+        assert not any(t["split"] for t in trials[:-1]) and trials[-1]["split"] and trials[-1]["sizes"] == []
         assert all(t["ms"] > 0 for t in trials)
-        best = min(trials, key=lambda t: t["ms"])
+        best = min(trials[:-1], key=lambda t: t["ms"])
         assert dqmc.dqmc_get_plan(ctx.ctx, n) == best["sizes"]
-        log("n=%d extra=%d: %d plans, best %s %.3f ms" % (n, extra, len(trials), best["sizes"], best["ms"]))
+        assert dqmc.dqmc_get_split(ctx.ctx, n) == (trials[-1]["ms"] < best["ms"])
+        log("n=%d extra=%d: %d plans, best %s %.3f ms, split %.3f ms" % (n, extra, len(trials) - 1, best["sizes"],
+                                                                       best["ms"], trials[-1]["ms"]))
         # the tuner's own output and a fresh call under the chosen plan
         assert (_hash(ctx, state), int(count.item())) == ref
         s2, _, c2 = ctx.primes(n, ttd, list_cap=0)
@@ -65,6 +69,7 @@ def test_plan_autotune(n, extra):
         assert (_hash(ctx, s2), int(c2.item())) == ref
     finally:
         dqmc.dqmc_set_plan(ctx.ctx, n, [])
+        dqmc.dqmc_set_split(ctx.ctx, n, -1)
 
 
 def test_plan_autotune_rejects_small_n():
