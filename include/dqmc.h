@@ -318,9 +318,10 @@ int dqmc_get_plan(const dqmc_ctx *ctx, int n, int32_t *sizes, int cap);
  * While slices 0 and 1 are filtered, the * third holds those implicants.  The
  * bitmap, list and count are the same as without the split; only the passes
  * differ (those of n - 1 variables).  mode 1: split, 0: whole-state passes,
- * -1: the default, which splits n = 25 only.  dqmc_get_split returns 1 if
- * the split is in use for n, else 0.  Errors: DQMC_EINVAL for a bad n or
- * mode. */
+ * -1: the default, which splits n = 25 only.  The thirds themselves are
+ * never split again.  dqmc_primes_sliced applies the same setting to its
+ * (n - t)-variable slices.  dqmc_get_split returns 1 if the split is in use
+ * for n, else 0.  Errors: DQMC_EINVAL for a bad n or mode. */
 int dqmc_set_split(dqmc_ctx *ctx, int n, int mode);
 int dqmc_get_split(const dqmc_ctx *ctx, int n);
 

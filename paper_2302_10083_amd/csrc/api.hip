@@ -250,9 +250,17 @@ int enqueue_reduce_high(dqmc_ctx *ctx, int n, const uint32_t *tt, uint32_t flip,
 // truth table.  The tile summaries of the slice go to tiles tile0.. of the
 // context's summary arrays.
 
-// Primes of the m-variable function `tt` into `state`, with the summaries.
-int enqueue_slice_primes(dqmc_ctx *ctx, int m, const uint32_t *tt, uint32_t *state, uint64_t tile0, hipStream_t s)
+int enqueue_split_state(dqmc_ctx *ctx, int n, const uint32_t *tt, uint32_t flip, uint32_t *state, uint64_t tile0,
+                        hipStream_t s);
+bool use_split(const dqmc_ctx *ctx, int n);
+
+// Primes of the m-variable function `tt` into `state`, with the summaries;
+// by the top-digit split where it is on for m, except inside a split (one
+// level only: the thirds' truth tables share one buffer).
+int enqueue_slice_primes(dqmc_ctx *ctx, int m, const uint32_t *tt, uint32_t *state, uint64_t tile0, hipStream_t s,
+                         bool allow_split = true)
 {
+    if (allow_split && use_split(ctx, m)) return enqueue_split_state(ctx, m, tt, 0u, state, tile0, s);
     if (m <= kLowDigits) {
         LowArgs a = low_args(ctx, m);
         a.tt = tt;
@@ -290,14 +298,14 @@ int enqueue_slice_filter(dqmc_ctx *ctx, int m, uint32_t *o, const uint32_t *mask
     });
 }
 
-// The truth table of slice (fixed, stars) of the top variables into the
-// context's slice buffer.
+// The truth table of slice (fixed, stars) of the top variables into `out`
+// (a context buffer: slice_tt for the sliced path, split_tt for the split).
 int enqueue_slice_tt(dqmc_ctx *ctx, int m, const uint32_t *tt, uint32_t fixed, uint32_t stars, uint32_t flip,
-                     hipStream_t s)
+                     uint32_t *out, hipStream_t s)
 {
     const double sub = (double)(1u << __builtin_popcount(stars));
     return run_pass(ctx, s, "slice_tt", m, tt_bytes(m) * (sub + 1.0), 0,
-                    [&] { return launch_slice_tt(tt, m, fixed, stars, flip, ctx->slice_tt, s); });
+                    [&] { return launch_slice_tt(tt, m, fixed, stars, flip, out, s); });
 }
 
 // Top-digit split of dqmc_primes (n > 12): the state of n variables is three
@@ -306,20 +314,31 @@ int enqueue_slice_tt(dqmc_ctx *ctx, int m, const uint32_t *tt, uint32_t fixed, u
 // functions' primes minus the implicants of f_* = f_0 AND f_1 (the star
 // neighbour of both, held meanwhile in the * third); the * slice is the
 // primes of f_*.  One scan and list over all tiles follow.
-int enqueue_primes_split(dqmc_ctx *ctx, int n, const uint32_t *tt, uint32_t flip, uint32_t *state, uint64_t *list,
-                         uint64_t cap, uint64_t *count, hipStream_t s)
+// The state and tile summaries (from tile0) of the split; the thirds' truth
+// tables go to the context's split_tt, so that `tt` may be the sliced path's
+// slice_tt.
+int enqueue_split_state(dqmc_ctx *ctx, int n, const uint32_t *tt, uint32_t flip, uint32_t *state, uint64_t tile0,
+                        hipStream_t s)
 {
     const int m = n - 1;
     const uint64_t third = dqmc_state_words(m), tiles = low_args(ctx, m).ntiles;
     uint32_t *star = state + 2 * third;
-    int rc = enqueue_slice_tt(ctx, m, tt, 0u, 1u, flip, s);
-    if (rc == DQMC_OK) rc = enqueue_slice_implicants(ctx, m, ctx->slice_tt, star, s);
+    int rc = enqueue_slice_tt(ctx, m, tt, 0u, 1u, flip, ctx->split_tt, s);
+    if (rc == DQMC_OK) rc = enqueue_slice_implicants(ctx, m, ctx->split_tt, star, s);
     for (uint32_t a = 0; a < 3 && rc == DQMC_OK; ++a) {
         uint32_t *o = state + a * third;
-        rc = enqueue_slice_tt(ctx, m, tt, a == 1 ? 1u : 0u, a == 2 ? 1u : 0u, flip, s);
-        if (rc == DQMC_OK) rc = enqueue_slice_primes(ctx, m, ctx->slice_tt, o, a * tiles, s);
-        if (rc == DQMC_OK && a < 2) rc = enqueue_slice_filter(ctx, m, o, star, a * tiles, s);
+        const uint64_t t0 = tile0 + a * tiles;
+        rc = enqueue_slice_tt(ctx, m, tt, a == 1 ? 1u : 0u, a == 2 ? 1u : 0u, flip, ctx->split_tt, s);
+        if (rc == DQMC_OK) rc = enqueue_slice_primes(ctx, m, ctx->split_tt, o, t0, s, false);
+        if (rc == DQMC_OK && a < 2) rc = enqueue_slice_filter(ctx, m, o, star, t0, s);
     }
+    return rc;
+}
+
+int enqueue_primes_split(dqmc_ctx *ctx, int n, const uint32_t *tt, uint32_t flip, uint32_t *state, uint64_t *list,
+                         uint64_t cap, uint64_t *count, hipStream_t s)
+{
+    const int rc = enqueue_split_state(ctx, n, tt, flip, state, 0, s);
     return rc != DQMC_OK ? rc : enqueue_scan_list(ctx, n, state, list, cap, count, nullptr, 0, s);
 }
 
@@ -386,6 +405,7 @@ int dqmc_create(int device, dqmc_ctx **out)
     c->offs = nullptr;
     c->sums = nullptr;
     c->slice_tt = nullptr;
+    c->split_tt = nullptr;
     c->run = nullptr;
     c->err[0] = 0;
     c->prof = false;
@@ -400,6 +420,7 @@ int dqmc_create(int device, dqmc_ctx **out)
         hipMalloc((void **)&c->offs, c->tiles_cap * sizeof(uint64_t)) != hipSuccess ||
         hipMalloc((void **)&c->sums, scan_scratch_words(c->tiles_cap) * sizeof(uint64_t)) != hipSuccess ||
         hipMalloc((void **)&c->slice_tt, dqmc_tt_words(DQMC_MAX_N) * sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc((void **)&c->split_tt, dqmc_tt_words(DQMC_MAX_N - 1) * sizeof(uint32_t)) != hipSuccess ||
         hipMalloc((void **)&c->run, 2 * sizeof(uint64_t)) != hipSuccess) {
         dqmc_destroy(c);
         return DQMC_ENOMEM;
@@ -419,6 +440,7 @@ void dqmc_destroy(dqmc_ctx *ctx)
     if (ctx->offs) (void)hipFree(ctx->offs);
     if (ctx->sums) (void)hipFree(ctx->sums);
     if (ctx->slice_tt) (void)hipFree(ctx->slice_tt);
+    if (ctx->split_tt) (void)hipFree(ctx->split_tt);
     if (ctx->run) (void)hipFree(ctx->run);
     delete ctx;
 }
@@ -530,7 +552,7 @@ int dqmc_primes_sliced(dqmc_ctx *ctx, int n, int t, const uint32_t *d_tt, uint32
         const SliceKey a_key = slice_key(idx, t);
         const uint32_t fixed = a_key.fixed, stars = a_key.stars;
         // primes of f_a into d_o, with the tile summaries
-        rc = enqueue_slice_tt(ctx, m, d_tt, fixed, stars, flip, s);
+        rc = enqueue_slice_tt(ctx, m, d_tt, fixed, stars, flip, ctx->slice_tt, s);
         if (rc == DQMC_OK) rc = enqueue_slice_primes(ctx, m, ctx->slice_tt, d_o, 0, s);
         if (rc != DQMC_OK) return rc;
         // Reduce along each binary top digit j: drop s where s.a[j <- *] is
@@ -557,7 +579,7 @@ int dqmc_primes_sliced(dqmc_ctx *ctx, int n, int t, const uint32_t *d_tt, uint32
         }
         for (const SliceKey &k : need) {
             if (!m_valid || !(k == m_key)) {
-                rc = enqueue_slice_tt(ctx, m, d_tt, k.fixed, k.stars, flip, s);
+                rc = enqueue_slice_tt(ctx, m, d_tt, k.fixed, k.stars, flip, ctx->slice_tt, s);
                 if (rc == DQMC_OK) rc = enqueue_slice_implicants(ctx, m, ctx->slice_tt, d_m, s);
                 if (rc != DQMC_OK) return rc;
                 m_key = k;

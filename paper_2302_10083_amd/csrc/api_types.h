@@ -17,6 +17,7 @@ struct dqmc_ctx {
     uint64_t *offs;
     uint64_t *sums;  // per-block sums of the count scan
     uint32_t *slice_tt;  // sliced path: truth table of one slice (2^20 words)
+    uint32_t *split_tt;  // top-digit split: truth table of one third (2^19 words)
     uint64_t *run;       // sliced path: running prime counts (2)
     char err[512];
     // per-pass timing (diagnostics)

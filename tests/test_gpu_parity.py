@@ -228,6 +228,20 @@ def test_top_digit_split_vs_oracle(n):
         dqmc.dqmc_set_split(ctx.ctx, n, -1)
 
 
+def test_top_digit_split_is_one_level():
+    """With the split on for n and n - 1, the thirds of n are not split again."""
+    from paper_2302_10083_amd import dqmc
+
+    ctx = context()
+    dqmc.dqmc_set_split(ctx.ctx, 16, 1)
+    dqmc.dqmc_set_split(ctx.ctx, 15, 1)
+    try:
+        check_against_oracle(16, make_tt(16, "bern0.9", 9611), "split 16 and 15")
+    finally:
+        dqmc.dqmc_set_split(ctx.ctx, 16, -1)
+        dqmc.dqmc_set_split(ctx.ctx, 15, -1)
+
+
 def test_top_digit_split_settings():
     from paper_2302_10083_amd import dqmc
 

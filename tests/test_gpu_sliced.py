@@ -222,3 +222,24 @@ def test_sliced_n26_unate_exact():
     assert c == len(expected)
     assert lst[:c].cpu().numpy().tolist() == expected
     torch.cuda.empty_cache()
+
+
+def test_sliced_with_split_slices_vs_oracle():
+    """Slices whose size has the top-digit split switched on are computed as
+    three thirds (one level: the thirds themselves are not split again)."""
+    from paper_2302_10083_amd import dqmc
+
+    ctx = context()
+    for m in (13, 14, 15):
+        dqmc.dqmc_set_split(ctx.ctx, m, 1)
+    try:
+        for n, t, kind in ((15, 1, "bern0.9"), (16, 2, "dnf40"), (16, 1, "bern0.85"), (17, 3, "bern0.95")):
+            tt = make_tt(n, kind, 9700 + n + t)
+            log("sliced n=%d t=%d with split slices" % (n, t))
+            _, _, ref = oracle_primes(n, tt)
+            lst, c = _sliced(n, t, tt)
+            assert c == len(ref)
+            assert np.array_equal(lst.cpu().numpy(), ref)
+    finally:
+        for m in (13, 14, 15):
+            dqmc.dqmc_set_split(ctx.ctx, m, -1)
