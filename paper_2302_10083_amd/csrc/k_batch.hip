@@ -134,8 +134,12 @@ __global__ __launch_bounds__(kBatchThreads) void tb_merge_tt_kernel(TileBatch b)
 // 2. Digits 13..n of every column l (merge, then reduce, in registers).
 __global__ __launch_bounds__(kColThreads) __attribute__((amdgpu_waves_per_eu(5))) void tb_column_kernel(TileBatch b)
 {
-    const uint32_t jid = blockIdx.x / kColBlocks;
-    const uint32_t l = (blockIdx.x % kColBlocks) * kColThreads + threadIdx.x;
+    // consecutive column blocks of a function on one XCD, whose L2 then
+    // holds the 128-byte lines they share (the 8192-function batch: 6.81 ->
+    // 6.62 ms)
+    const uint32_t bid = (uint32_t)xcd_remap(blockIdx.x, gridDim.x);
+    const uint32_t jid = bid / kColBlocks;
+    const uint32_t l = (bid % kColBlocks) * kColThreads + threadIdx.x;
     const TileJob &j = b.jobs[jid];
     switch (j.n - 12) {
     case 1: batch_column<1>(j.state, l); break;
