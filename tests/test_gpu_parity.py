@@ -228,6 +228,26 @@ def test_top_digit_split_vs_oracle(n):
         dqmc.dqmc_set_split(ctx.ctx, n, -1)
 
 
+@pytest.mark.parametrize("n", [13, 15, 17])
+def test_top_digit_split_negate_vs_oracle(n):
+    """The complement mode through the split: the primes of NOT f."""
+    import torch
+
+    from paper_2302_10083_amd import dqmc
+
+    ctx = context()
+    tt = make_tt(n, "bern0.15", 9800 + n)
+    _, _, ref = oracle_primes(n, ~tt)
+    dqmc.dqmc_set_split(ctx.ctx, n, 1)
+    try:
+        _, lst, cnt = ctx.primes(n, ctx.tt_to_device(tt), flags=dqmc.DQMC_NEGATE)
+        torch.cuda.synchronize()
+        assert int(cnt.item()) == len(ref)
+        assert np.array_equal(lst.cpu().numpy(), ref)
+    finally:
+        dqmc.dqmc_set_split(ctx.ctx, n, -1)
+
+
 def test_top_digit_split_is_one_level():
     """With the split on for n and n - 1, the thirds of n are not split again."""
     from paper_2302_10083_amd import dqmc
