@@ -61,8 +61,8 @@ typedef enum {
 typedef struct dqmc_ctx dqmc_ctx;
 
 /* Create a context on HIP device `device` and allocate its scratch (under
- * 100 MB: per-tile summaries and offsets for n = DQMC_MAX_N, and one slice
- * truth table of the sliced path).  Returns DQMC_ENOMEM / DQMC_EDEVICE on failure, with
+ * 100 MB: per-tile summaries and offsets for n = DQMC_MAX_N, and the slice
+ * truth tables of the sliced path and of the top-digit split).  Returns DQMC_ENOMEM / DQMC_EDEVICE on failure, with
  * *out set to NULL. */
 int dqmc_create(int device, dqmc_ctx **out);
 

@@ -308,15 +308,13 @@ int enqueue_slice_tt(dqmc_ctx *ctx, int m, const uint32_t *tt, uint32_t fixed, u
                     [&] { return launch_slice_tt(tt, m, fixed, stars, flip, out, s); });
 }
 
-// Top-digit split of dqmc_primes (n > 12): the state of n variables is three
-// consecutive slice states of m = n - 1 variables (digit n = 0, 1, *), and
-// its tiles are the slices' tiles in order.  Slices 0 and 1 are their
-// functions' primes minus the implicants of f_* = f_0 AND f_1 (the star
-// neighbour of both, held meanwhile in the * third); the * slice is the
-// primes of f_*.  One scan and list over all tiles follow.
-// The state and tile summaries (from tile0) of the split; the thirds' truth
-// tables go to the context's split_tt, so that `tt` may be the sliced path's
-// slice_tt.
+// Top-digit split (n > 12): the state of n variables is three consecutive
+// slice states of m = n - 1 variables (digit n = 0, 1, *), and its tiles are
+// the slices' tiles in order.  Slices 0 and 1 are their functions' primes
+// minus the implicants of f_* = f_0 AND f_1 (the star neighbour of both, held
+// meanwhile in the * third); the * slice is the primes of f_*.  This writes
+// the state and the tile summaries from tile0 on; the thirds' truth tables go
+// to the context's split_tt, so that `tt` may be the sliced path's slice_tt.
 int enqueue_split_state(dqmc_ctx *ctx, int n, const uint32_t *tt, uint32_t flip, uint32_t *state, uint64_t tile0,
                         hipStream_t s)
 {
@@ -335,6 +333,8 @@ int enqueue_split_state(dqmc_ctx *ctx, int n, const uint32_t *tt, uint32_t flip,
     return rc;
 }
 
+// dqmc_primes by the split: the split state, then one scan and list over all
+// tiles.
 int enqueue_primes_split(dqmc_ctx *ctx, int n, const uint32_t *tt, uint32_t flip, uint32_t *state, uint64_t *list,
                          uint64_t cap, uint64_t *count, hipStream_t s)
 {
