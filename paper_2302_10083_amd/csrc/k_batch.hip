@@ -135,8 +135,8 @@ __global__ __launch_bounds__(kBatchThreads) void tb_merge_tt_kernel(TileBatch b)
 __global__ __launch_bounds__(kColThreads) __attribute__((amdgpu_waves_per_eu(5))) void tb_column_kernel(TileBatch b)
 {
     // consecutive column blocks of a function on one XCD, whose L2 then
-    // holds the 128-byte lines they share (the 8192-function batch: 6.81 ->
-    // 6.62 ms)
+    // holds the 128-byte lines they share (the 8192-function batch: 6.8 ->
+    // 6.0 ms as a replayed graph, 6.81 -> 6.62 ms launched directly)
     const uint32_t bid = (uint32_t)xcd_remap(blockIdx.x, gridDim.x);
     const uint32_t jid = bid / kColBlocks;
     const uint32_t l = (bid % kColBlocks) * kColThreads + threadIdx.x;
