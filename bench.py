@@ -203,8 +203,8 @@ def bench_sparse(ctx, n=24, densities=(0.25, 0.5), reps=3):
 
 
 def bench_sliced(ctx, workload="c3x_n26_dnf2000_noise", ts=(2, 1), reps=2):
-    """Functions past one state in HBM: the sliced path on the n = 26 version
-    of the benchmark workload (two slice states of n - t variables)."""
+    """Functions past one state in HBM: the sliced path on the n = 26 (or 27)
+    version of the benchmark workload (two slice states of n - t variables)."""
     import numpy as np
     import torch
 
@@ -578,6 +578,7 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_sliced:
         out["sliced"] = bench_sliced(ctx)
+        out["sliced_n27"] = bench_sliced(ctx, "c3x_n27_dnf2000_noise", ts=(3,), reps=1)
     if not args.no_sparse:
         out["sparse"] = bench_sparse(ctx)
         print("bench: sparse %s" % ", ".join("d=%.2f %.1f ms (dense %.1f ms)" % (r["density"], r["ms_sparse"],

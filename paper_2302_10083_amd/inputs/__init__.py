@@ -198,6 +198,7 @@ CONFIGS = {
     "c3_n24_dnf2000_noise": dict(n=24, kind="dnf+noise", terms=2000, wlo=6, whi=14, p=0.02, seed=24),
     # the same recipe at n = 26, past one state in HBM (the sliced path)
     "c3x_n26_dnf2000_noise": dict(n=26, kind="dnf+noise", terms=2000, wlo=6, whi=14, p=0.02, seed=26),
+    "c3x_n27_dnf2000_noise": dict(n=27, kind="dnf+noise", terms=2000, wlo=6, whi=14, p=0.02, seed=27),
 }
 
 

@@ -248,3 +248,17 @@ def test_sliced_with_split_slices_vs_oracle():
     finally:
         for m in (13, 14, 15):
             dqmc.dqmc_set_split(ctx.ctx, m, -1)
+
+
+def test_sliced_n27_interval_exact():
+    """n = 27 (the paper's largest dense run) as 27 slices of 24 variables:
+    f = [25 <= |x| <= 27] has exactly the 351 primes with 25 ones and 2 stars."""
+    import torch
+
+    n = 27
+    lst, c = _sliced(n, 3, inputs.interval(n, 25, 27), list_cap=400)
+    log("sliced n=27: %d primes" % c)
+    expect = sorted(sum((2 if i in st else 1) * 3**i for i in range(n)) for st in itertools.combinations(range(n), 2))
+    assert c == len(expect) == 351
+    assert lst[:c].cpu().numpy().tolist() == expect
+    torch.cuda.empty_cache()
