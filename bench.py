@@ -202,7 +202,7 @@ def bench_sparse(ctx, n=24, densities=(0.25, 0.5), reps=3):
             "rows": rows}
 
 
-def bench_sliced(ctx, workload="c3x_n26_dnf2000_noise", ts=(2, 1), reps=2):
+def bench_sliced(ctx, workload="c3x_n26_dnf2000_noise", ts=((2, 1), (2, 3), (1, 1)), reps=2):
     """Functions past one state in HBM: the sliced path on the n = 26 (or 27)
     version of the benchmark workload (two slice states of n - t variables)."""
     import numpy as np
@@ -219,12 +219,13 @@ def bench_sliced(ctx, workload="c3x_n26_dnf2000_noise", ts=(2, 1), reps=2):
     out = {"workload": workload, "n": n, "cubes": 3**n, "truth_table": spec,
            "single_state_GB": 4 * 3 ** (n - 3) / 1e9, "rows": []}
     lst = None
-    for t in ts:
-        need = 2 * 4 * 3 ** (n - t - 3)
+    for t, nm in ts:
+        need = (1 + nm) * 4 * 3 ** (n - t - 3)
         try:
-            o, m = ctx.new_state(n - t), ctx.new_state(n - t)
+            o = ctx.new_state(n - t)
+            m = [ctx.new_state(n - t) for _ in range(nm)]
             if lst is None:
-                dqmc.dqmc_primes_sliced(ctx.ctx, n, t, ttd, 0, o, m, None, 0, count)
+                dqmc.dqmc_primes_sliced_multi(ctx.ctx, n, t, ttd, 0, o, m, None, 0, count)
                 torch.cuda.synchronize()
                 nprimes = int(count.item())
                 lst = torch.empty(max(nprimes, 1), dtype=torch.int64, device=dev)
@@ -232,23 +233,24 @@ def bench_sliced(ctx, workload="c3x_n26_dnf2000_noise", ts=(2, 1), reps=2):
         except torch.cuda.OutOfMemoryError:
             o = m = None
             torch.cuda.empty_cache()
-            out["rows"].append({"t": t, "skipped": "%.1f GB of slice states (and the list) do not fit; %.1f GB "
+            out["rows"].append({"t": t, "implicant_states": nm, "skipped": "%.1f GB of slice states (and the list) do not fit; %.1f GB "
                                 "free, %.1f GB held by torch" % (need / 1e9, torch.cuda.mem_get_info()[0] / 1e9,
                                                                  torch.cuda.memory_reserved() / 1e9)})
             continue
-        dqmc.dqmc_primes_sliced(ctx.ctx, n, t, ttd, 0, o, m, lst, nprimes, count)  # warm-up
+        dqmc.dqmc_primes_sliced_multi(ctx.ctx, n, t, ttd, 0, o, m, lst, nprimes, count)  # warm-up
         torch.cuda.synchronize()
         start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         start.record()
         for _ in range(reps):
-            dqmc.dqmc_primes_sliced(ctx.ctx, n, t, ttd, 0, o, m, lst, nprimes, count)
+            dqmc.dqmc_primes_sliced_multi(ctx.ctx, n, t, ttd, 0, o, m, lst, nprimes, count)
         end.record()
         torch.cuda.synchronize()
         assert int(count.item()) == nprimes
         ms = start.elapsed_time(end) / reps
-        out["rows"].append({"t": t, "slices": 3**t, "slice_states_GB": need / 1e9, "ms": ms,
-                            "cubes_per_s": 3**n / (ms / 1e3)})
-        print("bench: sliced n=%d t=%d %.1f ms" % (n, t, ms), file=sys.stderr, flush=True)
+        out["rows"].append({"t": t, "implicant_states": nm, "slices": 3**t, "slice_states_GB": need / 1e9,
+                            "ms": ms, "cubes_per_s": 3**n / (ms / 1e3)})
+        print("bench: sliced n=%d t=%d with %d implicant states %.1f ms" % (n, t, nm, ms), file=sys.stderr,
+              flush=True)
         del o, m
         torch.cuda.empty_cache()
     del lst, ttd
@@ -578,7 +580,7 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_sliced:
         out["sliced"] = bench_sliced(ctx)
-        out["sliced_n27"] = bench_sliced(ctx, "c3x_n27_dnf2000_noise", ts=(3,), reps=1)
+        out["sliced_n27"] = bench_sliced(ctx, "c3x_n27_dnf2000_noise", ts=((3, 1), (3, 4)), reps=1)
     if not args.no_sparse:
         out["sparse"] = bench_sparse(ctx)
         print("bench: sparse %s" % ", ".join("d=%.2f %.1f ms (dense %.1f ms)" % (r["density"], r["ms_sparse"],

@@ -157,8 +157,9 @@ int dqmc_sparse_primes(dqmc_ctx *ctx, int n, const uint32_t *d_tt, uint64_t *d_l
  *                        of a, s is not an implicant of f_{a[j <- *]}.
  * Per slice, in increasing order of a (as a base-3 number, * = 2): the primes
  * of f_a into d_o; for every binary digit j the implicants of f_{a[j <- *]}
- * into d_m (kept from the previous slice when it is the same function) and
- * d_o &= ~d_m; then the slice's primes are appended to the list.
+ * into d_m (kept from the previous slice when it is the same function; see
+ * dqmc_primes_sliced_multi for more states) and d_o &= ~d_m; then the
+ * slice's primes are appended to the list.
  *   d_tt      device, the n-variable truth table: 2^(n-5) words (1 for n < 5).
  *   flags     0 or DQMC_NEGATE (the primes of NOT f).
  *   d_o, d_m  device, dqmc_state_words(n - t) words each: slice states, used
@@ -174,6 +175,19 @@ int dqmc_sparse_primes(dqmc_ctx *ctx, int n, const uint32_t *d_tt, uint64_t *d_l
 #define DQMC_SLICED_MAX_T 8
 int dqmc_primes_sliced(dqmc_ctx *ctx, int n, int t, const uint32_t *d_tt, uint32_t flags, uint32_t *d_o,
                        uint32_t *d_m, uint64_t *d_list, uint64_t list_cap, uint64_t *d_count, void *stream);
+
+/* dqmc_primes_sliced with nm implicant states instead of one: d_ms is a
+ * host array of nm device pointers (1 <= nm <= DQMC_SLICED_MAX_STATES), each
+ * to dqmc_state_words(n - t) words, disjoint from each other and from d_o.
+ * The states keep the star neighbours' implicant bitmaps between slices; a
+ * missing one goes to the state whose bitmap is needed again last, so more
+ * states mean fewer recomputed bitmaps (n = 27, t = 3: 44 with one state, 28
+ * with four).  Same results and errors as dqmc_primes_sliced, which is this
+ * call with nm = 1. */
+#define DQMC_SLICED_MAX_STATES 16
+int dqmc_primes_sliced_multi(dqmc_ctx *ctx, int n, int t, const uint32_t *d_tt, uint32_t flags, uint32_t *d_o,
+                             uint32_t *const *d_ms, int nm, uint64_t *d_list, uint64_t list_cap, uint64_t *d_count,
+                             void *stream);
 
 /* Extraction alone (Alg. 4, output step): every set bit of a state bitmap,
  * as increasing cube indices.  Same list/capacity/count rules as

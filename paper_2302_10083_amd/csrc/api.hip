@@ -15,6 +15,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
 #include <cmath>
 #include <vector>
 
@@ -355,6 +356,7 @@ struct SliceKey {
     uint32_t fixed;
     uint32_t stars;
     bool operator==(const SliceKey &o) const { return fixed == o.fixed && stars == o.stars; }
+    uint64_t code() const { return (uint64_t)fixed | ((uint64_t)stars << 32); }
 };
 
 // Slice idx (its digits in base 3, * = 2) as a key.
@@ -526,6 +528,13 @@ int dqmc_get_split(const dqmc_ctx *ctx, int n)
 int dqmc_primes_sliced(dqmc_ctx *ctx, int n, int t, const uint32_t *d_tt, uint32_t flags, uint32_t *d_o,
                        uint32_t *d_m, uint64_t *d_list, uint64_t list_cap, uint64_t *d_count, void *stream)
 {
+    return dqmc_primes_sliced_multi(ctx, n, t, d_tt, flags, d_o, &d_m, 1, d_list, list_cap, d_count, stream);
+}
+
+int dqmc_primes_sliced_multi(dqmc_ctx *ctx, int n, int t, const uint32_t *d_tt, uint32_t flags, uint32_t *d_o,
+                             uint32_t *const *d_ms, int nm, uint64_t *d_list, uint64_t list_cap, uint64_t *d_count,
+                             void *stream)
+{
     if (ctx == nullptr) return DQMC_EINVAL;
     ctx->err[0] = 0;
     if (n < 1 || n > DQMC_SLICED_MAX_N || t < 1 || t > DQMC_SLICED_MAX_T || t > n || n - t > DQMC_MAX_N) {
@@ -538,55 +547,85 @@ int dqmc_primes_sliced(dqmc_ctx *ctx, int n, int t, const uint32_t *d_tt, uint32
     if (rc != DQMC_OK) return rc;
     if ((flags & ~(uint32_t)DQMC_NEGATE) != 0u) return fail(ctx, DQMC_EINVAL, "%s", "unknown flag bits");
     const uint32_t flip = (flags & DQMC_NEGATE) ? ~0u : 0u;
-    if (d_tt == nullptr || d_o == nullptr || d_m == nullptr || d_count == nullptr)
+    if (d_ms == nullptr || nm < 1 || nm > DQMC_SLICED_MAX_STATES)
+        return fail(ctx, DQMC_EINVAL, "%s", "need 1 to DQMC_SLICED_MAX_STATES implicant states");
+    if (d_tt == nullptr || d_o == nullptr || d_count == nullptr)
         return fail(ctx, DQMC_EINVAL, "%s", "NULL truth table, slice state or count");
-    if (!aligned(d_tt, 4) || !aligned(d_o, 4) || !aligned(d_m, 4) || !aligned(d_count, 8) || !aligned(d_list, 8))
+    if (!aligned(d_tt, 4) || !aligned(d_o, 4) || !aligned(d_count, 8) || !aligned(d_list, 8))
         return fail(ctx, DQMC_EINVAL, "%s", "misaligned buffer");
     const uint64_t sw = dqmc_state_words(m);
-    if (d_o < d_m + sw && d_m < d_o + sw) return fail(ctx, DQMC_EINVAL, "%s", "the slice states overlap");
+    std::vector<uint32_t *> states(1, d_o);
+    for (int i = 0; i < nm; ++i) {
+        if (d_ms[i] == nullptr || !aligned(d_ms[i], 4))
+            return fail(ctx, DQMC_EINVAL, "%s", "NULL or misaligned implicant state");
+        for (uint32_t *q : states)
+            if (d_ms[i] < q + sw && q < d_ms[i] + sw) return fail(ctx, DQMC_EINVAL, "%s", "the slice states overlap");
+        states.push_back(d_ms[i]);
+    }
     hipStream_t s = (hipStream_t)stream;
     const uint64_t nslices = pow3(t), slice_cubes = pow3(m);
-    SliceKey m_key{0u, 0u};  // the function whose implicants d_m holds
-    bool m_valid = false;
+    // The slices that need each star neighbour's implicant bitmap, in order,
+    // for choosing which bitmap to drop when the states are full (the one
+    // needed again last).
+    std::map<uint64_t, std::vector<uint64_t>> uses;
+    for (uint64_t idx = 0; idx < nslices; ++idx)
+        for (const SliceKey &k : star_neighbours(idx, t)) uses[k.code()].push_back(idx);
+    auto next_use = [&](const SliceKey &k, uint64_t after) -> uint64_t {
+        const std::vector<uint64_t> &u = uses[k.code()];
+        const auto it = std::upper_bound(u.begin(), u.end(), after);
+        return it == u.end() ? ~0ull : *it;
+    };
+    std::vector<SliceKey> held(nm);  // the function whose implicants state i holds
+    std::vector<bool> valid(nm, false);
     for (uint64_t idx = 0; idx < nslices; ++idx) {
         const SliceKey a_key = slice_key(idx, t);
-        const uint32_t fixed = a_key.fixed, stars = a_key.stars;
         // primes of f_a into d_o, with the tile summaries
-        rc = enqueue_slice_tt(ctx, m, d_tt, fixed, stars, flip, ctx->slice_tt, s);
+        rc = enqueue_slice_tt(ctx, m, d_tt, a_key.fixed, a_key.stars, flip, ctx->slice_tt, s);
         if (rc == DQMC_OK) rc = enqueue_slice_primes(ctx, m, ctx->slice_tt, d_o, 0, s);
         if (rc != DQMC_OK) return rc;
         // Reduce along each binary top digit j: drop s where s.a[j <- *] is
         // an implicant, i.e. where M of the star neighbour's function is set.
-        // That bitmap stays in d_m, so the neighbours are ordered to reuse it:
-        // first the one already there, last one that the next slice needs.
-        std::vector<SliceKey> need = star_neighbours(idx, t);
-        size_t lo = 0;  // need[0..lo) keeps its place
-        for (size_t i = 0; m_valid && i < need.size(); ++i) {
-            if (need[i] == m_key) {
-                std::swap(need[0], need[i]);
-                lo = 1;
-                break;
-            }
+        // The bitmaps already held are applied first; the missing ones are
+        // computed with the one needed again soonest last, each into the state
+        // whose bitmap is needed again last.
+        std::vector<SliceKey> hits, misses;
+        for (const SliceKey &k : star_neighbours(idx, t)) {
+            bool held_now = false;
+            for (int i = 0; i < nm; ++i) held_now = held_now || (valid[i] && held[i] == k);
+            (held_now ? hits : misses).push_back(k);
         }
-        if (need.size() > lo + 1 && idx + 1 < nslices) {
-            const std::vector<SliceKey> next = star_neighbours(idx + 1, t);
-            for (size_t i = lo; i + 1 < need.size(); ++i) {
-                if (std::find(next.begin(), next.end(), need[i]) != next.end()) {
-                    std::swap(need[i], need.back());
+        std::stable_sort(misses.begin(), misses.end(), [&](const SliceKey &x, const SliceKey &y) {
+            return next_use(x, idx) > next_use(y, idx);
+        });
+        for (const SliceKey &k : hits) {
+            for (int i = 0; i < nm; ++i) {
+                if (valid[i] && held[i] == k) {
+                    rc = enqueue_slice_filter(ctx, m, d_o, d_ms[i], 0, s);
+                    if (rc != DQMC_OK) return rc;
                     break;
                 }
             }
         }
-        for (const SliceKey &k : need) {
-            if (!m_valid || !(k == m_key)) {
-                rc = enqueue_slice_tt(ctx, m, d_tt, k.fixed, k.stars, flip, ctx->slice_tt, s);
-                if (rc == DQMC_OK) rc = enqueue_slice_implicants(ctx, m, ctx->slice_tt, d_m, s);
-                if (rc != DQMC_OK) return rc;
-                m_key = k;
-                m_valid = true;
+        for (const SliceKey &k : misses) {
+            int v = -1;
+            for (int i = 0; i < nm && v < 0; ++i)
+                if (!valid[i]) v = i;
+            if (v < 0) {
+                uint64_t far = 0;
+                for (int i = 0; i < nm; ++i) {
+                    const uint64_t nu = next_use(held[i], idx);
+                    if (v < 0 || nu > far) {
+                        v = i;
+                        far = nu;
+                    }
+                }
             }
-            rc = enqueue_slice_filter(ctx, m, d_o, d_m, 0, s);
+            rc = enqueue_slice_tt(ctx, m, d_tt, k.fixed, k.stars, flip, ctx->slice_tt, s);
+            if (rc == DQMC_OK) rc = enqueue_slice_implicants(ctx, m, ctx->slice_tt, d_ms[v], s);
+            if (rc == DQMC_OK) rc = enqueue_slice_filter(ctx, m, d_o, d_ms[v], 0, s);
             if (rc != DQMC_OK) return rc;
+            held[v] = k;
+            valid[v] = true;
         }
         // append the slice's primes: offsets continue from the previous
         // slices' total (two running counters, used alternately)

@@ -49,6 +49,7 @@ DQMC_NEGATE = 1
 DQMC_SPARSE_MAX_N = 31
 DQMC_SLICED_MAX_N = 30
 DQMC_SLICED_MAX_T = 8
+DQMC_SLICED_MAX_STATES = 16
 
 
 class dqmc_result(ctypes.Structure):
@@ -119,6 +120,8 @@ def load():
             "dqmc_primes_ex": (i32, [vp, i32, vp, ctypes.c_uint32, vp, vp, u64, vp, vp]),
             "dqmc_extract": (i32, [vp, i32, vp, vp, u64, vp, vp]),
             "dqmc_primes_sliced": (i32, [vp, i32, i32, vp, ctypes.c_uint32, vp, vp, vp, u64, vp, vp]),
+            "dqmc_primes_sliced_multi": (i32, [vp, i32, i32, vp, ctypes.c_uint32, vp, ctypes.POINTER(vp), i32, vp,
+                                               u64, vp, vp]),
             "dqmc_bitmap_to_dense": (i32, [vp, i32, vp, vp, vp]),
             "dqmc_primes_batch": (i32, [vp, ctypes.POINTER(dqmc_job), ctypes.c_int32, vp]),
             "dqmc_profile": (i32, [vp, i32]),
@@ -305,6 +308,22 @@ def dqmc_primes_sliced(ctx, n, t, tt, flags, o_state, m_state, lst, list_cap, co
         ctx, n, t, _ptr(tt, "tt", torch.int32, nw), int(flags), _ptr(o_state, "o_state", torch.int32, sw),
         _ptr(m_state, "m_state", torch.int32, sw), _ptr(lst, "list", torch.int64, cap), cap,
         _ptr(count, "count", torch.int64, 1), _stream(stream)))
+
+
+def dqmc_primes_sliced_multi(ctx, n, t, tt, flags, o_state, m_states, lst, list_cap, count, stream=None) -> None:
+    """Sliced path with several implicant states (see include/dqmc.h)."""
+    import torch
+
+    cap = 0 if lst is None else int(list_cap)
+    ok = 1 <= t <= DQMC_SLICED_MAX_T and t <= n <= DQMC_SLICED_MAX_N and n - t <= DQMC_MAX_N
+    nw = max(1, (1 << n) // 32) if ok else 1  # the library rejects other n, t
+    sw = dqmc_state_words(n - t) if ok else 1
+    ptrs = [_ptr(m, "m_states[%d]" % i, torch.int32, sw) for i, m in enumerate(m_states)]
+    arr = (ctypes.c_void_p * max(1, len(ptrs)))(*[p.value for p in ptrs])
+    _check(ctx, load().dqmc_primes_sliced_multi(
+        ctx, n, t, _ptr(tt, "tt", torch.int32, nw), int(flags), _ptr(o_state, "o_state", torch.int32, sw),
+        arr, len(ptrs), _ptr(lst, "list", torch.int64, cap), cap, _ptr(count, "count", torch.int64, 1),
+        _stream(stream)))
 
 
 def dqmc_extract(ctx, n, state, lst, list_cap, count, stream=None) -> None:
@@ -616,20 +635,22 @@ class Context:
             raise DqmcError(rc, "sparse path failed on the second run")
         return lst[:c], count
 
-    def sliced_primes(self, n, t, tt, list_cap=None, flags=0, states=None, stream=None):
+    def sliced_primes(self, n, t, tt, list_cap=None, flags=0, states=None, n_m=1, stream=None):
         """(list, count) of the sliced path with slices of n - t variables.
-        states: (o_state, m_state), else allocated here.  With list_cap None
-        a count-only call sizes the list first (the work runs twice)."""
+        states: (o_state, m_state, ...), else allocated here with n_m
+        implicant states.  With list_cap None a count-only call sizes the list
+        first (the work runs twice)."""
         import torch
 
         if states is None:
-            states = (self.new_state(n - t), self.new_state(n - t))
+            states = [self.new_state(n - t) for _ in range(1 + n_m)]
         count = torch.zeros(1, dtype=torch.int64, device=self.torch_device)
+        o, ms = states[0], list(states[1:])
         if list_cap is None:
-            dqmc_primes_sliced(self.ctx, n, t, tt, flags, states[0], states[1], None, 0, count, stream)
+            dqmc_primes_sliced_multi(self.ctx, n, t, tt, flags, o, ms, None, 0, count, stream)
             list_cap = int(count.item())
         lst = torch.empty(max(int(list_cap), 1), dtype=torch.int64, device=self.torch_device)
-        dqmc_primes_sliced(self.ctx, n, t, tt, flags, states[0], states[1], lst, list_cap, count, stream)
+        dqmc_primes_sliced_multi(self.ctx, n, t, tt, flags, o, ms, lst, list_cap, count, stream)
         return lst[:int(list_cap)], count
 
     def extract(self, n, state, list_cap, stream=None):

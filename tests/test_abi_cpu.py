@@ -56,6 +56,7 @@ def test_null_context_is_einval():
     assert lib.dqmc_extract(None, 4, None, None, 0, None, None) == dqmc.DQMC_EINVAL
     assert lib.dqmc_primes_batch(None, None, 0, None) == dqmc.DQMC_EINVAL
     assert lib.dqmc_primes_sliced(None, 26, 1, None, 0, None, None, None, 0, None, None) == dqmc.DQMC_EINVAL
+    assert lib.dqmc_primes_sliced_multi(None, 26, 1, None, 0, None, None, 0, None, 0, None, None) == dqmc.DQMC_EINVAL
     assert lib.dqmc_last_error(None) == b"no context"
     lib.dqmc_destroy(None)  # ignored
 

@@ -2,6 +2,7 @@
 list and count as the oracle for every slice shape at small n, the same as
 the single-state path at n = 24, and at n = 26 (a state of 377 GB, beyond one
 GPU) exact closed forms plus per-cube definitions on sampled cubes."""
+import ctypes
 import itertools
 import math
 
@@ -262,3 +263,47 @@ def test_sliced_n27_interval_exact():
     assert c == len(expect) == 351
     assert lst[:c].cpu().numpy().tolist() == expect
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("n,t,nm", [(12, 3, 2), (14, 4, 3), (16, 3, 4), (13, 2, 2), (15, 5, 6)])
+def test_sliced_multi_states_vs_oracle(n, t, nm):
+    """Several implicant states: fewer recomputed bitmaps, the same primes."""
+    ctx = context()
+    tt = make_tt(n, "bern0.9", 10100 + 7 * n + t + nm)
+    _, _, ref = oracle_primes(n, tt)
+    lst, count = ctx.sliced_primes(n, t, ctx.tt_to_device(tt), n_m=nm)
+    import torch
+
+    torch.cuda.synchronize()
+    assert int(count.item()) == len(ref)
+    assert np.array_equal(lst.cpu().numpy(), ref)
+
+
+def test_sliced_multi_bad_arguments():
+    import torch
+
+    from paper_2302_10083_amd import dqmc
+
+    ctx = context()
+    n, t = 12, 2
+    tt = ctx.tt_to_device(make_tt(n, "bern0.5", 3))
+    count = torch.zeros(1, dtype=torch.int64, device=ctx.torch_device)
+    o = ctx.new_state(n - t)
+    ms = [ctx.new_state(n - t) for _ in range(17)]
+    with pytest.raises(dqmc.DqmcError):
+        dqmc.dqmc_primes_sliced_multi(ctx.ctx, n, t, tt, 0, o, [], None, 0, count)  # no state
+    with pytest.raises(dqmc.DqmcError):
+        dqmc.dqmc_primes_sliced_multi(ctx.ctx, n, t, tt, 0, o, ms, None, 0, count)  # too many
+    with pytest.raises(dqmc.DqmcError):
+        dqmc.dqmc_primes_sliced_multi(ctx.ctx, n, t, tt, 0, o, [ms[0], ms[0]], None, 0, count)  # overlap
+    with pytest.raises(dqmc.DqmcError):
+        dqmc.dqmc_primes_sliced_multi(ctx.ctx, n, t, tt, 0, o, [ms[0], o], None, 0, count)  # overlap with o
+    lib = dqmc.load()
+    arr = (ctypes.c_void_p * 2)(ctypes.c_void_p(ms[0].data_ptr()).value, None)
+    assert lib.dqmc_primes_sliced_multi(ctx.ctx, n, t, ctypes.c_void_p(tt.data_ptr()), 0,
+                                        ctypes.c_void_p(o.data_ptr()), arr, 2, None, 0,
+                                        ctypes.c_void_p(count.data_ptr()), None) == dqmc.DQMC_EINVAL
+    # the context still works afterwards
+    dqmc.dqmc_primes_sliced_multi(ctx.ctx, n, t, tt, 0, o, ms[:3], None, 0, count)
+    torch.cuda.synchronize()
+    assert int(count.item()) == len(oracle_primes(n, make_tt(n, "bern0.5", 3))[2])
