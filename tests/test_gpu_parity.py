@@ -248,6 +248,31 @@ def test_top_digit_split_negate_vs_oracle(n):
         dqmc.dqmc_set_split(ctx.ctx, n, -1)
 
 
+def test_top_digit_split_capacity_and_extract():
+    """The split's list obeys the capacity rule, and its bitmap re-extracts."""
+    import torch
+
+    from paper_2302_10083_amd import dqmc
+
+    ctx = context()
+    n = 15
+    tt = make_tt(n, "bern0.9", 9660)
+    _, _, ref = oracle_primes(n, tt)
+    dqmc.dqmc_set_split(ctx.ctx, n, 1)
+    try:
+        cap = len(ref) // 3
+        _, glist, cnt = run_primes(n, tt, list_cap=cap)
+        assert cnt == len(ref)
+        assert np.array_equal(glist, ref[:cap])
+        state, _, _ = ctx.primes(n, ctx.tt_to_device(tt), list_cap=0)
+        lst, c2 = ctx.extract(n, state, len(ref))
+        torch.cuda.synchronize()
+        assert int(c2.item()) == len(ref)
+        assert np.array_equal(lst[: len(ref)].cpu().numpy(), ref)
+    finally:
+        dqmc.dqmc_set_split(ctx.ctx, n, -1)
+
+
 def test_top_digit_split_is_one_level():
     """With the split on for n and n - 1, the thirds of n are not split again."""
     from paper_2302_10083_amd import dqmc
