@@ -225,3 +225,70 @@ def test_n25_split_equals_whole_state_passes():
     assert np.array_equal(_bits_at(state, n, rhos), ref)
     del state
     torch.cuda.empty_cache()
+
+
+def _relabel_tt(n, tt, sigma, c):
+    """Truth table of g(y) = f(x) with x_i = y_sigma(i) XOR c_i."""
+    bits = inputs.to_bits(n, tt)
+    y = np.arange(1 << n, dtype=np.int64)
+    x = np.zeros_like(y)
+    for i in range(n):
+        x |= (((y >> int(sigma[i])) & 1) ^ int(c[i])) << i
+    return inputs.from_bits(n, bits[x])
+
+
+def _all_primes(ctx, n, ttd, state):
+    """Count, then the whole sorted list, reusing one state buffer."""
+    import torch
+
+    from paper_2302_10083_amd import dqmc
+
+    count = torch.zeros(1, dtype=torch.int64, device=ctx.torch_device)
+    dqmc.dqmc_primes(ctx.ctx, n, ttd, state, None, 0, count)
+    torch.cuda.synchronize()
+    c = int(count.item())
+    lst = torch.empty(max(c, 1), dtype=torch.int64, device=ctx.torch_device)
+    dqmc.dqmc_primes(ctx.ctx, n, ttd, state, lst, c, count)
+    torch.cuda.synchronize()
+    assert int(count.item()) == c
+    return lst[:c]
+
+
+@pytest.mark.parametrize("n", [24, 25])
+def test_relabel_equivariance_full_list(n):
+    """Exact check of the whole prime list at the full sizes, GPU against GPU.
+    Relabelling and negating variables is an automorphism of the cube lattice:
+    if g(y) = f(x) with x_i = y_sigma(i) XOR c_i, then s is a prime of f iff
+    the cube t with t_sigma(i) = s_i XOR c_i (and * kept) is a prime of g.
+    The relabelling moves digits between the low tile, the column groups and
+    (at n = 25) the split top digit, so an error tied to one pass or digit
+    position breaks the equality."""
+    import torch
+
+    ctx = context()
+    spec = dict(inputs.CONFIGS["c3_n24_dnf2000_noise"])
+    spec.update(n=n, seed=n)
+    tt = inputs.make(spec)
+    rng = np.random.default_rng(9000 + n)
+    sigma = rng.permutation(n)
+    c = rng.integers(0, 2, n)
+    log("n=%d relabel sigma=%s c=%s" % (n, sigma.tolist(), c.tolist()))
+    state = ctx.new_state(n)
+    try:
+        lf = _all_primes(ctx, n, ctx.tt_to_device(tt), state)
+        lg = _all_primes(ctx, n, ctx.tt_to_device(_relabel_tt(n, tt, sigma, c)), state)
+        log("n=%d: %d primes" % (n, lf.numel()))
+        assert lf.numel() == lg.numel() and lf.numel() > 0
+        mapped = torch.zeros_like(lf)
+        p = 1
+        for i in range(n):
+            d = torch.div(lf, p, rounding_mode="floor") % 3
+            t = torch.where(d == 2, d, d ^ int(c[i]))
+            mapped += t * (3 ** int(sigma[i]))
+            p *= 3
+            del d, t
+        mapped, _ = torch.sort(mapped)
+        assert torch.equal(mapped, lg)
+    finally:
+        del state
+        torch.cuda.empty_cache()
