@@ -111,3 +111,30 @@ def make_tt(n, kind, seed):
         T = int(kind[3:])
         return inputs.dnf(n, T, max(1, n // 4), max(2, n // 2), seed)
     raise ValueError(kind)
+
+
+def relabel_tt(n, tt, sigma, c):
+    """Truth table of g(y) = f(x) with x_i = y_sigma(i) XOR c_i."""
+    bits = inputs.to_bits(n, tt)
+    y = np.arange(1 << n, dtype=np.int64)
+    x = np.zeros_like(y)
+    for i in range(n):
+        x |= (((y >> int(sigma[i])) & 1) ^ int(c[i])) << i
+    return inputs.from_bits(n, bits[x])
+
+
+def relabel_cubes(n, lst, sigma, c):
+    """Sorted images of the cubes in the device tensor ``lst`` (cube indices of
+    f) as cubes of g = relabel_tt(f): digit i moves to position sigma(i), and a
+    binary digit is XORed with c_i.  Relabelling is an automorphism of the cube
+    lattice, so it maps the primes of f onto the primes of g."""
+    import torch
+
+    out = torch.zeros_like(lst)
+    p = 1
+    for i in range(n):
+        d = torch.div(lst, p, rounding_mode="floor") % 3
+        out += torch.where(d == 2, d, d ^ int(c[i])) * (3 ** int(sigma[i]))
+        p *= 3
+        del d
+    return torch.sort(out)[0]

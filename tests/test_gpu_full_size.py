@@ -11,7 +11,7 @@ import pytest
 import oracle
 from paper_2302_10083_amd import inputs
 
-from _gpu_common import context, log
+from _gpu_common import context, log, relabel_cubes, relabel_tt
 
 pytestmark = pytest.mark.gpu
 
@@ -227,16 +227,6 @@ def test_n25_split_equals_whole_state_passes():
     torch.cuda.empty_cache()
 
 
-def _relabel_tt(n, tt, sigma, c):
-    """Truth table of g(y) = f(x) with x_i = y_sigma(i) XOR c_i."""
-    bits = inputs.to_bits(n, tt)
-    y = np.arange(1 << n, dtype=np.int64)
-    x = np.zeros_like(y)
-    for i in range(n):
-        x |= (((y >> int(sigma[i])) & 1) ^ int(c[i])) << i
-    return inputs.from_bits(n, bits[x])
-
-
 def _all_primes(ctx, n, ttd, state):
     """Count, then the whole sorted list, reusing one state buffer."""
     import torch
@@ -276,19 +266,10 @@ def test_relabel_equivariance_full_list(n):
     state = ctx.new_state(n)
     try:
         lf = _all_primes(ctx, n, ctx.tt_to_device(tt), state)
-        lg = _all_primes(ctx, n, ctx.tt_to_device(_relabel_tt(n, tt, sigma, c)), state)
+        lg = _all_primes(ctx, n, ctx.tt_to_device(relabel_tt(n, tt, sigma, c)), state)
         log("n=%d: %d primes" % (n, lf.numel()))
         assert lf.numel() == lg.numel() and lf.numel() > 0
-        mapped = torch.zeros_like(lf)
-        p = 1
-        for i in range(n):
-            d = torch.div(lf, p, rounding_mode="floor") % 3
-            t = torch.where(d == 2, d, d ^ int(c[i]))
-            mapped += t * (3 ** int(sigma[i]))
-            p *= 3
-            del d, t
-        mapped, _ = torch.sort(mapped)
-        assert torch.equal(mapped, lg)
+        assert torch.equal(relabel_cubes(n, lf, sigma, c), lg)
     finally:
         del state
         torch.cuda.empty_cache()

@@ -12,7 +12,7 @@ import pytest
 import oracle
 from paper_2302_10083_amd import inputs
 
-from _gpu_common import context, log, make_tt, oracle_primes
+from _gpu_common import context, log, make_tt, oracle_primes, relabel_cubes, relabel_tt
 
 pytestmark = pytest.mark.gpu
 
@@ -188,6 +188,28 @@ def test_sliced_n26_c3_recipe_sampled():
     del lst
     torch.cuda.empty_cache()
 
+
+def test_sliced_n26_relabel_equivariance_full_list():
+    """The whole n = 26 prime list, exactly, GPU against GPU: a random
+    relabelling and negation of the variables (g(y) = f(x) with
+    x_i = y_sigma(i) XOR c_i) maps the primes of f onto those of g.  f runs
+    with two slice variables, g with three, so the relabelling also moves
+    variables into and out of the slice digits."""
+    import torch
+
+    n = 26
+    tt = inputs.config("c3x_n26_dnf2000_noise")
+    rng = np.random.default_rng(9026)
+    sigma = rng.permutation(n)
+    c = rng.integers(0, 2, n)
+    log("sliced n=26 relabel sigma=%s c=%s" % (sigma.tolist(), c.tolist()))
+    lf, cf = _sliced(n, 2, tt)
+    lg, cg = _sliced(n, 3, relabel_tt(n, tt, sigma, c))
+    log("sliced n=26: %d / %d primes" % (cf, cg))
+    assert cf == cg == lf.numel() == lg.numel() and cf > 0
+    assert torch.equal(relabel_cubes(n, lf, sigma, c), lg)
+    del lf, lg
+    torch.cuda.empty_cache()
 
 @pytest.mark.parametrize("t", [1, 2])
 def test_sliced_n26_interval_exact(t):
