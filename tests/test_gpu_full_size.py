@@ -227,32 +227,33 @@ def test_n25_split_equals_whole_state_passes():
     torch.cuda.empty_cache()
 
 
-def _all_primes(ctx, n, ttd, state):
+def _all_primes(ctx, n, ttd, state, flags=0):
     """Count, then the whole sorted list, reusing one state buffer."""
     import torch
 
     from paper_2302_10083_amd import dqmc
 
     count = torch.zeros(1, dtype=torch.int64, device=ctx.torch_device)
-    dqmc.dqmc_primes(ctx.ctx, n, ttd, state, None, 0, count)
+    dqmc.dqmc_primes_ex(ctx.ctx, n, ttd, flags, state, None, 0, count)
     torch.cuda.synchronize()
     c = int(count.item())
     lst = torch.empty(max(c, 1), dtype=torch.int64, device=ctx.torch_device)
-    dqmc.dqmc_primes(ctx.ctx, n, ttd, state, lst, c, count)
+    dqmc.dqmc_primes_ex(ctx.ctx, n, ttd, flags, state, lst, c, count)
     torch.cuda.synchronize()
     assert int(count.item()) == c
     return lst[:c]
 
 
-@pytest.mark.parametrize("n", [24, 25])
-def test_relabel_equivariance_full_list(n):
+@pytest.mark.parametrize("n,flags", [(24, 0), (25, 0), (24, 1)])
+def test_relabel_equivariance_full_list(n, flags):
     """Exact check of the whole prime list at the full sizes, GPU against GPU.
     Relabelling and negating variables is an automorphism of the cube lattice:
     if g(y) = f(x) with x_i = y_sigma(i) XOR c_i, then s is a prime of f iff
     the cube t with t_sigma(i) = s_i XOR c_i (and * kept) is a prime of g.
     The relabelling moves digits between the low tile, the column groups and
     (at n = 25) the split top digit, so an error tied to one pass or digit
-    position breaks the equality."""
+    position breaks the equality.  flags = 1 (DQMC_NEGATE) checks the prime
+    clauses the same way: NOT g is NOT f relabelled."""
     import torch
 
     ctx = context()
@@ -265,9 +266,9 @@ def test_relabel_equivariance_full_list(n):
     log("n=%d relabel sigma=%s c=%s" % (n, sigma.tolist(), c.tolist()))
     state = ctx.new_state(n)
     try:
-        lf = _all_primes(ctx, n, ctx.tt_to_device(tt), state)
-        lg = _all_primes(ctx, n, ctx.tt_to_device(relabel_tt(n, tt, sigma, c)), state)
-        log("n=%d: %d primes" % (n, lf.numel()))
+        lf = _all_primes(ctx, n, ctx.tt_to_device(tt), state, flags)
+        lg = _all_primes(ctx, n, ctx.tt_to_device(relabel_tt(n, tt, sigma, c)), state, flags)
+        log("n=%d flags=%d: %d primes" % (n, flags, lf.numel()))
         assert lf.numel() == lg.numel() and lf.numel() > 0
         assert torch.equal(relabel_cubes(n, lf, sigma, c), lg)
     finally:
