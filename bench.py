@@ -510,7 +510,7 @@ def main():
     traffic = read_traffic(dom["name"], args.workload)
 
     out = {
-        "metric": "ternary cubes/s (DenseQMC primes at n=24: truth table -> prime bitmap + sorted list)",
+        "metric": "ternary cubes/s (DenseQMC primes at n=%d: truth table -> prime bitmap + sorted list)" % n,
         "value": cubes / (ms_step / 1e3),
         "unit": "cubes/s",
         "n_gpus": 1,

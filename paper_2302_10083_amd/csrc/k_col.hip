@@ -19,6 +19,61 @@
 
 namespace dqmc {
 
+// Bit b set: binary wave combination b (bit r = digit r) is covered by the
+// wave combination cw, i.e. agrees with it on every binary digit.
+template <int GW>
+__device__ __forceinline__ uint32_t binary_cover(int cw)
+{
+    uint32_t cover = 0;
+    for (int b = 0; b < (1 << GW); ++b) {
+        bool ok = true;
+        int cc = cw;
+        for (int r = 0; r < GW; ++r, cc /= 3) {
+            const int d = cc % 3, bit = (b >> r) & 1;
+            if (d != 2 && d != bit) ok = false;
+        }
+        cover |= ok ? (1u << b) : 0u;
+    }
+    return cover;
+}
+
+// x &= ~M(w) on all 3^GR register rows, where w is the wave combination whose
+// covered binary waves are `cover`: its binary rows are the AND of theirs (in
+// xch, as the merge step left them) and its other rows follow by register
+// merges.  Built one third of the top register digit at a time (top digit 0,
+// 1, then * = the AND of the two) to hold 2 * 3^(GR-1) extra registers
+// instead of 3^GR.
+template <int GR, int GW>
+__device__ __forceinline__ void reduce_by_sibling(uint32_t (&x)[pow3(GR)], const uint32_t *xch, uint32_t cover,
+                                                  uint32_t lane)
+{
+    constexpr int CL = (int)pow3(GR - 1);
+    constexpr int BR = 1 << GR, BL = 1 << (GR - 1);
+    uint32_t y0[CL], y1[CL];
+    static_for<CL>([&](auto ci) {
+        constexpr int c = decltype(ci)::value;
+        if constexpr (all_binary(c, GR - 1)) {
+            uint32_t a0 = ~0u, a1 = ~0u;
+            for (int b = 0; b < (1 << GW); ++b) {
+                if ((cover >> b) & 1u) {
+                    a0 &= xch[(b * BR + bin_index(c, GR - 1)) * 64 + lane];
+                    a1 &= xch[(b * BR + BL + bin_index(c, GR - 1)) * 64 + lane];
+                }
+            }
+            y0[c] = a0;
+            y1[c] = a1;
+        }
+    });
+    reg_merge<GR - 1>(y0);
+    reg_merge<GR - 1>(y1);
+    static_for<CL>([&](auto ci) {
+        constexpr int c = decltype(ci)::value;
+        x[c] &= ~y0[c];
+        x[c + CL] &= ~y1[c];
+        x[c + 2 * CL] &= ~(y0[c] & y1[c]);
+    });
+}
+
 template <int GR, int GW, int MODE>
 __global__ __launch_bounds__(col_threads<GW>()) void col_kernel(ColArgs a)
 {
@@ -29,10 +84,10 @@ __global__ __launch_bounds__(col_threads<GW>()) void col_kernel(ColArgs a)
     constexpr int LANES = GW == 0 ? 256 : 64;
     constexpr bool NEED_MERGE = MODE != kColReduce;
     constexpr bool NEED_REDUCE = MODE != kColMerge;
-    // LDS: merge exchange of binary waves' binary combos, reduce exchange of
-    // star waves' full columns
+    // LDS: merge exchange of binary waves' binary combos; the reduce-only
+    // mode exchanges the star waves' full columns
     constexpr int XM = GW > 0 ? BW * BR * 64 : 1;
-    constexpr int XR = (GW > 0 && NEED_REDUCE) ? (CW - BW) * CR * 64 : 1;
+    constexpr int XR = (GW > 0 && !NEED_MERGE) ? (CW - BW) * CR * 64 : 1;
     constexpr int XSZ = XM > XR ? XM : XR;
     __shared__ uint32_t xch[XSZ];
 
@@ -87,16 +142,7 @@ __global__ __launch_bounds__(col_threads<GW>()) void col_kernel(ColArgs a)
             __syncthreads();
             if (!cw_binary) {
                 // AND over the binary wave combinations covered by cw
-                uint32_t cover = 0;  // bit b set: binary wave b is covered by cw
-                for (int b = 0; b < BW; ++b) {
-                    bool ok = true;
-                    int cc = cw;
-                    for (int r = 0; r < GW; ++r, cc /= 3) {
-                        const int d = cc % 3, bit = (b >> r) & 1;
-                        if (d != 2 && d != bit) ok = false;
-                    }
-                    cover |= ok ? (1u << b) : 0u;
-                }
+                const uint32_t cover = binary_cover<GW>(cw);
                 static_for<CR>([&](auto ci) {
                     constexpr int c = decltype(ci)::value;
                     if constexpr (all_binary(c, GR)) {
@@ -138,8 +184,22 @@ __global__ __launch_bounds__(col_threads<GW>()) void col_kernel(ColArgs a)
         // 4. wave digits first, all against the star neighbours' values
         //    before any of this group's reduces (same as doing those
         //    dimensions one after another)
-        if constexpr (GW > 0) {
-            if constexpr (NEED_MERGE) __syncthreads();  // xch reuse
+        if constexpr (GW > 0 && NEED_MERGE) {
+            // Right after the merge x holds M itself.  By the merge identity
+            // the star neighbour along wave digit r has M(self) AND M(sib),
+            // sib being this wave with digit r flipped, so on any x <= M(self)
+            // x AND NOT M(star) = x AND NOT M(sib).  The sibling's merged rows
+            // follow from the binary rows still in xch: no second exchange
+            // and no barrier before the stores.
+            int cc = cw, p = 1;
+            for (int r = 0; r < GW; ++r, cc /= 3, p *= 3) {
+                const int d = cc % 3;
+                if (d == 2) continue;
+                static_assert(GR >= 1, "the sibling reduce splits the top register digit");
+                const int sib = d == 0 ? cw + p : cw - p;
+                reduce_by_sibling<GR, GW>(x, xch, binary_cover<GW>(sib), lane);
+            }
+        } else if constexpr (GW > 0) {
             if (!cw_binary) {
                 const int ss = star_slot<GW>(cw);
                 static_for<CR>([&](auto ci) {
@@ -175,20 +235,21 @@ __global__ __launch_bounds__(col_threads<GW>()) void col_kernel(ColArgs a)
 
 int col_lanes_per_block(int gw) { return gw == 0 ? 256 : 64; }
 
-// Dynamic LDS of the merge pass with two wave digits: one workgroup per CU
-// (n = 24: the top group's merge 14.1 -> 9.0 ms, the first group's
-// 1.15 -> 0.80 ms).  The other two modes hold one workgroup per CU through
-// their own LDS exchange already.
-static size_t g_merge42_pad = 0;
+// Dynamic LDS of the merge and merge+reduce passes with two wave digits: one
+// workgroup per CU (n = 24: the top group's merge 14.1 -> 9.0 ms, the first
+// group's 1.15 -> 0.80 ms).  The reduce-only mode holds one workgroup per CU
+// through its own LDS exchange already.
+static size_t g_merge42_pad = 0, g_mr42_pad = 0;
 
 template <int GR, int GW>
 static hipError_t launch_col_gw(int mode, const ColArgs &a, hipStream_t s)
 {
     const dim3 grid((uint32_t)a.nblocks), block(col_threads<GW>());
     const size_t merge_pad = (GR == 4 && GW == 2) ? g_merge42_pad : 0;
+    const size_t mr_pad = (GR == 4 && GW == 2) ? g_mr42_pad : 0;
     switch (mode) {
     case kColMerge: hipLaunchKernelGGL((col_kernel<GR, GW, kColMerge>), grid, block, merge_pad, s, a); break;
-    case kColMergeReduce: hipLaunchKernelGGL((col_kernel<GR, GW, kColMergeReduce>), grid, block, 0, s, a); break;
+    case kColMergeReduce: hipLaunchKernelGGL((col_kernel<GR, GW, kColMergeReduce>), grid, block, mr_pad, s, a); break;
     case kColReduce: hipLaunchKernelGGL((col_kernel<GR, GW, kColReduce>), grid, block, 0, s, a); break;
     default: return hipErrorInvalidValue;
     }
@@ -208,7 +269,8 @@ hipError_t launch_col(int gr, int gw, int mode, const ColArgs &a, hipStream_t s)
 
 hipError_t col_setup()
 {
-    const hipError_t e = occupancy_cap((const void *)col_kernel<4, 2, kColMerge>, 1, &g_merge42_pad);
+    hipError_t e = occupancy_cap((const void *)col_kernel<4, 2, kColMerge>, 1, &g_merge42_pad);
+    if (e == hipSuccess) e = occupancy_cap((const void *)col_kernel<4, 2, kColMergeReduce>, 1, &g_mr42_pad);
     if (e != hipSuccess) return e;
     return chunk_setup();
 }
