@@ -434,3 +434,33 @@ def test_top_digit_slicing_identity(n, t, p, seed):
         got |= {s + idx * 3**m for s in keep}
     assert got == full
     assert len(full) > 0
+
+
+@pytest.mark.parametrize("n,kind,seed", [(5, 0.7, 1), (6, 0.85, 2), (7, "dnf", 3), (8, 0.95, 4)])
+def test_sibling_form_of_the_reduce(n, kind, seed):
+    """The derived identity the merge+reduce column pass uses: for a cube s
+    with digit i binary and s' the cube with that digit flipped,
+    M(s[i <- *]) = M(s) AND M(s') (the Lemma of Sec. 4.1), so reducing with
+    the sibling's M gives the same O as reducing with the star neighbour's."""
+    if kind == "dnf":
+        tt = inputs.dnf(n, 6, 1, 4, 9300 + seed)
+    else:
+        tt = inputs.bernoulli(n, kind, 9300 + seed)
+    M = np.zeros(3**n, dtype=bool)
+    M[sorted(oracle.bitmap_to_set(n, oracle.enum_M(n, tt)))] = True
+    rho = np.arange(3**n, dtype=np.int64)
+    p3 = 3 ** np.arange(n, dtype=np.int64)
+    digs = (rho[:, None] // p3[None, :]) % 3
+    by_star, by_sib = M.copy(), M.copy()
+    for i in range(n):
+        s = rho[digs[:, i] != 2]
+        d = digs[s, i]
+        star = s + (2 - d) * p3[i]
+        sib = s + (1 - 2 * d) * p3[i]
+        assert np.array_equal(M[star], M[s] & M[sib])
+        by_star[s] &= ~M[star]
+        by_sib[s] &= ~M[sib]
+    _, O, _ = oracle.primes(n, tt)
+    assert np.array_equal(by_star, by_sib)
+    assert set(np.flatnonzero(by_sib).tolist()) == oracle.bitmap_to_set(n, O)
+    assert by_sib.any() and (M & ~by_sib).any()
