@@ -533,9 +533,14 @@ def main():
                  "split_top_digit": dqmc.dqmc_get_split(ctx.ctx, n),
                  "autotune_trials": [["split" if t["split"] else t["sizes"], round(t["ms"], 3)]
                                      for t in plan_trials]},
+        # achieved: the pass's model bytes (reads and writes of every word) per
+        # second; the in-place reduces skip the stores of segments that were
+        # zero as loaded, so the counter traffic can be below the model, and
+        # traffic_GBps is the measured HBM rate
         "roofline": {"bound": "hbm", "kernel": dom["name"], "achieved": achieved, "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
-                     "traffic": traffic, "model_bytes_per_launch": dom_bytes},
+                     "traffic": traffic, "model_bytes_per_launch": dom_bytes,
+                     "traffic_GBps": traffic / (dom["ms"] / 1e3) / 1e9 if traffic else None},
         "paper_context": {"n24_seconds_one_core": PAPER_N24_SECONDS,
                           "n24_cubes_per_s": cubes / PAPER_N24_SECONDS if n == 24 else None},
     }

@@ -153,10 +153,10 @@ __global__ __launch_bounds__(kColThreads) __attribute__((amdgpu_waves_per_eu(5))
 __global__ __launch_bounds__(768) void tb_reduce_kernel(TileBatch b)
 {
     extern __shared__ uint32_t t[];
-    __shared__ uint32_t red[kMapWords + 1];
+    __shared__ uint32_t red[2 * kMapWords + 1];  // the upper half is unused here
     const uint32_t tile = blockIdx.x;
     const TileJob &j = b.jobs[b.tile_job[tile]];
-    reduce_full_tile(t, j.state + (uint64_t)(tile - j.first_tile) * kTileL, b.counts + tile,
+    reduce_full_tile<false>(t, j.state + (uint64_t)(tile - j.first_tile) * kTileL, b.counts + tile,
                      b.chunkmap + (uint64_t)tile * kMapWords, red);
 }
 

@@ -179,6 +179,15 @@ __global__ __launch_bounds__(col_threads<GW>()) void col_kernel(ColArgs a)
             x[c] = active ? ROW(c)[l] : 0u;
         });
     }
+    // Reduce-only mode works in place and only clears bits: a row whose 64
+    // words are all zero as loaded stays zero and is not stored again.
+    uint32_t live[(CR + 31) / 32] = {};
+    if constexpr (!NEED_MERGE) {
+        static_for<CR>([&](auto ci) {
+            constexpr int c = decltype(ci)::value;
+            if (__ballot(x[c] != 0u) != 0) live[c / 32] |= 1u << (c % 32);
+        });
+    }
 
     if constexpr (NEED_REDUCE) {
         // 4. wave digits first, all against the star neighbours' values
@@ -225,7 +234,8 @@ __global__ __launch_bounds__(col_threads<GW>()) void col_kernel(ColArgs a)
             const bool cw_allstar = (GW == 0) || (cw == CW - 1);
             static_for<CR>([&](auto ci) {
                 constexpr int c = decltype(ci)::value;
-                if (MODE == kColMergeReduce || !(cw_allstar && c == CR - 1)) ROW(c)[l] = x[c];
+                if (MODE == kColMergeReduce || (!(cw_allstar && c == CR - 1) && ((live[c / 32] >> (c % 32)) & 1u)))
+                    ROW(c)[l] = x[c];
             });
         }
     }

@@ -70,7 +70,7 @@ __global__ __launch_bounds__(low_threads<MODE>()) void low_kernel(LowArgs a)
             if (threadIdx.x == 0 && a.count != nullptr) *a.count = total;
         }
     } else {
-        __shared__ uint32_t red[kMapWords + 1];
+        __shared__ uint32_t red[2 * kMapWords + 1];
         // Consecutive tiles on one XCD, as in the column passes (n = 24, the
         // final reduce: 16.6 -> 14.6 ms against round-robin tiles).  Every
         // tile here is a full read of equal cost; the list pass and the batch
@@ -79,7 +79,7 @@ __global__ __launch_bounds__(low_threads<MODE>()) void low_kernel(LowArgs a)
         const uint32_t *src = a.state + tile * a.tw;
         if constexpr (MODE == kLowReduceCount) {
             // always a full tile here (n > 12)
-            reduce_full_tile(t, a.state + tile * a.tw, a.counts + tile, a.chunkmap + tile * kMapWords, red);
+            reduce_full_tile<true>(t, a.state + tile * a.tw, a.counts + tile, a.chunkmap + tile * kMapWords, red);
             return;
         } else {
             load_tile<false, THREADS>(t, src, a.tw);

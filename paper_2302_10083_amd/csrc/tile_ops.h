@@ -128,10 +128,14 @@ __device__ __forceinline__ uint64_t tile_list(const uint32_t *t, uint32_t tw, in
 }
 
 // Copy a tile from HBM into LDS (optionally applying the in-word Reduce),
-// with every load of a thread issued before the first LDS store.
+// with every load of a thread issued before the first LDS store.  With
+// `innz` (kMapWords words of LDS, zeroed before), bit k records that 64-word
+// chunk k of the tile held a non-zero word as loaded (THREADS is a multiple
+// of 64, so each wavefront load covers exactly one chunk).
 template <bool REDUCE, int THREADS>
-__device__ __forceinline__ void load_tile(uint32_t *t, const uint32_t *src, uint32_t tw)
+__device__ __forceinline__ void load_tile(uint32_t *t, const uint32_t *src, uint32_t tw, uint32_t *innz = nullptr)
 {
+    static_assert(THREADS % kChunkWords == 0, "one chunk per wavefront load");
     constexpr int U = (kMaxTileWords + THREADS - 1) / THREADS;
     uint32_t v[U];
     // (src + u * THREADS) is uniform: one scalar base per step, one lane offset
@@ -144,6 +148,13 @@ __device__ __forceinline__ void load_tile(uint32_t *t, const uint32_t *src, uint
         constexpr int u = decltype(ui)::value;
         if (threadIdx.x + u * THREADS < tw) t[threadIdx.x + u * THREADS] = REDUCE ? inword_reduce(v[u]) : v[u];
     });
+    if (innz != nullptr) {
+        static_for<U>([&](auto ui) {
+            constexpr int u = decltype(ui)::value;
+            const uint32_t k = (threadIdx.x + u * THREADS) / kChunkWords;
+            if (__ballot(v[u] != 0u) != 0 && lane_id() == 0) atomicOr(&innz[k / 32], 1u << (k % 32));
+        });
+    }
 }
 
 template <int THREADS>
@@ -166,8 +177,12 @@ __device__ __forceinline__ void store_tile(uint32_t *dst, const uint32_t *t, uin
 // owns column q, reduces it, and writes it to HBM (the prime bitmap);
 // consecutive threads write consecutive words.  It also builds the tile
 // summary in `red` (zeroed before): red[0] = set bits, red[1..] = map of the
-// non-zero 64-word chunks.
-__device__ __forceinline__ void last_round_to_hbm(uint32_t *t, uint32_t *dst, uint32_t *red)
+// non-zero 64-word chunks.  The tile is reduced in place in HBM and a Reduce
+// only clears bits, so a wavefront's 64-word store is skipped when every
+// 64-word chunk it overlaps was zero as loaded (`innz`, from load_tile):
+// those words are zero already.
+template <bool SKIP_ZERO>
+__device__ __forceinline__ void last_round_to_hbm(uint32_t *t, uint32_t *dst, uint32_t *red, const uint32_t *innz)
 {
     constexpr uint32_t S = 729;
     const uint32_t q = threadIdx.x;
@@ -179,9 +194,12 @@ __device__ __forceinline__ void last_round_to_hbm(uint32_t *t, uint32_t *dst, ui
             x[k] = t[q + k * S];
         });
         reg_reduce<3>(x);
+        const uint32_t q0 = q & ~63u;  // first column of this wavefront
+        const uint32_t q1 = q0 + 63u < S ? q0 + 63u : S - 1u;
         static_for<27>([&](auto ci) {
             constexpr int k = decltype(ci)::value;
-            dst[q + k * S] = x[k];
+            const uint32_t c0 = (q0 + k * S) / kChunkWords, c1 = (q1 + k * S) / kChunkWords;
+            if (!SKIP_ZERO || (((innz[c0 / 32] >> (c0 % 32)) | (innz[c1 / 32] >> (c1 % 32))) & 1u)) dst[q + k * S] = x[k];
             c += __popc(x[k]);
             if (x[k] != 0u) {
                 const uint32_t chunk = (q + k * S) / kChunkWords;
@@ -197,18 +215,25 @@ __device__ __forceinline__ void last_round_to_hbm(uint32_t *t, uint32_t *dst, ui
 // digits 1..3 on the way into LDS, digits 4..6 and 7..9 in LDS, digits
 // 10..12 in the last round straight back to HBM (the prime bitmap), and the
 // tile summary: *count = its set bits, map[0..kMapWords) = its non-zero
-// 64-word chunks.  `red` is kMapWords + 1 words of LDS.
+// 64-word chunks.  `red` is 2 * kMapWords + 1 words of LDS.  SKIP_ZERO
+// leaves out the stores of chunks that were zero as loaded (see
+// last_round_to_hbm); it pays where most of the tile is zero (a single large
+// function) and costs more than it saves on the small tiles of a batch.
+template <bool SKIP_ZERO>
 __device__ __forceinline__ void reduce_full_tile(uint32_t *t, uint32_t *tile, uint32_t *count, uint32_t *map,
                                                  uint32_t *red)
 {
-    if (threadIdx.x < kMapWords + 1) red[threadIdx.x] = 0;
-    load_tile<true, 768>(t, tile, kMaxTileWords);
+    // red[kMapWords + 1 ..] holds the input-chunk flags of load_tile
+    uint32_t *innz = red + kMapWords + 1;
+    if (threadIdx.x < 2 * kMapWords + 1) red[threadIdx.x] = 0;
+    if constexpr (SKIP_ZERO) __syncthreads();  // flags zeroed before load_tile sets them
+    load_tile<true, 768>(t, tile, kMaxTileWords, SKIP_ZERO ? innz : nullptr);
     __syncthreads();
     lds_group<3, false>(t, kMaxTileWords, 1);
     __syncthreads();
     lds_group<3, false>(t, kMaxTileWords, 27);
     __syncthreads();
-    last_round_to_hbm(t, tile, red);
+    last_round_to_hbm<SKIP_ZERO>(t, tile, red, innz);
     __syncthreads();
     if (threadIdx.x == 0) *count = red[0];
     if (threadIdx.x < kMapWords) map[threadIdx.x] = red[1 + threadIdx.x];
