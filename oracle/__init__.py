@@ -13,6 +13,9 @@ arXiv 2302.10083):
 * ``enum_M`` / ``enum_O``: the Lemma of Sec. 4.1 (MergeAll, ReduceAll),
   cube by cube in increasing rho; the O formula is read with OR (see
   ``dqmc_oracle.c``).
+* ``enum_O_range`` / ``primes_range``: the same O formula on one range of
+  rho only, reading the whole M ("streaming": the O bitmap of the whole
+  function is never held, so n = 24 fits next to its 35.3 GB M).
 * ``extract``: set bits in increasing rho (Alg. 4, output step).
 
 Cube index rho(s) = sum 3^(i-1) rho(s_i), with 0, 1, * -> 0, 1, 2 (Sec. 4.2).
@@ -63,8 +66,12 @@ def _load():
             lib.orc_enum_M.argtypes = [i32, vp, vp, i32]
             lib.orc_enum_O.restype = None
             lib.orc_enum_O.argtypes = [i32, vp, vp, i32]
+            lib.orc_enum_O_range.restype = None
+            lib.orc_enum_O_range.argtypes = [i32, vp, u64, u64, vp, i32]
             lib.orc_extract.restype = u64
             lib.orc_extract.argtypes = [i32, vp, vp, u64]
+            lib.orc_extract_bits.restype = u64
+            lib.orc_extract_bits.argtypes = [u64, vp, vp, u64, u64]
             lib.orc_sample.restype = i32
             lib.orc_sample.argtypes = [i32, vp, vp, u64, vp, i32, i32]
             _lib = lib
@@ -120,6 +127,32 @@ def enum_O(n: int, M: np.ndarray, threads: int = 0) -> np.ndarray:
     O = np.zeros(bitmap_words(n), dtype=np.uint64)
     _load().orc_enum_O(n, M.ctypes.data, O.ctypes.data, threads)
     return O
+
+
+def enum_O_range(n: int, M: np.ndarray, r0: int, r1: int, threads: int = 0) -> np.ndarray:
+    """O on the cubes r0 <= rho < r1 only: a bitmap whose bit k is cube
+    r0 + k (ceil((r1 - r0) / 64) words)."""
+    assert 0 <= r0 <= r1 <= 3**n
+    M = np.ascontiguousarray(M, dtype=np.uint64)
+    assert M.size >= bitmap_words(n)
+    out = np.zeros(max(1, (r1 - r0 + 63) // 64), dtype=np.uint64)
+    _load().orc_enum_O_range(n, M.ctypes.data, r0, r1, out.ctypes.data, threads)
+    return out
+
+
+def extract_bits(nbits: int, bm: np.ndarray, base: int = 0) -> np.ndarray:
+    """Set bits of a bitmap whose bit k is cube base + k, ascending."""
+    bm = np.ascontiguousarray(bm, dtype=np.uint64)
+    lib = _load()
+    cnt = int(lib.orc_extract_bits(nbits, bm.ctypes.data, None, 0, base))
+    out = np.zeros(max(cnt, 1), dtype=np.uint64)
+    lib.orc_extract_bits(nbits, bm.ctypes.data, out.ctypes.data, cnt, base)
+    return out[:cnt]
+
+
+def primes_range(n: int, M: np.ndarray, r0: int, r1: int, threads: int = 0) -> np.ndarray:
+    """Sorted primes with r0 <= rho < r1, from the whole implicant bitmap M."""
+    return extract_bits(r1 - r0, enum_O_range(n, M, r0, r1, threads), r0)
 
 
 def extract(n: int, O: np.ndarray, cap: int | None = None):

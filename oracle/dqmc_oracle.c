@@ -236,7 +236,7 @@ void orc_enum_M(int n, const uint32_t *tt, uint64_t *M, int nthreads)
     memset(M, 0, nw * 8);
     int T = resolve_threads(nthreads);
     if (T > 256) T = 256;
-    int t = n < 4 ? n : 4;
+    int t = n < 6 ? n : 6;
     uint64_t nb = orc_pow3(t);
     uint64_t *blocks = (uint64_t *)malloc(nb * sizeof(uint64_t));
     for (int lev = 0; lev <= t; ++lev) {
@@ -259,12 +259,15 @@ void orc_enum_M(int n, const uint32_t *tt, uint64_t *M, int nthreads)
 /* Prime bitmap by the Lemma's formula for O (Sec. 4.1), read with OR: the
  * printed formula uses a big AND, but s is redundant as soon as ONE merge
  * s + t = u has M(u) = 1 (Alg. 1 marks both merged implicants redundant):
- *   O(s) = M(s) AND NOT OR_{i : s_i != *} M(s with digit i set to *). */
+ *   O(s) = M(s) AND NOT OR_{i : s_i != *} M(s with digit i set to *).
+ * Each cube only reads M, so any range of rho can be evaluated on its own:
+ * the range [r0, r0 + nbits) goes to a bitmap whose bit k is cube r0 + k
+ * (a "streaming" sweep that never holds the whole O bitmap). */
 typedef struct {
     int n;
     const uint64_t *M;
     uint64_t *O;
-    uint64_t nwords;
+    uint64_t r0, nbits, nwords;
     uint64_t next;
 } osweep_job;
 
@@ -274,19 +277,20 @@ static void *osweep_worker(void *arg)
 {
     osweep_job *J = (osweep_job *)arg;
     int n = J->n, d[MAXN];
-    uint64_t N = orc_pow3(n), p3[MAXN];
+    uint64_t p3[MAXN];
     for (int i = 0; i < n; ++i) p3[i] = orc_pow3(i);
     for (;;) {
         uint64_t c = __atomic_fetch_add(&J->next, 1, __ATOMIC_RELAXED);
         uint64_t w0 = c * OCHUNK;
         if (w0 >= J->nwords) break;
         uint64_t w1 = w0 + OCHUNK < J->nwords ? w0 + OCHUNK : J->nwords;
-        digits_of(n, w0 * 64, d);
+        digits_of(n, J->r0 + w0 * 64, d);
         for (uint64_t w = w0; w < w1; ++w) {
             uint64_t ow = 0;
             for (uint64_t b = 0; b < 64; ++b) {
-                uint64_t r = w * 64 + b;
-                if (r >= N) break;
+                uint64_t k = w * 64 + b;
+                if (k >= J->nbits) break;
+                uint64_t r = J->r0 + k;
                 if (bm_get(J->M, r)) {
                     int red = 0;
                     for (int i = 0; i < n && !red; ++i)
@@ -304,10 +308,12 @@ static void *osweep_worker(void *arg)
     return NULL;
 }
 
-void orc_enum_O(int n, const uint64_t *M, uint64_t *O, int nthreads)
+/* O restricted to the cubes r0 <= rho < r1 (r1 <= 3^n), from the whole M:
+ * out receives ceil((r1 - r0) / 64) words, bit k = O(r0 + k). */
+void orc_enum_O_range(int n, const uint64_t *M, uint64_t r0, uint64_t r1, uint64_t *out, int nthreads)
 {
-    uint64_t N = orc_pow3(n);
-    osweep_job J = {n, M, O, (N + 63) / 64, 0};
+    uint64_t nbits = r1 > r0 ? r1 - r0 : 0;
+    osweep_job J = {n, M, out, r0, nbits, (nbits + 63) / 64, 0};
     int T = resolve_threads(nthreads);
     if (T > 256) T = 256;
     pthread_t th[256];
@@ -315,22 +321,35 @@ void orc_enum_O(int n, const uint64_t *M, uint64_t *O, int nthreads)
     for (int i = 0; i < T; ++i) pthread_join(th[i], NULL);
 }
 
-/* Extraction (Alg. 4, last step): every rho whose bit is set, in increasing
- * rho.  Writes the first min(count, cap) entries; returns the count. */
-uint64_t orc_extract(int n, const uint64_t *O, uint64_t *list, uint64_t cap)
+void orc_enum_O(int n, const uint64_t *M, uint64_t *O, int nthreads)
 {
-    uint64_t N = orc_pow3(n), nw = (N + 63) / 64, cnt = 0;
+    orc_enum_O_range(n, M, 0, orc_pow3(n), O, nthreads);
+}
+
+/* Set bits of a bitmap of nbits bits whose bit k stands for cube base + k,
+ * in increasing order.  Writes the first min(count, cap) entries; returns the
+ * count. */
+uint64_t orc_extract_bits(uint64_t nbits, const uint64_t *O, uint64_t *list, uint64_t cap, uint64_t base)
+{
+    uint64_t nw = (nbits + 63) / 64, cnt = 0;
     for (uint64_t w = 0; w < nw; ++w) {
         uint64_t v = O[w];
         while (v) {
-            uint64_t r = w * 64 + (uint64_t)__builtin_ctzll(v);
+            uint64_t k = w * 64 + (uint64_t)__builtin_ctzll(v);
             v &= v - 1;
-            if (r >= N) break;
-            if (list && cnt < cap) list[cnt] = r;
+            if (k >= nbits) break;
+            if (list && cnt < cap) list[cnt] = base + k;
             ++cnt;
         }
     }
     return cnt;
+}
+
+/* Extraction (Alg. 4, last step): every rho whose bit is set, in increasing
+ * rho.  Writes the first min(count, cap) entries; returns the count. */
+uint64_t orc_extract(int n, const uint64_t *O, uint64_t *list, uint64_t cap)
+{
+    return orc_extract_bits(orc_pow3(n), O, list, cap, 0);
 }
 
 /* ------------------------------------------------------------------------

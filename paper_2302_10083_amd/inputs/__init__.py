@@ -196,8 +196,12 @@ CONFIGS = {
     "c2a_n20_bern09": dict(n=20, kind="bernoulli", p=0.9, seed=2001),
     "c2b_n20_dnf200": dict(n=20, kind="dnf", terms=200, wlo=4, whi=10, seed=2002),
     "c3_n24_dnf2000_noise": dict(n=24, kind="dnf+noise", terms=2000, wlo=6, whi=14, p=0.02, seed=24),
-    # the same recipe at n = 25 (the largest single state) and at n = 26, 27,
-    # past one state in HBM (the sliced path)
+    # the same recipe at n = 21..23 (exact block digests next to n = 24), at
+    # n = 25 (the largest single state) and at n = 26, 27, past one state in
+    # HBM (the sliced path)
+    "c3x_n21_dnf2000_noise": dict(n=21, kind="dnf+noise", terms=2000, wlo=6, whi=14, p=0.02, seed=21),
+    "c3x_n22_dnf2000_noise": dict(n=22, kind="dnf+noise", terms=2000, wlo=6, whi=14, p=0.02, seed=22),
+    "c3x_n23_dnf2000_noise": dict(n=23, kind="dnf+noise", terms=2000, wlo=6, whi=14, p=0.02, seed=23),
     "c3x_n25_dnf2000_noise": dict(n=25, kind="dnf+noise", terms=2000, wlo=6, whi=14, p=0.02, seed=25),
     "c3x_n26_dnf2000_noise": dict(n=26, kind="dnf+noise", terms=2000, wlo=6, whi=14, p=0.02, seed=26),
     "c3x_n27_dnf2000_noise": dict(n=27, kind="dnf+noise", terms=2000, wlo=6, whi=14, p=0.02, seed=27),

@@ -464,3 +464,88 @@ def test_sibling_form_of_the_reduce(n, kind, seed):
     assert np.array_equal(by_star, by_sib)
     assert set(np.flatnonzero(by_sib).tolist()) == oracle.bitmap_to_set(n, O)
     assert by_sib.any() and (M & ~by_sib).any()
+
+
+# ----------------------------------------------------------------------------
+# the ranged ("streaming") O sweep and the block digests built on it
+
+
+@pytest.mark.parametrize("n", list(range(0, 15)))
+def test_ranged_sweep_matches_whole_and_bruteforce(n):
+    """O evaluated one block of the top digits at a time, and on random
+    unaligned ranges, gives the whole function's primes; for n <= 11 that list
+    is also the brute force's (per-cube definitions of Sec. 2)."""
+    tt = inputs.bernoulli(n, 0.85, 900 + n) if n % 2 else inputs.dnf(n, 3 * n + 1, 1, max(1, n // 2), 900 + n)
+    M = oracle.enum_M(n, tt)
+    whole, _ = oracle.extract(n, oracle.enum_O(n, M))
+    if n <= 11:
+        _, Ob = oracle.bruteforce(n, tt)
+        ref, _ = oracle.extract(n, Ob)
+        assert np.array_equal(whole, ref)
+    top = min(n, 4)
+    bs = 3 ** (n - top)
+    parts = [oracle.primes_range(n, M, b * bs, (b + 1) * bs) for b in range(3**top)]
+    assert np.array_equal(np.concatenate(parts), whole)
+    rng = np.random.default_rng(n)
+    for _ in range(8):
+        a, b = sorted(int(v) for v in rng.integers(0, 3**n + 1, size=2))
+        got = oracle.primes_range(n, M, a, b)
+        assert np.array_equal(got, whole[(whole >= a) & (whole < b)]), (a, b)
+
+
+@pytest.mark.parametrize("n,a,b", [(14, 5, 9), (13, 0, 13), (12, 6, 6)])
+def test_ranged_sweep_closed_form(n, a, b):
+    """Interval-symmetric f = [a <= |x| <= b]: its primes are the cubes with
+    exactly a ones and b - a stars; the block-wise sweep lists exactly them."""
+    M = oracle.enum_M(n, inputs.interval(n, a, b))
+    bs = 3 ** (n - 4)
+    got = np.concatenate([oracle.primes_range(n, M, k * bs, (k + 1) * bs) for k in range(81)])
+    ref = sorted(r for r in _cubes_with(n, a, b - a))
+    assert got.tolist() == ref
+
+
+def _cubes_with(n, ones, stars):
+    for pos in itertools.combinations(range(n), ones + stars):
+        for sp in itertools.combinations(pos, stars):
+            yield sum((2 if i in sp else 1) * 3**i for i in pos)
+
+
+def test_block_digests_match_list_digests():
+    """The digest writer's per-block form equals digests of the whole list,
+    and a change to one prime changes exactly its block's line."""
+    import sys
+    sys.path.insert(0, GOLDEN)
+    import make_block_digests as mbd
+
+    for name, n in (("c3x", 12), ("c3x", 9)):
+        spec = dict(inputs.CONFIGS["c3x_n21_dnf2000_noise"], n=n, seed=77 + n)
+        tt = inputs.make(spec)
+        M, O, lst = oracle.primes(n, tt)
+        rows = mbd.block_digests(n, M)
+        assert rows == mbd.digests_of_list(n, lst)
+        assert sum(c for c, _ in rows) == lst.size
+        bad = lst.copy()
+        k = bad.size // 2
+        bad = np.delete(bad, k)
+        rows_bad = mbd.digests_of_list(n, bad)
+        diff = [i for i in range(81) if rows_bad[i] != rows[i]]
+        assert diff == [int(lst[k]) // 3 ** (n - 4)]
+
+
+@pytest.mark.parametrize("config", ["c3x_n21_dnf2000_noise", "c3x_n22_dnf2000_noise",
+                                    "c3x_n23_dnf2000_noise", "c3_n24_dnf2000_noise"])
+def test_block_digest_files_well_formed(config):
+    import sys
+    sys.path.insert(0, GOLDEN)
+    import make_block_digests as mbd
+
+    if not os.path.exists(mbd.path_for(config)):
+        pytest.skip("digest file not written yet")
+    n, top, total, rows = mbd.read(config)
+    assert n == inputs.CONFIGS[config]["n"] and top == 4
+    assert len(rows) == 81 and sum(c for c, _ in rows) == total
+    assert all(len(h) == 64 for _, h in rows)
+    # the empty block's digest is the SHA-256 of no bytes
+    import hashlib
+    empty = hashlib.sha256(b"").hexdigest()
+    assert all((c == 0) == (h == empty) for c, h in rows)
