@@ -53,30 +53,63 @@ def read_traffic(kernel: str, workload: str):
         return None
 
 
-def cpu_baseline(n, tt, seconds, threads):
-    """The oracle's per-cube prime test on uniformly random cubes of the same
-    function, on the host cores, for about `seconds` seconds."""
+def host_info():
+    """nproc, CPU model and RAM of the host the baseline ran on."""
+    info = {"nproc": os.cpu_count(), "cpu_share": len(os.sched_getaffinity(0))}
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    info["cpu_model"] = line.split(":", 1)[1].strip()
+                    break
+        with open("/proc/meminfo") as f:
+            for line in f:
+                if line.startswith("MemTotal"):
+                    info["ram_GB"] = round(int(line.split()[1]) * 1024 / 1e9, 1)
+                    break
+    except OSError:
+        pass
+    return info
+
+
+def baseline_threads(requested):
+    """Host threads for the oracle: every core of this process's CPU share,
+    at most 16 (one GPU's share of the host cores) unless asked otherwise."""
+    if requested > 0:
+        return requested
+    return max(1, min(len(os.sched_getaffinity(0)), 16))
+
+
+def oracle_o2_seconds(n, tt, threads):
+    """The oracle's definitional enumerator (O2: the M sweep of the Lemma of
+    Sec. 4.1, then the O formula over every cube), timed on the host."""
+    import oracle
+
+    t0 = time.perf_counter()
+    M = oracle.enum_M(n, tt, threads)
+    t1 = time.perf_counter()
+    O = oracle.enum_O(n, M, threads)
+    t2 = time.perf_counter()
+    lst, cnt = oracle.extract(n, O)
+    t3 = time.perf_counter()
+    return dict(M_s=t1 - t0, O_s=t2 - t1, extract_s=t3 - t2, total_s=t3 - t0, primes=int(cnt)), lst
+
+
+def cpu_baseline(n, tt, sub_n, threads):
+    """O2 on a bounded sample of the workload: the restriction of f to
+    x_(sub_n+1) = ... = x_n = 0, a function of sub_n variables whose cubes are
+    the first 3^sub_n cubes of f's cube space (the block whose top n - sub_n
+    digits are all 0).  Returns (cubes/s, threads, details, sorted primes of
+    the restriction)."""
     import numpy as np
 
-    import oracle
-    from paper_2302_10083_amd import inputs
-
-    k = 2000
-    done, elapsed, used = 0, 0.0, 0
-    rhos_all = []
-    res_all = []
-    while elapsed < seconds:
-        r = (inputs.u64_array(0xC0FFEE, k, start=done) % np.uint64(3**n)).astype(np.uint64)
-        t0 = time.perf_counter()
-        res, used = oracle.sample(n, tt, r, "prime", threads)
-        dt = time.perf_counter() - t0
-        elapsed += dt
-        done += k
-        rhos_all.append(r)
-        res_all.append(res)
-        if dt < seconds / 8:
-            k *= 2
-    return done / elapsed, used, elapsed, np.concatenate(rhos_all), np.concatenate(res_all)
+    sub_n = min(sub_n, n)
+    words = max(1, (1 << sub_n) // 32)
+    sub_tt = np.ascontiguousarray(np.asarray(tt, dtype=np.uint32)[:words])
+    if sub_n < 5:
+        sub_tt = sub_tt & np.uint32((1 << (1 << sub_n)) - 1)
+    det, lst = oracle_o2_seconds(sub_n, sub_tt, threads)
+    return 3**sub_n / det["total_s"], threads, det, sub_tt, lst
 
 
 def bench_batch(ctx, reps=5):
@@ -258,10 +291,12 @@ def bench_sliced(ctx, workload="c3x_n26_dnf2000_noise", ts=((2, 1), (2, 3), (1, 
     return out
 
 
-def bench_configs(ctx, n24_tt=None, n24_list=None):
+def bench_configs(ctx, n24_tt=None, n24_list=None, oracle_threads=0):
     """The smaller named workloads: n = 12 latency (median of 1000 calls) and
     n = 20 (median of 5), plus the host transfers the main step leaves out
-    (truth table in, prime list out, pinned host memory)."""
+    (truth table in, prime list out, pinned host memory).  With
+    oracle_threads > 0 the oracle's O2 is timed on each whole workload as
+    well, and its prime list is compared with the GPU's."""
     import numpy as np
     import torch
 
@@ -272,7 +307,8 @@ def bench_configs(ctx, n24_tt=None, n24_list=None):
     for name, reps in (("c1_n12_bern05", 1000), ("c2a_n20_bern09", 5), ("c2b_n20_dnf200", 5)):
         spec = inputs.CONFIGS[name]
         n = spec["n"]
-        ttd = ctx.tt_to_device(inputs.make(spec))
+        tt = inputs.make(spec)
+        ttd = ctx.tt_to_device(tt)
         state = ctx.new_state(n)
         count = torch.zeros(1, dtype=torch.int64, device=dev)
         dqmc.dqmc_primes(ctx.ctx, n, ttd, state, None, 0, count)
@@ -292,6 +328,12 @@ def bench_configs(ctx, n24_tt=None, n24_list=None):
                "cubes_per_s": 3**n / (med / 1e3)}
         if n == 12:
             row["median_us"] = med * 1e3
+        if oracle_threads > 0:
+            det, ref = oracle_o2_seconds(n, tt, oracle_threads)
+            row["oracle_O2"] = dict(det, threads=oracle_threads, cubes_per_s=3**n / det["total_s"],
+                                    gpu_over_oracle=det["total_s"] / (med / 1e3),
+                                    list_equal=bool(len(ref) == c and np.array_equal(
+                                        lst[:c].cpu().numpy().view(np.uint64), ref)))
         out[name] = row
         print("bench: %s median %.4f ms" % (name, med), file=sys.stderr, flush=True)
         del state, lst
@@ -419,8 +461,9 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c3_n24_dnf2000_noise")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--cpu-threads", type=int, default=16)
+    ap.add_argument("--cpu-sub-n", type=int, default=21,
+                    help="the CPU baseline runs the oracle on f restricted to its first CPU_SUB_N variables")
+    ap.add_argument("--cpu-threads", type=int, default=0, help="0: every core of the CPU share, at most 16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
@@ -540,23 +583,37 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom["name"], "achieved": achieved, "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
                      "traffic": traffic, "model_bytes_per_launch": dom_bytes,
-                     "traffic_GBps": traffic / (dom["ms"] / 1e3) / 1e9 if traffic else None},
+                     "traffic_GBps": traffic / (dom["ms"] / 1e3) / 1e9 if traffic else None,
+                     "frac_traffic": traffic / (dom["ms"] / 1e3) / 1e9 / HBM_PEAK_GBPS if traffic else None},
         "paper_context": {"n24_seconds_one_core": PAPER_N24_SECONDS,
                           "n24_cubes_per_s": cubes / PAPER_N24_SECONDS if n == 24 else None},
     }
 
     if not args.no_cpu_baseline:
-        rate, used, el, rhos, ref = cpu_baseline(n, tt, args.cpu_seconds, args.cpu_threads)
-        # the sampled cubes double as a parity check of the GPU bitmap
-        r_t = torch.from_numpy(rhos.astype(np.int64)).to(dev)
-        words = torch.div(r_t, 27, rounding_mode="floor") if n >= 3 else torch.zeros_like(r_t)
-        bits = torch.remainder(r_t, 27) if n >= 3 else r_t
-        got = ((state[words].to(torch.int64) >> bits) & 1).cpu().numpy().astype(bool)
-        mism = int(np.count_nonzero(got != ref))
+        threads = baseline_threads(args.cpu_threads)
+        print("bench: oracle O2 on the %d-variable restriction, %d threads" % (min(args.cpu_sub_n, n), threads),
+              file=sys.stderr, flush=True)
+        rate, used, det, sub_tt, sub_primes = cpu_baseline(n, tt, args.cpu_sub_n, threads)
+        sub_n = min(args.cpu_sub_n, n)
+        # the restriction's primes double as a parity check of the GPU path
+        sub_ttd = ctx.tt_to_device(sub_tt)
+        sub_state = ctx.new_state(sub_n)
+        sub_count = torch.zeros(1, dtype=torch.int64, device=dev)
+        sub_list = torch.empty(max(len(sub_primes), 1), dtype=torch.int64, device=dev)
+        dqmc.dqmc_primes(ctx.ctx, sub_n, sub_ttd, sub_state, sub_list, len(sub_primes), sub_count)
+        torch.cuda.synchronize()
+        same = (int(sub_count.item()) == len(sub_primes) and
+                np.array_equal(sub_list[:len(sub_primes)].cpu().numpy().view(np.uint64), sub_primes))
+        del sub_ttd, sub_state, sub_list
         out["cpu_baseline"] = {"value": rate, "unit": "cubes/s", "cores": used, "kind": "oracle",
-                               "sample": "%d uniformly random cubes of the same n=%d function, per-cube "
-                                         "prime test (Sec. 2 definitions), %.1f s" % (len(rhos), n, el)}
-        out["sample_parity"] = {"cubes": int(len(rhos)), "primes_in_sample": int(ref.sum()), "mismatches": mism}
+                               "variant": "O2 (M sweep by the Lemma of Sec. 4.1, then the O formula)",
+                               "sample": "O2 of the n=%d workload restricted to x%d..x%d = 0: a %d-variable "
+                                         "function, the first 3^%d cubes of its cube space; %.1f s" %
+                                         (n, sub_n + 1, n, sub_n, sub_n, det["total_s"]),
+                               "seconds": det, "host": host_info(),
+                               "gpu_over_cpu": (cubes / (ms_step / 1e3)) / rate}
+        out["sample_parity"] = {"function": "restriction to x%d..x%d = 0" % (sub_n + 1, n), "n": sub_n,
+                                "oracle_primes": det["primes"], "gpu_equal": bool(same)}
     if not args.no_cnf:
         # CNF of a sparse function: the primes of its complement, with the
         # complement taken as the table is loaded (DQMC_NEGATE).  The sparse
@@ -579,7 +636,8 @@ def main():
         del sd
         print("bench: cnf %.2f ms" % ms_cnf, file=sys.stderr, flush=True)
     if not args.no_configs:
-        out["configs"] = bench_configs(ctx, tt if n == 24 else None, lst[:nprimes] if n == 24 else None)
+        out["configs"] = bench_configs(ctx, tt if n == 24 else None, lst[:nprimes] if n == 24 else None,
+                                       0 if args.no_cpu_baseline else baseline_threads(args.cpu_threads))
     if not args.no_batch or not args.no_sparse or not args.no_sliced:
         del lst, state
         torch.cuda.empty_cache()

@@ -1,5 +1,6 @@
 """Serving loop: every request's result is identical alone and in the mix
-(count, prime bitmap and list, compared through device hashes), admission
+(count, prime bitmap and list, compared through device hashes), every served
+list with n <= 18 equals the oracle's, admission
 never exceeds the memory budget, and bad requests fail alone."""
 import time
 
@@ -79,7 +80,7 @@ def test_alone_equals_mix():
         served = []
         for jid, s, tt in zip(ids, specs, tts):
             r, key = _served(srv, jid)
-            if s["n"] <= 14:
+            if s["n"] <= 18:
                 lst = srv.read(jid, r["listed"])
                 _, _, ref = oracle.primes(s["n"], tt)
                 assert r["count"] == len(ref) and np.array_equal(lst, ref[: len(lst)])
