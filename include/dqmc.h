@@ -55,7 +55,8 @@ typedef enum {
     DQMC_OK = 0,
     DQMC_EINVAL = -1,  /* bad argument (n out of range, NULL, bad size) */
     DQMC_ENOMEM = -2,  /* device allocation failed (context creation only) */
-    DQMC_EDEVICE = -3  /* a HIP runtime call failed */
+    DQMC_EDEVICE = -3, /* a HIP runtime call failed */
+    DQMC_ESCRATCH = -4 /* beyond the fixed scratch of dqmc_primes_noalloc */
 } dqmc_status;
 
 typedef struct dqmc_ctx dqmc_ctx;
@@ -116,6 +117,27 @@ int dqmc_primes(dqmc_ctx *ctx, int n, const uint32_t *d_tt, uint32_t *d_state, u
 int dqmc_implicants_ex(dqmc_ctx *ctx, int n, const uint32_t *d_tt, uint32_t flags, uint32_t *d_state, void *stream);
 int dqmc_primes_ex(dqmc_ctx *ctx, int n, const uint32_t *d_tt, uint32_t flags, uint32_t *d_state, uint64_t *d_list,
                    uint64_t list_cap, uint64_t *d_count, void *stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * results as dqmc_primes (prime bitmap O in d_state, sorted list, count), with
+ * no context.  Its kernels keep their per-tile summaries, list offsets and
+ * scan sums in a fixed device array of the library (27.6 MB: the summaries of
+ * the 3^12 tiles of n = 24; held on each device that runs the library until
+ * the process ends), so the call allocates nothing.  It runs on the current HIP
+ * device with the default pass plan and no top-digit split.
+ *   n         0 <= n <= 24.  n = 25 returns DQMC_ESCRATCH (its tile summaries
+ *             do not fit the fixed scratch); n outside [0, 25]: DQMC_EINVAL.
+ *   d_tt, d_state, d_list, list_cap, d_count: as for dqmc_primes.
+ * Calls on one device share that device's scratch: calls that overlap on one
+ * device (different streams, or different host threads without ordering)
+ * race and give wrong results; order them.  Nothing in the scratch needs to
+ * start at zero (every call overwrites what it reads).  The first call on a
+ * device looks up the scratch's device address and sets kernel attributes.
+ * Errors: DQMC_EINVAL (n, NULL, alignment), DQMC_ESCRATCH, DQMC_EDEVICE; there
+ * is no context, so no dqmc_last_error text. */
+int dqmc_primes_noalloc(int n, const uint32_t *d_tt, uint32_t *d_state, uint64_t *d_list, uint64_t list_cap,
+                        uint64_t *d_count, void *stream);
 
 /* Sparse path (Sec. 5): the classic level-by-level Quine-McCluskey method
  * (Alg. 1) with hash-based neighbour search, for functions of low density,

@@ -16,6 +16,7 @@
 
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <cmath>
 #include <vector>
 
@@ -382,6 +383,44 @@ std::vector<SliceKey> star_neighbours(uint64_t idx, int t)
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Fixed device scratch of dqmc_primes_noalloc: the per-tile summaries (set-bit
+// count and non-zero chunk map), the list offsets and the scan's block sums of
+// one function of at most kNoAllocMaxN variables.  Each device holds its own
+// copy for the life of the process.  In host code `scratch` names a host-side
+// stand-in: its device address comes from hipGetSymbolAddress, once per
+// device (noalloc_scratch below), and only that address is ever used.
+namespace {
+constexpr int kNoAllocMaxN = 24;
+constexpr uint64_t kNoAllocTiles = pow3(kNoAllocMaxN - kLowDigits);
+constexpr uint64_t kNoAllocSums = (kNoAllocTiles + 8191) / 8192 + 1;  // >= scan_scratch_words(tiles)
+// layout in uint64 words: offs | sums | counts (u32) | chunkmap (u32)
+constexpr uint64_t kNoAllocWords = kNoAllocTiles + kNoAllocSums + (kNoAllocTiles * (1 + kMapWords) + 1) / 2;
+constexpr int kNoAllocMaxDevices = 64;
+}  // namespace
+
+static __device__ __align__(256) uint64_t scratch[kNoAllocWords];
+
+namespace {
+std::mutex g_noalloc_mu;
+uint64_t *g_noalloc_ptr[kNoAllocMaxDevices];  // device address of `scratch`, per device
+
+// The device address of this device's scratch (the current device), with the
+// kernels' launch attributes set, on the first call on the device.  Returns
+// nullptr on a HIP error.
+uint64_t *noalloc_scratch(int dev)
+{
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (g_noalloc_ptr[dev] != nullptr) return g_noalloc_ptr[dev];
+    if (scan_scratch_words(kNoAllocTiles) > kNoAllocSums) return nullptr;
+    if (low_setup() != hipSuccess || col_setup() != hipSuccess) return nullptr;
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr) return nullptr;
+    g_noalloc_ptr[dev] = (uint64_t *)p;
+    return g_noalloc_ptr[dev];
+}
+}  // namespace
+
 extern "C" {
 
 uint64_t dqmc_num_cubes(int n) { return (n < 0 || n > DQMC_MAX_N) ? 0 : pow3(n); }
@@ -507,6 +546,47 @@ int dqmc_primes_ex(dqmc_ctx *ctx, int n, const uint32_t *d_tt, uint32_t flags, u
     rc = enqueue_reduce_high(ctx, n, d_tt, flip, d_state, s);
     if (rc != DQMC_OK) return rc;
     return enqueue_extract_tiles(ctx, n, kLowReduceCount, d_state, d_list, list_cap, d_count, s);
+}
+
+int dqmc_primes_noalloc(int n, const uint32_t *d_tt, uint32_t *d_state, uint64_t *d_list, uint64_t list_cap,
+                        uint64_t *d_count, void *stream)
+{
+    if (n < 0 || n > DQMC_MAX_N) return DQMC_EINVAL;
+    if (n > kNoAllocMaxN) return DQMC_ESCRATCH;
+    if (d_tt == nullptr || d_state == nullptr || d_count == nullptr) return DQMC_EINVAL;
+    if (!aligned(d_tt, 4) || !aligned(d_state, 4) || !aligned(d_count, 8) || !aligned(d_list, 8)) return DQMC_EINVAL;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kNoAllocMaxDevices) return DQMC_EDEVICE;
+    uint64_t *p = noalloc_scratch(dev);
+    if (p == nullptr) return DQMC_EDEVICE;
+    // a context on the stack whose scratch pointers lie in this device's
+    // static scratch: default pass plan, no top-digit split, no profiling
+    dqmc_ctx c{};
+    c.device = dev;
+    c.ncu = 256;
+    c.tiles_cap = kNoAllocTiles;
+    c.offs = p;
+    c.sums = p + kNoAllocTiles;
+    c.counts = (uint32_t *)(p + kNoAllocTiles + kNoAllocSums);
+    c.chunkmap = c.counts + kNoAllocTiles;
+    for (int i = 0; i <= DQMC_MAX_N; ++i) {
+        c.plan_len[i] = 0;
+        c.split[i] = 0;
+    }
+    if (check_common(&c, n) != DQMC_OK) return DQMC_EDEVICE;
+    hipStream_t s = (hipStream_t)stream;
+    if (n <= kLowDigits) {
+        LowArgs a = low_args(&c, n);
+        a.tt = d_tt;
+        a.state = d_state;
+        a.list = d_list;
+        a.cap = d_list ? list_cap : 0;
+        a.count = d_count;
+        return launch_low(kLowPrimesTT, a, 1, s) == hipSuccess ? DQMC_OK : DQMC_EDEVICE;
+    }
+    int rc = enqueue_reduce_high(&c, n, d_tt, 0u, d_state, s);
+    if (rc == DQMC_OK) rc = enqueue_extract_tiles(&c, n, kLowReduceCount, d_state, d_list, list_cap, d_count, s);
+    return rc;
 }
 
 int dqmc_set_split(dqmc_ctx *ctx, int n, int mode)

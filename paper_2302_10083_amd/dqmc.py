@@ -20,7 +20,7 @@ import threading
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdqmc.so")
 
-DQMC_OK, DQMC_EINVAL, DQMC_ENOMEM, DQMC_EDEVICE = 0, -1, -2, -3
+DQMC_OK, DQMC_EINVAL, DQMC_ENOMEM, DQMC_EDEVICE, DQMC_ESCRATCH = 0, -1, -2, -3, -4
 DQMC_MAX_N = 25
 
 _lib = None
@@ -118,6 +118,7 @@ def load():
             "dqmc_sparse_workspace_bytes": (u64, [i32, u64, u64]),
             "dqmc_sparse_primes": (i32, [vp, i32, vp, vp, u64, vp, vp, u64, ctypes.POINTER(ctypes.c_uint64), vp]),
             "dqmc_primes_ex": (i32, [vp, i32, vp, ctypes.c_uint32, vp, vp, u64, vp, vp]),
+            "dqmc_primes_noalloc": (i32, [i32, vp, vp, vp, u64, vp, vp]),
             "dqmc_extract": (i32, [vp, i32, vp, vp, u64, vp, vp]),
             "dqmc_primes_sliced": (i32, [vp, i32, i32, vp, ctypes.c_uint32, vp, vp, vp, u64, vp, vp]),
             "dqmc_primes_sliced_multi": (i32, [vp, i32, i32, vp, ctypes.c_uint32, vp, ctypes.POINTER(vp), i32, vp,
@@ -253,6 +254,20 @@ def dqmc_primes(ctx, n, tt, state, lst, list_cap, count, stream=None) -> None:
         _ptr(state, "state", torch.int32, dqmc_state_words(n)),
         _ptr(lst, "list", torch.int64, cap), cap,
         _ptr(count, "count", torch.int64, 1), _stream(stream)))
+
+
+def dqmc_primes_noalloc(n, tt, state, lst, list_cap, count, stream=None) -> None:
+    """No context: the library's fixed device scratch, on the current device."""
+    import torch
+
+    cap = 0 if lst is None else int(list_cap)
+    rc = load().dqmc_primes_noalloc(
+        n, _ptr(tt, "tt", torch.int32, dqmc_tt_words(n)),
+        _ptr(state, "state", torch.int32, dqmc_state_words(n)),
+        _ptr(lst, "list", torch.int64, cap), cap,
+        _ptr(count, "count", torch.int64, 1), _stream(stream))
+    if rc != DQMC_OK:
+        raise DqmcError(rc, "dqmc_primes_noalloc(n=%d) failed" % n)
 
 
 def dqmc_implicants_ex(ctx, n, tt, flags, state, stream=None) -> None:
