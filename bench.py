@@ -163,7 +163,7 @@ def bench_batch(ctx, reps=5):
     b.record()
     torch.cuda.synchronize()
     ms_single = a.elapsed_time(b)
-    state_bytes = sum(4 * 3 ** max(s["n"] - 3, 0) for s in specs)
+    state_bytes = sum(32 * 3 ** max(s["n"] - 5, 0) for s in specs)
     del g
     plan.close()
     return {"workload": "8192 functions, n uniform 6..16, half Bernoulli half DNF (seed 8192)",
@@ -250,7 +250,7 @@ def bench_sliced(ctx, workload="c3x_n26_dnf2000_noise", ts=((2, 1), (2, 3), (1, 
     ttd = ctx.tt_to_device(tt)
     count = torch.zeros(1, dtype=torch.int64, device=dev)
     out = {"workload": workload, "n": n, "cubes": 3**n, "truth_table": spec,
-           "single_state_GB": 4 * 3 ** (n - 3) / 1e9, "rows": []}
+           "single_state_GB": 32 * 3 ** (n - 5) / 1e9, "rows": []}
     lst = None
     for t, nm in ts:
         need = (1 + nm) * 4 * 3 ** (n - t - 3)
@@ -566,7 +566,7 @@ def main():
         "dtype": "u32",
         "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "cubes": cubes, "truth_table": spec,
-                   "primes": nprimes, "layout": "T27", "parallelism": "single-gpu"},
+                   "primes": nprimes, "layout": "H5 (243 cubes per 256-bit block)", "parallelism": "single-gpu"},
         "hbm_GBps_model": total_bytes / (ms_step / 1e3) / 1e9,
         "hbm_frac_model": total_bytes / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBPS,
         "model_bytes_per_step": total_bytes,

@@ -18,11 +18,14 @@
  *  truth     little-endian uint32 words, dqmc_tt_words(n) of them; bit x
  *  table     (word x/32, bit x%32) is f(x), where variable x_i is bit i-1 of
  *            x.  Bits at x >= 2^n (only when n < 5) are ignored.
- *  state     the 3^n-bit cube bitmap in the "T27" layout: dqmc_state_words(n)
- *            uint32 words; cube rho lives in word rho/27, bit rho%27 (n >= 3).
- *            For n < 3 there is one word and cube rho is bit rho.  Bits 27..31
- *            of every word (bits >= 3^n for n < 3) are always 0.  The order of
- *            the words is increasing rho.
+ *  state     the 3^n-bit cube bitmap in the "H5" block layout (the bottom
+ *            layer of Sec. 4.2 with h = 5): dqmc_state_words(n) uint32 words,
+ *            grouped in 256-bit blocks of 8 words; cube rho lives in block
+ *            rho/243 at bit p = rho%243, i.e. bit p%32 of word
+ *            8*(rho/243) + p/32.  For n < 5 there is one block and cube rho
+ *            is bit rho of it.  Bits 243..255 of every block (bits >= 3^n for
+ *            n < 5) are always 0.  The order of the words is increasing
+ *            rho.  States must be 16-byte aligned (DQMC_EINVAL otherwise).
  *  list      uint64 cube indices rho, strictly increasing.
  *  stream    a hipStream_t passed as void* (NULL = the null stream).
  *
@@ -78,7 +81,7 @@ const char *dqmc_last_error(const dqmc_ctx *ctx);
 /* Sizes (pure functions; 0 when n is out of range). */
 uint64_t dqmc_num_cubes(int n);    /* 3^n (Sec. 4.1: the state has one bit per cube) */
 uint64_t dqmc_tt_words(int n);     /* max(1, 2^(n-5)) uint32 words */
-uint64_t dqmc_state_words(int n);  /* 3^max(n-3, 0) uint32 words */
+uint64_t dqmc_state_words(int n);  /* 8 * 3^max(n-5, 0) uint32 words */
 uint64_t dqmc_dense_words(int n);  /* ceil(3^n / 64) uint64 words */
 
 /* Implicant bitmap M (Sec. 4.1, Lemma on MergeAll/ReduceAll; computed by the
@@ -217,7 +220,7 @@ int dqmc_primes_sliced_multi(dqmc_ctx *ctx, int n, int t, const uint32_t *d_tt, 
 int dqmc_extract(dqmc_ctx *ctx, int n, const uint32_t *d_state, uint64_t *d_list, uint64_t list_cap,
                  uint64_t *d_count, void *stream);
 
-/* Repack a T27 state into the exact 3^n-bit bitmap: bit rho of the
+/* Repack a block state into the exact 3^n-bit bitmap: bit rho of the
  * little-endian uint64 array d_dense (dqmc_dense_words(n) words, fully
  * overwritten; bits >= 3^n are 0).  Interoperability and tests; not part of
  * the prime computation. */
@@ -312,7 +315,7 @@ typedef struct {
     int32_t status;           /* DQMC_OK, or the error of the job's launch */
     uint64_t count;           /* number of primes */
     uint64_t listed;          /* entries in list: min(count, reserve) */
-    const uint32_t *state;    /* device: prime bitmap (T27 layout) */
+    const uint32_t *state;    /* device: prime bitmap (block layout) */
     const uint64_t *list;     /* device: the smallest `listed` primes, increasing */
     double t_submit, t_admit, t_done;
 } dqmc_result;
@@ -347,7 +350,7 @@ int dqmc_get_plan(const dqmc_ctx *ctx, int n, int32_t *sizes, int cap);
 
 /* Top-digit split of dqmc_primes / dqmc_primes_ex (12 < n <= 25): the
  * n-variable state is computed as its three consecutive thirds, the slices
- * of digit n = 0, 1, * (each an (n-1)-variable state of the same T27 layout),
+ * of digit n = 0, 1, * (each an (n-1)-variable state of the same block layout),
  * by the identity of dqmc_primes_sliced with t = 1: slice a holds the primes
  * of f_a, and slices 0 and 1 lose the cubes that are implicants of
  * f_* = f_0 AND f_1 (the Lemma of Sec. 4.1, one-step form, on digit n).

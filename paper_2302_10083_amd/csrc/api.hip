@@ -23,7 +23,7 @@
 #include "api_types.h"
 #include "dqmc.h"  // include/dqmc.h (the public C ABI)
 #include "launch.h"
-#include "t27.h"
+#include "h5.h"
 
 using namespace dqmc;
 
@@ -104,7 +104,11 @@ int check_common(dqmc_ctx *ctx, int n)
     return DQMC_OK;
 }
 
-double state_bytes(int n) { return 4.0 * (double)pow3(n > 3 ? n - 3 : 0); }
+double state_bytes(int n) { return 4.0 * kBlockWords * (double)pow3(n > 5 ? n - 5 : 0); }
+
+// States are read in 16-byte pieces (the final low pass loads a run of three
+// blocks per thread as four-word vectors).
+constexpr size_t kStateAlign = 16;
 double tt_bytes(int n) { return n <= 5 ? 4.0 : (double)(1ull << (n - 3)); }
 
 // Enqueue one kernel pass; with profiling on, bracket it with events.
@@ -131,8 +135,8 @@ LowArgs low_args(dqmc_ctx *ctx, int n)
 {
     LowArgs a{};
     a.n = n;
-    a.lw = n <= 3 ? 0 : (n - 3 < 9 ? n - 3 : 9);
-    a.tw = (uint32_t)pow3(a.lw);
+    a.lw = n <= 5 ? 0 : (n - 5 < 7 ? n - 5 : 7);
+    a.tw = kBlockWords * (uint32_t)pow3(a.lw);
     a.ntiles = n <= kLowDigits ? 1 : pow3(n - kLowDigits);
     a.counts = ctx->counts;
     a.chunkmap = ctx->chunkmap;
@@ -144,7 +148,7 @@ ColArgs col_args(uint32_t *state, int n, const Group &g, bool outer_binary)
 {
     ColArgs c{};
     c.state = state;
-    c.L = pow3(g.g0 - 4);
+    c.L = kBlockWords * pow3(g.g0 - 6);
     const uint64_t lanes = (uint64_t)col_lanes_per_block(g.gw);
     c.nlb = (c.L + lanes - 1) / lanes;
     const int od = n - (g.g0 + g.size() - 1);
@@ -425,7 +429,10 @@ extern "C" {
 
 uint64_t dqmc_num_cubes(int n) { return (n < 0 || n > DQMC_MAX_N) ? 0 : pow3(n); }
 uint64_t dqmc_tt_words(int n) { return (n < 0 || n > DQMC_MAX_N) ? 0 : (n <= 5 ? 1 : (1ull << (n - 5))); }
-uint64_t dqmc_state_words(int n) { return (n < 0 || n > DQMC_MAX_N) ? 0 : pow3(n > 3 ? n - 3 : 0); }
+uint64_t dqmc_state_words(int n)
+{
+    return (n < 0 || n > DQMC_MAX_N) ? 0 : kBlockWords * pow3(n > 5 ? n - 5 : 0);
+}
 uint64_t dqmc_dense_words(int n) { return (n < 0 || n > DQMC_MAX_N) ? 0 : (pow3(n) + 63) / 64; }
 
 int dqmc_create(int device, dqmc_ctx **out)
@@ -500,7 +507,7 @@ int dqmc_implicants_ex(dqmc_ctx *ctx, int n, const uint32_t *d_tt, uint32_t flag
     if ((flags & ~(uint32_t)DQMC_NEGATE) != 0u) return fail(ctx, DQMC_EINVAL, "%s", "unknown flag bits");
     const uint32_t flip = (flags & DQMC_NEGATE) ? ~0u : 0u;
     if (d_tt == nullptr || d_state == nullptr) return fail(ctx, DQMC_EINVAL, "%s", "NULL truth table or state");
-    if (!aligned(d_tt, 4) || !aligned(d_state, 4)) return fail(ctx, DQMC_EINVAL, "%s", "misaligned buffer");
+    if (!aligned(d_tt, 4) || !aligned(d_state, kStateAlign)) return fail(ctx, DQMC_EINVAL, "%s", "misaligned buffer");
     hipStream_t s = (hipStream_t)stream;
     if (n <= kLowDigits) {
         LowArgs a = low_args(ctx, n);
@@ -528,7 +535,7 @@ int dqmc_primes_ex(dqmc_ctx *ctx, int n, const uint32_t *d_tt, uint32_t flags, u
     const uint32_t flip = (flags & DQMC_NEGATE) ? ~0u : 0u;
     if (d_tt == nullptr || d_state == nullptr || d_count == nullptr)
         return fail(ctx, DQMC_EINVAL, "%s", "NULL truth table, state or count");
-    if (!aligned(d_tt, 4) || !aligned(d_state, 4) || !aligned(d_count, 8) || !aligned(d_list, 8))
+    if (!aligned(d_tt, 4) || !aligned(d_state, kStateAlign) || !aligned(d_count, 8) || !aligned(d_list, 8))
         return fail(ctx, DQMC_EINVAL, "%s", "misaligned buffer");
     hipStream_t s = (hipStream_t)stream;
     if (n <= kLowDigits) {
@@ -554,7 +561,8 @@ int dqmc_primes_noalloc(int n, const uint32_t *d_tt, uint32_t *d_state, uint64_t
     if (n < 0 || n > DQMC_MAX_N) return DQMC_EINVAL;
     if (n > kNoAllocMaxN) return DQMC_ESCRATCH;
     if (d_tt == nullptr || d_state == nullptr || d_count == nullptr) return DQMC_EINVAL;
-    if (!aligned(d_tt, 4) || !aligned(d_state, 4) || !aligned(d_count, 8) || !aligned(d_list, 8)) return DQMC_EINVAL;
+    if (!aligned(d_tt, 4) || !aligned(d_state, kStateAlign) || !aligned(d_count, 8) || !aligned(d_list, 8))
+        return DQMC_EINVAL;
     int dev = -1;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kNoAllocMaxDevices) return DQMC_EDEVICE;
     uint64_t *p = noalloc_scratch(dev);
@@ -631,12 +639,12 @@ int dqmc_primes_sliced_multi(dqmc_ctx *ctx, int n, int t, const uint32_t *d_tt, 
         return fail(ctx, DQMC_EINVAL, "%s", "need 1 to DQMC_SLICED_MAX_STATES implicant states");
     if (d_tt == nullptr || d_o == nullptr || d_count == nullptr)
         return fail(ctx, DQMC_EINVAL, "%s", "NULL truth table, slice state or count");
-    if (!aligned(d_tt, 4) || !aligned(d_o, 4) || !aligned(d_count, 8) || !aligned(d_list, 8))
+    if (!aligned(d_tt, 4) || !aligned(d_o, kStateAlign) || !aligned(d_count, 8) || !aligned(d_list, 8))
         return fail(ctx, DQMC_EINVAL, "%s", "misaligned buffer");
     const uint64_t sw = dqmc_state_words(m);
     std::vector<uint32_t *> states(1, d_o);
     for (int i = 0; i < nm; ++i) {
-        if (d_ms[i] == nullptr || !aligned(d_ms[i], 4))
+        if (d_ms[i] == nullptr || !aligned(d_ms[i], kStateAlign))
             return fail(ctx, DQMC_EINVAL, "%s", "NULL or misaligned implicant state");
         for (uint32_t *q : states)
             if (d_ms[i] < q + sw && q < d_ms[i] + sw) return fail(ctx, DQMC_EINVAL, "%s", "the slice states overlap");
@@ -723,7 +731,7 @@ int dqmc_extract(dqmc_ctx *ctx, int n, const uint32_t *d_state, uint64_t *d_list
     int rc = check_common(ctx, n);
     if (rc != DQMC_OK) return rc;
     if (d_state == nullptr || d_count == nullptr) return fail(ctx, DQMC_EINVAL, "%s", "NULL state or count");
-    if (!aligned(d_state, 4) || !aligned(d_count, 8) || !aligned(d_list, 8))
+    if (!aligned(d_state, kStateAlign) || !aligned(d_count, 8) || !aligned(d_list, 8))
         return fail(ctx, DQMC_EINVAL, "%s", "misaligned buffer");
     return enqueue_extract_tiles(ctx, n, kLowCount, const_cast<uint32_t *>(d_state), d_list, list_cap, d_count,
                                  (hipStream_t)stream);
@@ -734,7 +742,8 @@ int dqmc_bitmap_to_dense(dqmc_ctx *ctx, int n, const uint32_t *d_state, uint64_t
     int rc = check_common(ctx, n);
     if (rc != DQMC_OK) return rc;
     if (d_state == nullptr || d_dense == nullptr) return fail(ctx, DQMC_EINVAL, "%s", "NULL state or output");
-    if (!aligned(d_state, 4) || !aligned(d_dense, 8)) return fail(ctx, DQMC_EINVAL, "%s", "misaligned buffer");
+    if (!aligned(d_state, kStateAlign) || !aligned(d_dense, 8))
+        return fail(ctx, DQMC_EINVAL, "%s", "misaligned buffer");
     hipStream_t s = (hipStream_t)stream;
     return run_pass(ctx, s, "to_dense", n, state_bytes(n) + 8.0 * (double)dqmc_dense_words(n), 0,
                     [&] { return launch_to_dense(n, d_state, d_dense, s); });
@@ -801,7 +810,7 @@ int dqmc_batch_create(dqmc_ctx *ctx, dqmc_job *jobs, int32_t njobs, dqmc_batch *
     for (int32_t i = 0; i < njobs; ++i) {
         dqmc_job &j = jobs[i];
         const bool ok = j.n >= 0 && j.n <= DQMC_MAX_N && j.tt != nullptr && j.state != nullptr &&
-                        j.count != nullptr && aligned(j.tt, 4) && aligned(j.state, 4) && aligned(j.count, 8) &&
+                        j.count != nullptr && aligned(j.tt, 4) && aligned(j.state, kStateAlign) && aligned(j.count, 8) &&
                         aligned(j.list, 8);
         j.status = ok ? DQMC_OK : DQMC_EINVAL;
         if (!ok) continue;
@@ -934,6 +943,8 @@ int dqmc_set_plan(dqmc_ctx *ctx, int n, const int32_t *sizes, int ngroups)
         sum += sizes[i];
     }
     if (ngroups > 0 && sum != n - kLowDigits) return fail(ctx, DQMC_EINVAL, "%s", "group sizes must sum to n - 12");
+    if (ngroups > 0 && n - sizes[ngroups - 1] + 1 > kMaxGroupStart)
+        return fail(ctx, DQMC_EINVAL, "%s", "a group may not start above digit 24 (32-bit row offsets)");
     for (int i = 0; i < ngroups; ++i) ctx->plan[n][i] = sizes[i];
     ctx->plan_len[n] = ngroups;
     return DQMC_OK;

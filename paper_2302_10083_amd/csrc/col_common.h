@@ -2,7 +2,7 @@
 // k_col_chunk.hip).
 #pragma once
 
-#include "t27.h"
+#include "h5.h"
 
 namespace dqmc {
 
@@ -27,7 +27,7 @@ __host__ __device__ constexpr int col_threads()
 }
 
 // Occupancy caps.  A column pass writes 256-byte row segments that start at
-// multiples of 3^(g0-4) words, off the 128-byte lines, so the lines at their
+// multiples of 8 * 3^(g0-6) words, off the 128-byte lines, so the lines at their
 // edges are shared with the neighbouring blocks.  Stores of that shape run
 // faster with few workgroups per CU (a store-only probe on MI355X: 4.9 TB/s
 // at one workgroup per CU, 2.6 TB/s at full occupancy), and so do several of

@@ -1,12 +1,17 @@
-// T27 state layout and the per-dimension Merge/Reduce transforms on it.
+// Block state layout ("H5") and the per-dimension Merge/Reduce transforms on
+// it.
 //
 // A state is the indicator of a set of ternary cubes (Sec. 4.1, "State
 // representation").  Cube rho (Sec. 4.2, notation rho: digit i of rho is the
-// symbol s_i, with * = 2) lives in 32-bit word rho / 27, bit rho % 27.  So the
-// three lowest ternary digits are inside a word ("bottom layer" of Sec. 4.2
-// with h = 3 and 27 of 32 bits used) and digit i >= 4 moves the word index by
-// 3^(i-4) ("top layer").  Word bits 27..31 are always 0.  For n < 3 the state
-// is one word holding bits 0..3^n-1.
+// symbol s_i, with * = 2) lives in 256-bit block rho / 243, at bit
+// p = rho % 243 of the block; a block is 8 consecutive uint32 words and bit p
+// is bit p % 32 of its word p / 32.  So the five lowest ternary digits are
+// inside a block (the bottom layer of Sec. 4.2 with h = 5: 243 of 256 bits
+// used, the paper's own AVX2 choice), and digit i >= 6 moves the block index
+// by 3^(i-6), i.e. the word index by 8 * 3^(i-6) (the top layer).  Bits
+// 243..255 of a block (bits 19..31 of its last word) are always 0.  For
+// n < 5 the state is one block holding bits 0..3^n-1.  Memory order is rho
+// order.
 //
 // Merge (Sec. 4.1, Def. of Merge) for dimension i maps the triple of cubes
 // (s, t, u) with s_i = 0, t_i = 1, u_i = * and equal elsewhere to
@@ -39,12 +44,6 @@ __device__ __forceinline__ void static_for(F &&f)
 {
     static_for_impl(f, std::make_integer_sequence<int, N>{});
 }
-
-// Bits of a word whose in-word digit 1 / 2 / 3 is 0 (the masks mu_i of
-// Sec. 4.2 for h = 3).
-constexpr uint32_t kMu1 = 0x1249249u;
-constexpr uint32_t kMu2 = 0x1C0E07u;
-constexpr uint32_t kMu3 = 0x1FFu;
 
 __host__ __device__ constexpr uint64_t pow3(int k)
 {
@@ -82,38 +81,116 @@ __host__ __device__ constexpr int bin_index(int c, int k)
     return b;
 }
 
-// Merge of the three in-word dimensions on a word whose set bits are all at
-// cubes without * in those digits.
-__device__ __forceinline__ uint32_t inword_merge(uint32_t v)
+constexpr int kBlockWords = 8;     // uint32 words per block
+constexpr int kBlockCubes = 243;   // cubes per block (3^5)
+constexpr int kBlockDigits = 5;    // digits inside a block
+
+// Word w of the mask mu_i (Sec. 4.2) for the in-block digit i (0-based):
+// bits p = 32 w + b < 243 whose digit i is 0.
+__host__ __device__ constexpr uint32_t block_mu(int i, int w)
 {
-    v |= ((v & (v >> 1)) & kMu1) << 2;
-    v |= ((v & (v >> 3)) & kMu2) << 6;
-    v |= ((v & (v >> 9)) & kMu3) << 18;
-    return v;
+    uint32_t m = 0;
+    for (int b = 0; b < 32; ++b) {
+        const uint64_t p = 32u * (uint32_t)w + (uint32_t)b;
+        if (p < (uint64_t)kBlockCubes && (p / pow3(i)) % 3 == 0) m |= 1u << b;
+    }
+    return m;
 }
 
-// Reduce of the three in-word dimensions (in place, one after the other).
-__device__ __forceinline__ uint32_t inword_reduce(uint32_t v)
+// 256-bit shifts of a block held in 8 registers (word 0 = bits 0..31).
+template <int K>
+__device__ __forceinline__ void block_shr(const uint32_t (&v)[kBlockWords], uint32_t (&o)[kBlockWords])
 {
-    uint32_t k;
-    k = (v >> 2) & kMu1;
-    v &= ~(k | (k << 1));
-    k = (v >> 6) & kMu2;
-    v &= ~(k | (k << 3));
-    k = (v >> 18) & kMu3;
-    v &= ~(k | (k << 9));
-    return v;
+    constexpr int q = K / 32, r = K % 32;
+    static_for<kBlockWords>([&](auto wi) {
+        constexpr int w = decltype(wi)::value;
+        if constexpr (w + q >= kBlockWords) o[w] = 0u;
+        else if constexpr (r == 0) o[w] = v[w + q];
+        else if constexpr (w + q + 1 >= kBlockWords) o[w] = v[w + q] >> r;
+        else o[w] = __builtin_amdgcn_alignbit(v[w + q + 1], v[w + q], (uint32_t)r);
+    });
 }
 
-// Truth-table byte (f at x = 8m + j, j = x_1 + 2 x_2 + 4 x_3) placed at the
-// T27 positions x_1 + 3 x_2 + 9 x_3 of the cubes without * in digits 1..3.
-__device__ __forceinline__ uint32_t expand_byte(uint32_t byte)
+template <int K>
+__device__ __forceinline__ void block_shl(const uint32_t (&v)[kBlockWords], uint32_t (&o)[kBlockWords])
 {
-    uint32_t v = 0;
-#pragma unroll
-    for (int j = 0; j < 8; ++j)
-        v |= ((byte >> j) & 1u) << ((j & 1) + 3 * ((j >> 1) & 1) + 9 * ((j >> 2) & 1));
-    return v;
+    constexpr int q = K / 32, r = K % 32;
+    static_for<kBlockWords>([&](auto wi) {
+        constexpr int w = decltype(wi)::value;
+        if constexpr (w - q < 0) o[w] = 0u;
+        else if constexpr (r == 0) o[w] = v[w - q];
+        else if constexpr (w - q - 1 < 0) o[w] = v[w - q] << r;
+        else o[w] = __builtin_amdgcn_alignbit(v[w - q], v[w - q - 1], (uint32_t)(32 - r));
+    });
+}
+
+// Merge of the five in-block dimensions on a block whose set bits are all at
+// cubes without * in those digits: u = s AND t, with s at bit p (digit i of p
+// is 0), t at p + 3^i and u at p + 2 * 3^i.
+__device__ __forceinline__ void block_merge(uint32_t (&v)[kBlockWords])
+{
+    static_for<kBlockDigits>([&](auto ii) {
+        constexpr int i = decltype(ii)::value;
+        constexpr int S = (int)pow3(i);
+        uint32_t a[kBlockWords], b[kBlockWords];
+        block_shr<S>(v, a);
+        static_for<kBlockWords>([&](auto wi) {
+            constexpr int w = decltype(wi)::value;
+            a[w] &= v[w] & block_mu(i, w);
+        });
+        block_shl<2 * S>(a, b);
+        static_for<kBlockWords>([&](auto wi) {
+            constexpr int w = decltype(wi)::value;
+            v[w] |= b[w];
+        });
+    });
+}
+
+// Reduce of the five in-block dimensions (in place, one after the other).
+__device__ __forceinline__ void block_reduce(uint32_t (&v)[kBlockWords])
+{
+    static_for<kBlockDigits>([&](auto ii) {
+        constexpr int i = decltype(ii)::value;
+        constexpr int S = (int)pow3(i);
+        uint32_t a[kBlockWords], b[kBlockWords];
+        block_shr<2 * S>(v, a);  // the * cube's bit, at its digit-0 sibling
+        static_for<kBlockWords>([&](auto wi) {
+            constexpr int w = decltype(wi)::value;
+            a[w] &= block_mu(i, w);
+        });
+        block_shl<S>(a, b);  // and at its digit-1 sibling
+        static_for<kBlockWords>([&](auto wi) {
+            constexpr int w = decltype(wi)::value;
+            v[w] &= ~(a[w] | b[w]);
+        });
+    });
+}
+
+// Cube position x_1 + 3 x_2 + 9 x_3 + 27 x_4 + 81 x_5 of the minterm
+// j = x_1 + 2 x_2 + 4 x_3 + 8 x_4 + 16 x_5 inside a block.
+__host__ __device__ constexpr int block_pos(int j)
+{
+    int p = 0;
+    for (int r = 0; r < kBlockDigits; ++r) p += ((j >> r) & 1) * (int)pow3(r);
+    return p;
+}
+
+// Truth-table word (f at x = 32 m + j) placed at the positions of its 32
+// minterms in a block (the cubes without * in digits 1..5).
+__device__ __forceinline__ void block_from_tt(uint32_t x, uint32_t (&v)[kBlockWords])
+{
+    static_for<kBlockWords>([&](auto wi) { v[decltype(wi)::value] = 0u; });
+    static_for<32>([&](auto ji) {
+        constexpr int j = decltype(ji)::value;
+        constexpr int p = block_pos(j);
+        v[p / 32] |= ((x >> j) & 1u) << (p % 32);
+    });
+}
+
+// Cube index of bit 0 of state word `w` (word w % 8 of block w / 8).
+__host__ __device__ __forceinline__ uint64_t rho_of_word(uint64_t w)
+{
+    return (uint64_t)kBlockCubes * (w >> 3) + 32u * (uint32_t)(w & 7u);
 }
 
 // Merge of K dimensions on a register column x[c], c = sum_r digit_r 3^r,

@@ -19,10 +19,10 @@
 namespace dqmc {
 
 constexpr int kBatchThreads = 768;
-constexpr uint32_t kTileL = 19683;  // words spanned by digits 4..12
+constexpr uint32_t kTileL = kTileWords;  // words spanned by digits 1..12
 
 // Column pass of a function with 13 <= n <= 16: the digits 13..n (GR of them)
-// are merged, then reduced, in registers for state words l + 3^9 * c.  The
+// are merged, then reduced, in registers for state words l + kTileL * c.  The
 // column is processed in three chunks over its top digit: chunk 2 (top digit
 // *) is the AND of chunks 0 and 1 on the binary inputs; every chunk is merged
 // and reduced over the lower digits; then chunks 0 and 1 are reduced against
@@ -79,15 +79,14 @@ __device__ __forceinline__ void batch_column(uint32_t *state, uint32_t l)
 __device__ void batch_job(const BatchJob &j, uint32_t *t, uint64_t *sh)
 {
     const int n = j.n;
-    const int lw = n <= 3 ? 0 : n - 3;
-    const uint32_t tw = (uint32_t)pow3(lw);
+    const int lw = n <= 5 ? 0 : n - 5;
+    const uint32_t tw = kBlockWords * (uint32_t)pow3(lw);
     tile_from_tt(t, j.tt, n, lw, tw, 0);
     lds_all_digits<true>(t, tw, lw);
-    for (uint32_t w = threadIdx.x; w < tw; w += blockDim.x) t[w] = inword_reduce(t[w]);
-    __syncthreads();
+    lds_inblock_reduce(t, tw);
     lds_all_digits<false>(t, tw, lw);
     for (uint32_t w = threadIdx.x; w < tw; w += blockDim.x) j.state[w] = t[w];
-    const uint64_t total = tile_list(t, tw, n, 0, j.list, j.cap, 0, sh);
+    const uint64_t total = tile_list(t, tw, 0, j.list, j.cap, 0, sh);
     if (threadIdx.x == 0) *j.count = total;
 }
 
@@ -95,7 +94,7 @@ __device__ void batch_job(const BatchJob &j, uint32_t *t, uint64_t *sh)
 __global__ __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per_eu(6)))
 void batch_kernel(const BatchJob *jobs, const uint32_t *order, uint32_t njobs, uint32_t *ticket)
 {
-    extern __shared__ uint32_t t[];
+    extern __shared__ __align__(16) uint32_t t[];
     __shared__ uint64_t sh[kBatchThreads / 64];
     __shared__ uint32_t item;
     for (;;) {
@@ -118,12 +117,12 @@ constexpr uint32_t kColBlocks = (kTileL + kColThreads - 1) / kColThreads;  // pe
 //    digits 1..12, to the state.
 __global__ __launch_bounds__(kBatchThreads) void tb_merge_tt_kernel(TileBatch b)
 {
-    extern __shared__ uint32_t t[];
+    extern __shared__ __align__(16) uint32_t t[];
     const uint32_t item = blockIdx.x;
     const TileJob &j = b.jobs[b.bin_job[item]];
     const uint64_t bh = item - j.first_bin;
-    tile_from_tt(t, j.tt, j.n, 9, kTileL, bh);
-    lds_all_digits<true>(t, kTileL, 9);
+    tile_from_tt(t, j.tt, j.n, 7, kTileL, bh);
+    lds_all_digits<true>(t, kTileL, 7);
     uint64_t tile = 0;
     for (int q = 0; q < j.n - 12; ++q)
         if ((bh >> q) & 1) tile += pow3(q);
@@ -152,7 +151,7 @@ __global__ __launch_bounds__(kColThreads) __attribute__((amdgpu_waves_per_eu(5))
 // 3. Every tile: reduce digits 1..12 (the prime bitmap) and its summary.
 __global__ __launch_bounds__(768) void tb_reduce_kernel(TileBatch b)
 {
-    extern __shared__ uint32_t t[];
+    extern __shared__ __align__(16) uint32_t t[];
     __shared__ uint32_t red[2 * kMapWords + 1];  // the upper half is unused here
     const uint32_t tile = blockIdx.x;
     const TileJob &j = b.jobs[b.tile_job[tile]];
@@ -190,8 +189,8 @@ __global__ __launch_bounds__(256) void tb_list_kernel(TileBatch b)
     const uint64_t off = b.offs[tile];
     if (j.list == nullptr || c == 0 || off >= j.cap) return;
     const uint64_t local = tile - j.first_tile;
-    list_tile(j.state + local * kTileL, kTileL, true, local * kTileL, off, b.chunkmap + (uint64_t)tile * kMapWords,
-              j.list, j.cap, nzs[threadIdx.x / 64]);
+    list_tile(j.state + local * kTileL, kTileL, local * kTileL, off, b.chunkmap + (uint64_t)tile * kMapWords, j.list,
+              j.cap, nzs[threadIdx.x / 64]);
 }
 
 hipError_t launch_tile_batch(const TileBatch &b, hipStream_t s)

@@ -1,21 +1,22 @@
 // Column passes: Merge / Reduce over a group of high digits (digit >= 13).
 //
 // These are the top-layer dimensions of Sec. 4.2: for digit i the triples
-// are words at distance 3^(i-4) (eq. indexes), processed as a batch bit-slice
-// over all 27 cubes of a word at once.  Instead of one memory sweep per digit
-// (Alg. 4), a pass takes a group of G = GR + GW consecutive digits g0.. and
-// applies all of them while the data is on chip:
+// are blocks at distance 3^(i-6) (eq. indexes), i.e. words at distance
+// 8 * 3^(i-6), processed as a batch bit-slice over the 32 bit positions of a
+// word at once.  Instead of one memory sweep per digit (Alg. 4), a pass takes
+// a group of G = GR + GW consecutive digits g0.. and applies all of them
+// while the data is on chip:
 //
-//   word index  w = l + L * (cr + 3^GR * (cw + 3^GW * o)),   L = 3^(g0-4)
+//   word index  w = l + L * (cr + 3^GR * (cw + 3^GW * o)),   L = 8 * 3^(g0-6)
 //
-// l (digits 4..g0-1) runs over consecutive words, one per lane, so every
-// access of a wavefront is 64 consecutive words; cr (GR digits) indexes a
-// lane's registers; cw (GW digits) is the wavefront within the workgroup;
-// o is the combination of the digits above the group.  Digits of cr are
-// transformed in registers, digits of cw through LDS.
+// l (the word in a block and digits 6..g0-1) runs over consecutive words, one
+// per lane, so every access of a wavefront is 64 consecutive words; cr (GR
+// digits) indexes a lane's registers; cw (GW digits) is the wavefront within
+// the workgroup; o is the combination of the digits above the group.  Digits
+// of cr are transformed in registers, digits of cw through LDS.
 #include "col_common.h"
 #include "launch.h"
-#include "t27.h"
+#include "h5.h"
 
 namespace dqmc {
 
@@ -106,7 +107,7 @@ __global__ __launch_bounds__(col_threads<GW>()) void col_kernel(ColArgs a)
     const uint64_t L = a.L;
     const uint64_t l64 = lb * LANES + lane;
     const bool active = l64 < L;
-    const uint32_t l = (uint32_t)l64;  // L <= 3^18 for n <= 25
+    const uint32_t l = (uint32_t)l64;  // L < 2^32: plans keep g0 <= 24
     uint32_t *rows = a.state + L * (uint64_t)CR * ((uint64_t)cw + (uint64_t)CW * o);
 #define ROW(c) (rows + (uint64_t)(c) * L)
 

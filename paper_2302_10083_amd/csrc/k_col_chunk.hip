@@ -4,7 +4,7 @@
 // digit, so that 27 rows are in flight instead of 81.
 #include "col_common.h"
 #include "launch.h"
-#include "t27.h"
+#include "h5.h"
 
 namespace dqmc {
 
@@ -51,7 +51,7 @@ __global__ __launch_bounds__(col_threads<GW>()) void col_chunk_kernel(ColArgs a)
     const uint64_t L = a.L;
     const uint64_t l64 = lb * LANES + lane;
     const bool active = l64 < L;
-    const uint32_t l = (uint32_t)l64;  // L <= 3^18 for n <= 25
+    const uint32_t l = (uint32_t)l64;  // L < 2^32: plans keep g0 <= 24
     uint32_t *rows = a.state + L * (uint64_t)CR * ((uint64_t)cw + (uint64_t)CW * o);
 #define ROW(c) (rows + (uint64_t)(c) * L)
 

@@ -3,7 +3,7 @@
 // set bits and which 64-word chunks are non-zero); a scan turns the counts
 // into list offsets, and the list pass reads only the non-zero chunks.
 #include "launch.h"
-#include "t27.h"
+#include "h5.h"
 #include "tile_ops.h"
 
 namespace dqmc {
@@ -124,14 +124,13 @@ __global__ __launch_bounds__(kListThreads) void list_kernel(ListArgs a)
     constexpr int NW = kListThreads / 64;
     __shared__ uint16_t nzs[NW][kTileChunks];
     const uint32_t wv = threadIdx.x / 64;
-    const bool words = a.n >= 3;
     const uint64_t nwaves = (uint64_t)gridDim.x * NW;
     for (uint64_t tile = (uint64_t)blockIdx.x * NW + wv; tile < a.ntiles; tile += nwaves) {
         const uint32_t c = a.counts[tile];
         const uint64_t off = a.offs[tile];
         if (c == 0 || off >= a.cap) continue;
-        list_tile(a.state + tile * a.tw, a.tw, words, tile * a.tw, off, a.chunkmap + tile * kMapWords, a.list, a.cap,
-                  nzs[wv], a.rho0);
+        list_tile(a.state + tile * a.tw, a.tw, tile * a.tw, off, a.chunkmap + tile * kMapWords, a.list, a.cap, nzs[wv],
+                  a.rho0);
     }
 }
 

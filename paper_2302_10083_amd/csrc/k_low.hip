@@ -1,13 +1,14 @@
-// Low tile kernels: the in-word digits 1..3 and the word digits 4..12 of one
-// tile of 3^min(n,12) cubes, processed in LDS.
+// Low tile kernels: the in-block digits 1..5 and the block digits 6..12 of
+// one tile of 3^min(n,12) cubes, processed in LDS.
 //
 // Alg. 4 loads the support into the state, then applies the Merge transform
 // per dimension (top layer over whole blocks, bottom layer inside a block),
 // then Reduce, then scans the state for the output list.  Here a tile is the
-// unit of on-chip work: digits 1..3 use the in-word shift-and-mask form of the
-// bottom layer (Sec. 4.2, masks mu_i), digits 4..12 use the top-layer triple
-// indexing of Sec. 4.2 (eq. indexes) on LDS words, three digits at a time in
-// registers.  Digits above 12 are handled by the column passes (k_col.hip).
+// unit of on-chip work: digits 1..5 use the shift-and-mask form of the bottom
+// layer on a 256-bit block held in eight registers (Sec. 4.2, masks mu_i),
+// digits 6..12 use the top-layer triple indexing of Sec. 4.2 (eq. indexes) on
+// LDS words, three digits at a time in registers.  Digits above 12 are
+// handled by the column passes (k_col.hip).
 #include "launch.h"
 #include "tile_ops.h"
 
@@ -37,16 +38,18 @@ __device__ __forceinline__ void tile_summary(const uint32_t *t, const LowArgs &a
 template <int MODE>
 __host__ __device__ constexpr int low_threads()
 {
-    // the tile passes over HBM-resident states use one 27-word column per
-    // thread per LDS round (729 columns in a full tile)
+    // the tile passes over HBM-resident states use one run of three blocks
+    // per thread on the way in (729 runs in a full tile) and one 27-word
+    // column per thread in the LDS rounds (648 columns)
     return (MODE == kLowReduceCount || MODE == kLowCount) ? 768 : kLowThreads;
 }
 
+// Two workgroups per CU (the LDS tile allows two): registers held to 80.
 template <int MODE>
-__global__ __launch_bounds__(low_threads<MODE>()) void low_kernel(LowArgs a)
+__global__ __launch_bounds__(low_threads<MODE>()) __attribute__((amdgpu_waves_per_eu(6))) void low_kernel(LowArgs a)
 {
     constexpr int THREADS = low_threads<MODE>();
-    extern __shared__ uint32_t dyn[];
+    extern __shared__ __align__(16) uint32_t dyn[];
     __shared__ uint64_t sh[THREADS / 64];
     uint32_t *t = dyn;
 
@@ -62,11 +65,10 @@ __global__ __launch_bounds__(low_threads<MODE>()) void low_kernel(LowArgs a)
             uint32_t *dst = a.state + tile * a.tw;
             for (uint32_t w = threadIdx.x; w < a.tw; w += blockDim.x) dst[w] = t[w];
         } else {
-            for (uint32_t w = threadIdx.x; w < a.tw; w += blockDim.x) t[w] = inword_reduce(t[w]);
-            __syncthreads();
+            lds_inblock_reduce(t, a.tw);
             lds_all_digits<false>(t, a.tw, a.lw);
             for (uint32_t w = threadIdx.x; w < a.tw; w += blockDim.x) a.state[w] = t[w];
-            const uint64_t total = tile_list(t, a.tw, a.n, 0, a.list, a.cap, 0, sh);
+            const uint64_t total = tile_list(t, a.tw, 0, a.list, a.cap, 0, sh);
             if (threadIdx.x == 0 && a.count != nullptr) *a.count = total;
         }
     } else {
@@ -82,7 +84,7 @@ __global__ __launch_bounds__(low_threads<MODE>()) void low_kernel(LowArgs a)
             reduce_full_tile<true>(t, a.state + tile * a.tw, a.counts + tile, a.chunkmap + tile * kMapWords, red);
             return;
         } else {
-            load_tile<false, THREADS>(t, src, a.tw);
+            load_tile<THREADS>(t, src, a.tw);
             __syncthreads();
         }
         tile_summary(t, a, tile, red);
@@ -97,7 +99,7 @@ static size_t low_lds_bytes(int mode, uint32_t tw)
 
 hipError_t low_setup()
 {
-    const int bytes = (int)low_lds_bytes(kLowMergeTT, (uint32_t)pow3(9));
+    const int bytes = (int)low_lds_bytes(kLowMergeTT, kTileWords);
     hipError_t e;
     if ((e = hipFuncSetAttribute((const void *)low_kernel<kLowMergeTT>,
                                  hipFuncAttributeMaxDynamicSharedMemorySize, bytes)) != hipSuccess)

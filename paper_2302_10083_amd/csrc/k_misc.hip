@@ -1,7 +1,8 @@
 // Small helper kernels: fills (used instead of memset so that every enqueued
-// operation is a kernel node) and the T27 -> exact 3^n-bit repack.
+// operation is a kernel node), the block state -> exact 3^n-bit repack, and a
+// hash of words for comparing results.
 #include "launch.h"
-#include "t27.h"
+#include "h5.h"
 
 namespace dqmc {
 
@@ -38,31 +39,28 @@ hipError_t launch_fill_u32(uint32_t *p, uint64_t count, uint32_t value, hipStrea
     return hipGetLastError();
 }
 
-// Output word j holds cubes 64j .. 64j+63, which come from T27 words
-// floor(64j/27) .. floor((64j+63)/27) (at most 4 words).
-__global__ void to_dense_kernel(int n, const uint32_t *state, uint64_t *dense, uint64_t nwords, uint64_t ncubes)
+// Output word j holds cubes 64j .. 64j+63.  Cube rho is bit rho % 243 of
+// block rho / 243, i.e. bit (rho % 243) % 32 of state word
+// 8 * (rho / 243) + (rho % 243) / 32; a run of cubes inside one word is
+// copied at once.
+__global__ void to_dense_kernel(const uint32_t *state, uint64_t *dense, uint64_t nwords, uint64_t ncubes)
 {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < nwords; j += stride) {
-        uint64_t out = 0;
-        if (n < 3) {
-            out = state[0];
-        } else {
-            const uint64_t r0 = 64 * j;
-            uint64_t w = r0 / 27;
-            uint32_t b = (uint32_t)(r0 % 27);
-            const uint64_t nsw = ncubes / 27;
-            uint32_t filled = 0;
-            while (filled < 64 && w < nsw) {
-                const uint64_t bits = (uint64_t)(state[w] >> b);
-                out |= bits << filled;
-                filled += 27 - b;
-                b = 0;
-                ++w;
-            }
+        uint64_t out = 0, r = 64 * j;
+        const uint64_t rend = r + 64 < ncubes ? r + 64 : ncubes;
+        uint32_t filled = 0;
+        while (r < rend) {
+            const uint64_t blk = r / kBlockCubes;
+            const uint32_t p = (uint32_t)(r - blk * kBlockCubes), b = p & 31u;
+            uint32_t take = 32u - b;
+            if ((uint32_t)kBlockCubes - p < take) take = (uint32_t)kBlockCubes - p;
+            if (rend - r < take) take = (uint32_t)(rend - r);
+            const uint64_t bits = ((uint64_t)state[kBlockWords * blk + (p >> 5)] >> b) & ((1ull << take) - 1ull);
+            out |= bits << filled;
+            filled += take;
+            r += take;
         }
-        const uint64_t rem = ncubes - 64 * j;
-        if (rem < 64) out &= (1ull << rem) - 1;
         dense[j] = out;
     }
 }
@@ -70,11 +68,13 @@ __global__ void to_dense_kernel(int n, const uint32_t *state, uint64_t *dense, u
 hipError_t launch_to_dense(int n, const uint32_t *state, uint64_t *dense, hipStream_t s)
 {
     const uint64_t ncubes = pow3(n), nwords = (ncubes + 63) / 64;
-    hipLaunchKernelGGL(to_dense_kernel, dim3(fill_grid(nwords)), dim3(256), 0, s, n, state, dense, nwords, ncubes);
+    hipLaunchKernelGGL(to_dense_kernel, dim3(fill_grid(nwords)), dim3(256), 0, s, state, dense, nwords, ncubes);
     return hipGetLastError();
 }
 
 // Order-dependent hash: sum over i of a 64-bit mix of (i, word i), mod 2^64.
+// The mix is the output finaliser of SplitMix64 (Steele, Lea and Flood,
+// "Fast splittable pseudorandom number generators", OOPSLA 2014).
 __device__ __forceinline__ uint64_t mix64(uint64_t z)
 {
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;

@@ -13,7 +13,7 @@
 #include <algorithm>
 
 #include "launch.h"
-#include "t27.h"
+#include "h5.h"
 
 namespace dqmc {
 

@@ -6,8 +6,9 @@
 
 namespace dqmc {
 
-// Low tile: the cubes whose digits 13..n are fixed, i.e. 3^min(n-3, 9)
-// consecutive state words (3^min(n,12) cubes), held in LDS.
+// Low tile: the cubes whose digits 13..n are fixed, i.e. 3^min(n-5, 7)
+// consecutive blocks (8 * 3^min(n-5, 7) state words, 3^min(n,12) cubes),
+// held in LDS.
 enum LowMode : int {
     kLowMergeTT = 0,        // truth table -> merged tile (digits 1..12) -> state
     kLowPrimesTT = 1,       // n <= 12: truth table -> M -> O -> state + list
@@ -15,11 +16,14 @@ enum LowMode : int {
     kLowCount = 3,          // state -> tile info only (no transform, no write)
 };
 
+constexpr uint32_t kTileBlocks = 2187;            // 3^7 blocks: digits 6..12
+constexpr uint32_t kTileWords = 8 * kTileBlocks;  // 17496 words (69,984 bytes)
+
 // Per-tile summary written by kLowReduceCount / kLowCount: the number of set
 // bits, and a bitmap of the 64-word chunks that hold any set bit.
 constexpr int kChunkWords = 64;
-constexpr int kTileChunks = (19683 + kChunkWords - 1) / kChunkWords;  // 308
-constexpr int kMapWords = (kTileChunks + 31) / 32;                   // 10
+constexpr int kTileChunks = (kTileWords + kChunkWords - 1) / kChunkWords;  // 274
+constexpr int kMapWords = (kTileChunks + 31) / 32;                         // 9
 
 struct LowArgs {
     const uint32_t *tt;
@@ -32,7 +36,7 @@ struct LowArgs {
     uint64_t ntiles;
     uint32_t tw;        // words per tile
     int n;
-    int lw;             // word digits inside a tile (tw = 3^lw)
+    int lw;             // block digits inside a tile (tw = 8 * 3^lw)
     uint32_t flip;      // XOR applied to the truth-table words (~0u: complement)
 };
 
@@ -64,9 +68,14 @@ enum ColMode : int {
     kColReduce = 2,       // reduce the group
 };
 
+// Highest first digit of a group: a group starting at digit g0 has rows
+// L = 8 * 3^(g0-6) words apart, and lanes address a row with 32-bit offsets
+// (L < 2^32 up to g0 = 24).
+constexpr int kMaxGroupStart = 24;
+
 struct ColArgs {
     uint32_t *state;
-    uint64_t L;          // 3^(g0-4): words spanned by digits 4..g0-1
+    uint64_t L;          // 8 * 3^(g0-6): words spanned by digits 1..g0-1
     uint64_t nlb;        // l-blocks
     uint64_t nouter;     // outer (above the group) combinations launched
     uint64_t nblocks;    // nlb * nouter

@@ -29,7 +29,7 @@
 
 #include "dqmc.h"
 #include "launch.h"
-#include "t27.h"
+#include "h5.h"
 
 using namespace dqmc;
 
@@ -52,13 +52,14 @@ uint64_t list_reserve(int n)
 }
 
 uint64_t tt_words_of(int n) { return n <= 5 ? 1 : (1ull << (n - 5)); }
+uint64_t state_words_of(int n) { return kBlockWords * pow3(n > 5 ? n - 5 : 0); }
 
 uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
 
 // Bytes of a job's arena block: state, list reserve, truth table, count.
 uint64_t footprint(int n)
 {
-    return align256(4 * pow3(n > 3 ? n - 3 : 0)) + align256(8 * list_reserve(n)) + align256(4 * tt_words_of(n)) + 256;
+    return align256(4 * state_words_of(n)) + align256(8 * list_reserve(n)) + align256(4 * tt_words_of(n)) + 256;
 }
 
 enum Phase { kPending, kRunning, kDone, kReleased };
@@ -191,7 +192,7 @@ void free_job_device(dqmc_server *s, SJob &j)
 // truth table on `st`.
 bool stage_job(dqmc_server *s, SJob &j, hipStream_t st)
 {
-    const uint64_t nw = tt_words_of(j.n), sw = pow3(j.n > 3 ? j.n - 3 : 0);
+    const uint64_t nw = tt_words_of(j.n), sw = state_words_of(j.n);
     j.cap = list_reserve(j.n);
     uint8_t *p = s->arena_base + j.off;
     j.d_state = (uint32_t *)p;

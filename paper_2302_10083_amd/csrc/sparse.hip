@@ -28,7 +28,7 @@
 
 #include "api_types.h"
 #include "dqmc.h"
-#include "t27.h"
+#include "h5.h"
 
 namespace dqmc {
 
@@ -36,6 +36,9 @@ constexpr uint64_t kEmpty = ~0ull;          // never a key: 11 is not a symbol
 constexpr uint64_t kRedundant = 1ull << 63;  // control bit of a stored key
 constexpr int kSpThreads = 256;
 
+// Slot hash of a key: the "Mix01" variant of the MurmurHash3 64-bit finaliser
+// (shifts 31, 27, 33 and the two multipliers of D. Stafford, "Better Bit
+// Mixing - Improving on MurmurHash3's 64-bit Finalizer", 2011).
 __device__ __forceinline__ uint64_t sp_hash(uint64_t k)
 {
     k = (k ^ (k >> 31)) * 0x7FB5D329728EA185ULL;

@@ -10,6 +10,9 @@
 
 #include "api_types.h"
 #include "dqmc.h"
+#include "launch.h"
+
+using dqmc::kMaxGroupStart;
 
 namespace {
 
@@ -130,6 +133,11 @@ int dqmc_plan_autotune(dqmc_ctx *ctx, int n, const uint32_t *d_tt, uint32_t *d_s
     std::vector<std::vector<int>> cands;
     std::vector<int> cur;
     for (int k = kmin; k <= std::min(h, kmin + extra_groups); ++k) splits(h, k, cur, cands, DQMC_MAX_PLAN_TRIALS);
+    // plans whose top group starts above digit kMaxGroupStart are not valid
+    // (dqmc_set_plan rejects them)
+    cands.erase(std::remove_if(cands.begin(), cands.end(),
+                               [&](const std::vector<int> &c) { return n - c.back() + 1 > kMaxGroupStart; }),
+                cands.end());
     // the plan and split mode in force are restored if a run fails
     int32_t keep[DQMC_MAX_N];
     const int nkeep = ctx->plan_len[n], keep_split = ctx->split[n];

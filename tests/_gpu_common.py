@@ -20,23 +20,32 @@ def context():
     return dqmc.Context(0)
 
 
-def t27_to_dense(n, state_u32):
-    """Host conversion of a T27 state (uint32 words) into the exact 3^n-bit
-    bitmap (uint64 words), written independently of the library's repack."""
+def h5_to_dense(n, state_u32):
+    """Host conversion of a block state (uint32 words; cube rho at bit
+    rho % 243 of the 256-bit block rho // 243) into the exact 3^n-bit bitmap
+    (uint64 words), written independently of the library's repack.  Checks
+    that every padding bit is 0."""
     N = 3**n
-    if n < 3:
-        bits = np.array([(int(state_u32[0]) >> b) & 1 for b in range(N)], dtype=np.uint8)
-    else:
-        w = np.ascontiguousarray(state_u32, dtype=np.uint32)
-        if np.any(w >> np.uint32(27)):
-            raise AssertionError("padding bits 27..31 set in a state word")
-        bits = np.unpackbits(w.view(np.uint8), bitorder="little").reshape(-1, 32)[:, :27].reshape(-1)
-        bits = bits[:N]
+    w = np.ascontiguousarray(state_u32, dtype=np.uint32)
+    assert w.size % 8 == 0
+    bits = np.unpackbits(w.view(np.uint8), bitorder="little").reshape(-1, 256)
+    if np.any(bits[:, 243:]):
+        raise AssertionError("padding bits 243..255 set in a block")
+    bits = bits[:, :243].reshape(-1)
+    if np.any(bits[N:]):
+        raise AssertionError("bits past 3^n set")
+    bits = bits[:N]
     nbytes = ((N + 63) // 64) * 8
     packed = np.packbits(bits, bitorder="little")
     buf = np.zeros(nbytes, dtype=np.uint8)
     buf[: packed.size] = packed
     return buf.view(np.uint64)
+
+
+def word_and_bit(rho):
+    """State word and bit of cube rho (numpy or torch integer arrays)."""
+    blk, p = rho // 243, rho % 243
+    return 8 * blk + p // 32, p % 32
 
 
 def dev_to_u32(t):

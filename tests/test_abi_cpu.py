@@ -37,10 +37,10 @@ def test_library_exports_every_declared_function():
 def test_sizes(n):
     assert dqmc.dqmc_num_cubes(n) == 3**n
     assert dqmc.dqmc_tt_words(n) == max(1, 2 ** (n - 5)) if n >= 5 else dqmc.dqmc_tt_words(n) == 1
-    assert dqmc.dqmc_state_words(n) == 3 ** max(n - 3, 0)
+    assert dqmc.dqmc_state_words(n) == 8 * 3 ** max(n - 5, 0)
     assert dqmc.dqmc_dense_words(n) == (3**n + 63) // 64
-    # every cube has a slot: 27 per word (or all of them in one word)
-    assert dqmc.dqmc_state_words(n) * 27 >= 3**n
+    # every cube has a slot: 243 per 8-word block (or all of them in one block)
+    assert dqmc.dqmc_state_words(n) // 8 * 243 >= 3**n
 
 
 @pytest.mark.parametrize("n", [-1, 26, 100])

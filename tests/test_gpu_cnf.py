@@ -7,7 +7,7 @@ import pytest
 import oracle
 from paper_2302_10083_amd import inputs
 
-from _gpu_common import context, dev_to_u32, log, t27_to_dense
+from _gpu_common import context, dev_to_u32, h5_to_dense, log, word_and_bit
 
 pytestmark = pytest.mark.gpu
 
@@ -44,7 +44,7 @@ def test_negate_vs_oracle(n, kind, seed):
     _, O, ref = oracle.primes(n, _complement(n, tt))
     assert c == len(ref)
     assert np.array_equal(lst, ref)
-    assert np.array_equal(t27_to_dense(n, dev_to_u32(state)), O)
+    assert np.array_equal(h5_to_dense(n, dev_to_u32(state)), O)
 
 
 @pytest.mark.parametrize("n", [6, 12, 14, 18])
@@ -59,7 +59,7 @@ def test_implicants_negate_vs_oracle(n):
     dqmc.dqmc_implicants_ex(ctx.ctx, n, ctx.tt_to_device(tt), dqmc.DQMC_NEGATE, state)
     torch.cuda.synchronize()
     M = oracle.enum_M(n, _complement(n, tt))
-    assert np.array_equal(t27_to_dense(n, dev_to_u32(state)), M)
+    assert np.array_equal(h5_to_dense(n, dev_to_u32(state)), M)
 
 
 def test_negate_bad_flags():
@@ -118,7 +118,8 @@ def test_negate_n24_equals_complemented_table():
     rng = np.random.default_rng(2424)
     rhos = rng.integers(0, 3**n, size=200_000, dtype=np.int64)
     r = torch.from_numpy(rhos).to(s1.device)
-    got = ((s1[torch.div(r, 27, rounding_mode="floor")].to(torch.int64) >> torch.remainder(r, 27)) & 1)
+    w, b = word_and_bit(r)
+    got = (s1[w].to(torch.int64) >> b) & 1
     got = got.cpu().numpy().astype(bool)
     want, _ = oracle.sample(n, comp, rhos.astype(np.uint64), "prime")
     assert np.array_equal(got, want.astype(bool))

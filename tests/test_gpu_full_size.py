@@ -11,7 +11,7 @@ import pytest
 import oracle
 from paper_2302_10083_amd import inputs
 
-from _gpu_common import context, log, relabel_cubes, relabel_tt
+from _gpu_common import context, log, relabel_cubes, relabel_tt, word_and_bit
 
 pytestmark = pytest.mark.gpu
 
@@ -21,8 +21,7 @@ def _bits_at(state, n, rhos):
     import torch
 
     r = torch.from_numpy(np.asarray(rhos, dtype=np.int64)).to(state.device)
-    w = torch.div(r, 27, rounding_mode="floor")
-    b = torch.remainder(r, 27)
+    w, b = word_and_bit(r)
     return ((state[w].to(torch.int64) >> b) & 1).cpu().numpy().astype(bool)
 
 
@@ -33,8 +32,8 @@ def _popcount_state(state):
     chunk = 1 << 28
     for i in range(0, state.numel(), chunk):
         part = state[i:i + chunk]
-        x = part.to(torch.int64) & 0x7FFFFFF
-        # SWAR popcount on int64 lanes holding 27-bit words
+        x = part.to(torch.int64) & 0xFFFFFFFF
+        # SWAR popcount on int64 lanes holding 32-bit words
         x = x - ((x >> 1) & 0x5555555555555555)
         x = (x & 0x3333333333333333) + ((x >> 2) & 0x3333333333333333)
         x = (x + (x >> 4)) & 0x0F0F0F0F0F0F0F0F

@@ -14,7 +14,7 @@ import oracle
 from paper_2302_10083_amd import inputs
 
 from _gpu_common import (dense_of, dev_to_u32, log, make_tt, oracle_primes, rho_of_binary, run_implicants,
-                         run_primes, t27_to_dense, context)
+                         run_primes, h5_to_dense, context)
 
 pytestmark = pytest.mark.gpu
 
@@ -28,7 +28,7 @@ def check_against_oracle(n, tt, what=""):
     dense = dense_of(n, state)
     assert np.array_equal(dense, O), "prime bitmap differs"
     if n <= 16:
-        assert np.array_equal(t27_to_dense(n, dev_to_u32(state)), O), "T27 state differs"
+        assert np.array_equal(h5_to_dense(n, dev_to_u32(state)), O), "block state differs"
     mstate = run_implicants(n, tt)
     assert np.array_equal(dense_of(n, mstate), M), "implicant bitmap differs"
     return state
@@ -75,7 +75,7 @@ def test_to_dense_matches_host_conversion():
     for n in (0, 1, 2, 3, 5, 9, 13):
         tt = make_tt(n, "bern0.8", 77 + n)
         state, _, _ = run_primes(n, tt)
-        assert np.array_equal(dense_of(n, state), t27_to_dense(n, dev_to_u32(state)))
+        assert np.array_equal(dense_of(n, state), h5_to_dense(n, dev_to_u32(state)))
 
 
 def test_capacity_overflow_keeps_smallest():
