@@ -1,6 +1,6 @@
 """Calibration run for HBM byte counters: one device-to-device copy of a known
 size, so that a profiler's FETCH_SIZE / WRITE_SIZE readings can be scaled to
-bytes.  ``python -m paper_2302_10083_amd.calib_copy [GiB]``"""
+bytes.  ``python calib_copy.py [GiB]``"""
 import sys
 
 import torch
