@@ -242,36 +242,54 @@ typedef struct {
 } dqmc_job;
 
 /* Prime implicants of many independent functions (the batch bit-slicing of
- * independent executions, Sec. 4.2).  Functions with n <= 12 run in ONE
- * persistent launch in which each workgroup takes the next function (largest
- * first) and runs its whole pipeline; functions with 13 <= n <= 16 share
- * five tile-parallel launches (every tile and column of every such function
- * is one work item); larger functions of the batch take the single-function
- * path on the same stream afterwards.  The result of each job is exactly
- * what dqmc_primes gives for it alone.
+ * independent executions, Sec. 4.2), from a DEVICE-RESIDENT job array.
  *
- * Plans separate the host work (checks, ordering, upload of the job table)
- * from the launch, so that dqmc_batch_run can be captured in a HIP graph and
- * replayed; it allocates nothing.  The buffers the jobs point to must stay
- * valid while a plan is run.
- *   dqmc_batch_create: jobs[i].status is set (DQMC_OK, or DQMC_EINVAL for a
- *     malformed job, which is left out while the others still run); the
- *     plan's device memory (job tables, per-tile scratch of the functions
- *     with 13..16 variables: 52 bytes per tile) is allocated here.  Returns DQMC_OK,
- *     DQMC_EINVAL for a NULL/negative job array, DQMC_ENOMEM / DQMC_EDEVICE.
- *   dqmc_batch_config: for the persistent launch of the functions with
- *     n <= 12, grid = number of workgroups (0 = default: two per compute
- *     unit) and order = 0 largest first, 1 interleaved sizes.
- *   dqmc_batch_run: enqueue everything on `stream`.
- *   dqmc_batch_destroy: free the plan (no run may be in flight).
- * dqmc_primes_batch = create + run + wait for the stream + destroy: it
- * returns after the results are complete. */
+ * Every call only enqueues kernels on `stream` and returns.  A planner (one
+ * workgroup) checks each job and writes jobs[i].status on the device
+ * (DQMC_OK, or DQMC_EINVAL for n outside 0..16, a NULL tt/state/count, or a
+ * misaligned buffer: tt 4, state 16, count and list 8 bytes), sorts the valid
+ * jobs by n and lays out the work items of every pass; five launches then
+ * work through them: the whole-function items (n <= 12: the whole pipeline in
+ * one workgroup, largest first) with the truth-table tiles of the jobs with
+ * 13 <= n <= 16, then that group's column pass, tile reduces with summaries,
+ * count scans and lists.
+ * Results are valid after the stream is synchronised; each job's result is
+ * exactly what dqmc_primes gives for it alone (list: the min(count,
+ * list_cap) smallest primes; list may be NULL).  Functions with n > 16 are
+ * not batched: use dqmc_primes.
+ *   d_jobs   device array of njobs dqmc_job (8-byte aligned), read by the
+ *            kernels, status fields written; the buffers it points to must
+ *            stay valid until the work completes.  0 <= njobs <= 2^20.
+ *
+ * dqmc_primes_batch: uses the context's batch scratch (the job order and the
+ * per-tile summaries, about 3.9 KB per job), which the call allocates when
+ * njobs exceeds every earlier call's (then it also synchronises the device
+ * before freeing the smaller one); other calls allocate nothing.  Calls on one
+ * context must be ordered.
+ * Plans own their scratch, so that a run allocates nothing and can be
+ * captured in a HIP graph and replayed:
+ *   dqmc_batch_create: allocates the plan's scratch for njobs jobs and runs
+ *     the planner once (synchronously) to learn how many valid jobs of each
+ *     n the array holds; the plan's launches are then sized exactly
+ *     (dqmc_primes_batch, which knows nothing of the jobs, launches by
+ *     bounds: up to 81 tiles per job, the idle workgroups exiting at once).
+ *     Between runs the jobs' buffers may change; their sizes may not: a run
+ *     that finds different numbers of valid jobs per n does nothing and sets
+ *     every status to DQMC_EINVAL.  DQMC_EINVAL (NULL, njobs out of range,
+ *     misaligned array), DQMC_ENOMEM, DQMC_EDEVICE.
+ *   dqmc_batch_config: col_cap = at most this many workgroups per compute
+ *     unit in the column pass (0, the default: as many as its registers
+ *     allow, four; 1..4 otherwise), order 0 (default): the whole-function
+ *     items (largest first) before the truth-table tiles in the first
+ *     launch, 1: after them.  DQMC_EINVAL outside those ranges.
+ *   dqmc_batch_run: enqueue the planner and the five launches.
+ *   dqmc_batch_destroy: free the plan (no run may be in flight). */
 typedef struct dqmc_batch dqmc_batch;
-int dqmc_batch_create(dqmc_ctx *ctx, dqmc_job *jobs, int32_t njobs, dqmc_batch **out);
-int dqmc_batch_config(dqmc_batch *plan, int32_t grid, int32_t order);
+int dqmc_batch_create(dqmc_ctx *ctx, dqmc_job *d_jobs, int32_t njobs, dqmc_batch **out);
+int dqmc_batch_config(dqmc_batch *plan, int32_t col_cap, int32_t order);
 int dqmc_batch_run(dqmc_batch *plan, void *stream);
 void dqmc_batch_destroy(dqmc_batch *plan);
-int dqmc_primes_batch(dqmc_ctx *ctx, dqmc_job *jobs, int32_t njobs, void *stream);
+int dqmc_primes_batch(dqmc_ctx *ctx, dqmc_job *d_jobs, int32_t njobs, void *stream);
 
 /* ---------------------------------------------------------------------------
  * Serving: a request loop over one device.
@@ -283,7 +301,8 @@ int dqmc_primes_batch(dqmc_ctx *ctx, dqmc_job *jobs, int32_t njobs, void *stream
  * (dqmc_state_words(n) words), a list reserve of min(3^n, max(2^18,
  * 3^(n-3)/16)) entries, its truth table and its count, each rounded up to
  * 256 bytes.  Jobs with n <= 16 that are admitted together run as one batch
- * (the launches of dqmc_batch_run); larger jobs run on their own stream and
+ * (the planned persistent launch of dqmc_primes_batch); larger jobs run on
+ * their own stream and
  * context.  Jobs that arrive
  * while others run are admitted as memory and slots free up (continuous
  * batching), and their work overlaps on the device.  Results stay on the
@@ -378,9 +397,9 @@ int dqmc_get_split(const dqmc_ctx *ctx, int n);
  * NULL) the number timed.  A trial's ms is its fastest of `reps` timed runs
  * (reps >= 1), each after one untimed run.
  *
- * dqmc_batch_autotune: candidates are 1, 2 and 4 persistent workgroups per
- * compute unit, each with order 0 and 1 (six trials); the fastest is set on
- * the plan with dqmc_batch_config.
+ * dqmc_batch_autotune: candidates are the column-pass caps 0, 1, 2 and 3,
+ * each with item order 0 and 1 (eight trials); the fastest is set on the plan
+ * with dqmc_batch_config.
  *
  * dqmc_plan_autotune (12 < n <= 25): candidates are the plans with the
  * fewest groups up to that number plus extra_groups (0..2): every ordered
@@ -395,11 +414,11 @@ int dqmc_get_split(const dqmc_ctx *ctx, int n);
  * for the split trial: DQMC_MAX_PLAN_TRIALS + 1.
  */
 typedef struct {
-    int32_t grid;
+    int32_t col_cap;
     int32_t order;
     float ms;
 } dqmc_batch_trial;
-int dqmc_batch_autotune(dqmc_batch *plan, int32_t reps, void *stream, dqmc_batch_trial *trials, int32_t cap,
+int dqmc_batch_autotune(dqmc_batch *plan, int32_t reps, void *stream, dqmc_batch_trial *trials, int32_t cap_trials,
                         int32_t *ntrials);
 
 #define DQMC_MAX_PLAN_TRIALS 64

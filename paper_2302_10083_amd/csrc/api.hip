@@ -455,6 +455,8 @@ int dqmc_create(int device, dqmc_ctx **out)
     c->slice_tt = nullptr;
     c->split_tt = nullptr;
     c->run = nullptr;
+    c->batch_mem = nullptr;
+    c->batch_cap = 0;
     c->err[0] = 0;
     c->prof = false;
     c->events_made = false;
@@ -490,6 +492,7 @@ void dqmc_destroy(dqmc_ctx *ctx)
     if (ctx->slice_tt) (void)hipFree(ctx->slice_tt);
     if (ctx->split_tt) (void)hipFree(ctx->split_tt);
     if (ctx->run) (void)hipFree(ctx->run);
+    if (ctx->batch_mem) (void)hipFree(ctx->batch_mem);
     delete ctx;
 }
 
@@ -752,133 +755,59 @@ int dqmc_bitmap_to_dense(dqmc_ctx *ctx, int n, const uint32_t *d_state, uint64_t
 }  // extern "C"
 
 
-namespace {
-
-int batch_upload_order(dqmc_batch *b)
-{
-    const size_t m = b->small.size();
-    std::vector<uint32_t> ord(m);
-    for (size_t i = 0; i < m; ++i) ord[i] = (uint32_t)i;
-    // largest first (stable), so that the longest jobs start early
-    std::stable_sort(ord.begin(), ord.end(), [&](uint32_t x, uint32_t y) { return b->small[x].n > b->small[y].n; });
-    if (b->order_mode == 1) {
-        // interleave from both ends: largest, smallest, second largest, ...
-        std::vector<uint32_t> il;
-        size_t lo = 0, hi = m;
-        while (lo < hi) {
-            il.push_back(ord[lo++]);
-            if (lo < hi) il.push_back(ord[--hi]);
-        }
-        ord.swap(il);
-    }
-    if (m > 0 && hipMemcpy(b->d_order, ord.data(), m * sizeof(uint32_t), hipMemcpyHostToDevice) != hipSuccess)
-        return fail(b->ctx, DQMC_EDEVICE, "%s", "upload of the batch order failed");
-    return DQMC_OK;
-}
-
-}  // namespace
-
 extern "C" {
 
 void dqmc_batch_destroy(dqmc_batch *b)
 {
     if (b == nullptr) return;
     (void)hipSetDevice(b->ctx->device);
-    if (b->d_jobs) (void)hipFree(b->d_jobs);
-    if (b->d_order) (void)hipFree(b->d_order);
-    if (b->d_ticket) (void)hipFree(b->d_ticket);
-    void *tbl[] = {(void *)b->tb.jobs, (void *)b->tb.bin_job, (void *)b->tb.tile_job,
-                   (void *)b->tb.counts, (void *)b->tb.chunkmap, (void *)b->tb.offs};
-    for (void *p : tbl)
-        if (p) (void)hipFree(p);
+    if (b->mem) (void)hipFree(b->mem);
     delete b;
 }
 
-int dqmc_batch_create(dqmc_ctx *ctx, dqmc_job *jobs, int32_t njobs, dqmc_batch **out)
+int dqmc_batch_create(dqmc_ctx *ctx, dqmc_job *d_jobs, int32_t njobs, dqmc_batch **out)
 {
     if (out != nullptr) *out = nullptr;
-    if (ctx == nullptr || out == nullptr || njobs < 0 || (jobs == nullptr && njobs > 0)) return DQMC_EINVAL;
+    if (ctx == nullptr || out == nullptr) return DQMC_EINVAL;
     ctx->err[0] = 0;
+    if (njobs < 0 || (uint32_t)njobs > kBatchMaxJobs || (d_jobs == nullptr && njobs > 0) || !aligned(d_jobs, 8))
+        return fail(ctx, DQMC_EINVAL, "%s", "need 0 <= njobs <= 2^20 and an 8-byte aligned device job array");
     if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, DQMC_EDEVICE, "%s", "hipSetDevice failed");
     dqmc_batch *b = new dqmc_batch();
     b->ctx = ctx;
-    b->d_jobs = nullptr;
-    b->d_order = nullptr;
-    b->d_ticket = nullptr;
-    b->tb = TileBatch{};
+    b->d_jobs = d_jobs;
+    b->njobs = njobs;
+    b->mem = nullptr;
+    b->col_cap = 0;
     b->order_mode = 0;
-    for (int32_t i = 0; i < njobs; ++i) {
-        dqmc_job &j = jobs[i];
-        const bool ok = j.n >= 0 && j.n <= DQMC_MAX_N && j.tt != nullptr && j.state != nullptr &&
-                        j.count != nullptr && aligned(j.tt, 4) && aligned(j.state, kStateAlign) && aligned(j.count, 8) &&
-                        aligned(j.list, 8);
-        j.status = ok ? DQMC_OK : DQMC_EINVAL;
-        if (!ok) continue;
-        BatchJob bj{j.tt, j.state, j.list, j.list ? j.list_cap : 0, j.count, j.n, 0};
-        (j.n <= kBatchWholeMaxN ? b->small : j.n <= kBatchTileMaxN ? b->tiled : b->big).push_back(bj);
-    }
-    b->grid = 2 * ctx->ncu;
-    const size_t m = b->small.size();
-    if (hipMalloc((void **)&b->d_ticket, 256) != hipSuccess ||
-        (m > 0 && (hipMalloc((void **)&b->d_jobs, m * sizeof(BatchJob)) != hipSuccess ||
-                   hipMalloc((void **)&b->d_order, m * sizeof(uint32_t)) != hipSuccess))) {
+    const uint32_t cap = njobs > 0 ? (uint32_t)njobs : 1u;
+    if (hipMalloc(&b->mem, batch_scratch_bytes(cap)) != hipSuccess) {
         dqmc_batch_destroy(b);
         return fail(ctx, DQMC_ENOMEM, "%s", "batch plan allocation failed");
     }
-    if (m > 0 && hipMemcpy(b->d_jobs, b->small.data(), m * sizeof(BatchJob), hipMemcpyHostToDevice) != hipSuccess) {
-        dqmc_batch_destroy(b);
-        return fail(ctx, DQMC_EDEVICE, "%s", "upload of the batch job table failed");
-    }
-    const int rc = batch_upload_order(b);
-    if (rc != DQMC_OK) {
-        dqmc_batch_destroy(b);
-        return rc;
-    }
-    // tile-parallel functions: work-item tables and per-tile scratch
-    const uint32_t mt = (uint32_t)b->tiled.size();
-    if (mt > 0) {
-        if (b->tiled.size() > (1u << 24)) {
+    b->bs = batch_scratch_at(b->mem, cap);
+    b->ex = BatchExpect{};
+    if (njobs > 0) {
+        // the jobs' sizes, by the planner itself: the runs get exact grids
+        std::vector<uint32_t> hdr(batch_header_words());
+        if (launch_batch_plan(d_jobs, (uint32_t)njobs, b->bs, nullptr) != hipSuccess ||
+            hipMemcpy(hdr.data(), b->bs.hdr, hdr.size() * 4, hipMemcpyDeviceToHost) != hipSuccess) {
             dqmc_batch_destroy(b);
-            return fail(ctx, DQMC_EINVAL, "%s", "too many functions with 13..16 variables in one batch");
+            return fail(ctx, DQMC_EDEVICE, "%s", "planning the batch failed");
         }
-        std::vector<TileJob> tj(mt);
-        std::vector<uint32_t> bin_job(mt * 16), tile_job(mt * 81);
-        tile_layout(b->tiled.data(), mt, tj.data(), bin_job.data(), tile_job.data(), b->tb);
-        TileBatch &t = b->tb;
-        const uint64_t nt = t.ntiles;
-        bool ok = hipMalloc((void **)&t.jobs, mt * sizeof(TileJob)) == hipSuccess &&
-                  hipMalloc((void **)&t.bin_job, t.nbin * sizeof(uint32_t)) == hipSuccess &&
-                  hipMalloc((void **)&t.tile_job, nt * sizeof(uint32_t)) == hipSuccess &&
-                  hipMalloc((void **)&t.counts, nt * sizeof(uint32_t)) == hipSuccess &&
-                  hipMalloc((void **)&t.chunkmap, nt * kMapWords * sizeof(uint32_t)) == hipSuccess &&
-                  hipMalloc((void **)&t.offs, nt * sizeof(uint64_t)) == hipSuccess;
-        if (!ok) {
-            dqmc_batch_destroy(b);
-            return fail(ctx, DQMC_ENOMEM, "%s", "batch plan allocation failed");
-        }
-        ok = hipMemcpy((void *)t.jobs, tj.data(), mt * sizeof(TileJob), hipMemcpyHostToDevice) == hipSuccess &&
-             hipMemcpy((void *)t.bin_job, bin_job.data(), t.nbin * sizeof(uint32_t), hipMemcpyHostToDevice) ==
-                 hipSuccess &&
-             hipMemcpy((void *)t.tile_job, tile_job.data(), nt * sizeof(uint32_t), hipMemcpyHostToDevice) ==
-                 hipSuccess;
-        if (!ok) {
-            dqmc_batch_destroy(b);
-            return fail(ctx, DQMC_EDEVICE, "%s", "upload of the batch tables failed");
-        }
+        batch_expect_from_header(hdr.data(), &b->ex);
     }
     *out = b;
     return DQMC_OK;
 }
 
-int dqmc_batch_config(dqmc_batch *b, int32_t grid, int32_t order)
+int dqmc_batch_config(dqmc_batch *b, int32_t col_cap, int32_t order)
 {
-    if (b == nullptr || grid < 0 || order < 0 || order > 1) return DQMC_EINVAL;
-    if (hipSetDevice(b->ctx->device) != hipSuccess) return fail(b->ctx, DQMC_EDEVICE, "%s", "hipSetDevice failed");
-    if (grid > 0) b->grid = grid;
-    if (order != b->order_mode) {
-        b->order_mode = order;
-        return batch_upload_order(b);
-    }
+    if (b == nullptr) return DQMC_EINVAL;
+    if (col_cap < 0 || col_cap > kBatchMaxColCap || order < 0 || order >= kBatchModes)
+        return fail(b->ctx, DQMC_EINVAL, "%s", "need 0 <= col_cap <= 4 and order 0 or 1");
+    b->col_cap = col_cap;
+    b->order_mode = order;
     return DQMC_OK;
 }
 
@@ -888,37 +817,40 @@ int dqmc_batch_run(dqmc_batch *b, void *stream)
     dqmc_ctx *ctx = b->ctx;
     ctx->err[0] = 0;
     if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, DQMC_EDEVICE, "%s", "hipSetDevice failed");
+    if (b->njobs == 0) return DQMC_OK;
     hipStream_t s = (hipStream_t)stream;
-    const uint32_t m = (uint32_t)b->small.size();
-    double bytes = 0;
-    for (const BatchJob &j : b->small) bytes += 3.0 * state_bytes(j.n);
-    int rc = run_pass(ctx, s, "batch", -1, bytes, 8, [&] {
-        return launch_batch(b->d_jobs, b->d_order, m, b->d_ticket, (uint32_t)b->grid, s);
+    // the job sizes live on the device: no byte model for the profile record
+    return run_pass(ctx, s, "batch", -1, 0.0, 8, [&] {
+        return launch_batch(b->d_jobs, (uint32_t)b->njobs, b->bs, b->col_cap, b->order_mode, s, &b->ex);
     });
-    if (rc != DQMC_OK) return rc;
-    if (!b->tiled.empty()) {
-        double tbytes = 0;
-        for (const BatchJob &j : b->tiled) tbytes += 3.0 * state_bytes(j.n);
-        rc = run_pass(ctx, s, "batch_tiles", -1, tbytes, 8, [&] { return launch_tile_batch(b->tb, s); });
-        if (rc != DQMC_OK) return rc;
-    }
-    for (const BatchJob &j : b->big) {
-        rc = dqmc_primes(ctx, j.n, j.tt, j.state, j.list, j.cap, j.count, stream);
-        if (rc != DQMC_OK) return rc;
-    }
-    return DQMC_OK;
 }
 
-int dqmc_primes_batch(dqmc_ctx *ctx, dqmc_job *jobs, int32_t njobs, void *stream)
+int dqmc_primes_batch(dqmc_ctx *ctx, dqmc_job *d_jobs, int32_t njobs, void *stream)
 {
-    dqmc_batch *b = nullptr;
-    int rc = dqmc_batch_create(ctx, jobs, njobs, &b);
-    if (rc != DQMC_OK) return rc;
-    rc = dqmc_batch_run(b, stream);
-    if (rc == DQMC_OK && hipStreamSynchronize((hipStream_t)stream) != hipSuccess)
-        rc = fail(ctx, DQMC_EDEVICE, "%s", "batch did not complete");
-    dqmc_batch_destroy(b);
-    return rc;
+    if (ctx == nullptr) return DQMC_EINVAL;
+    ctx->err[0] = 0;
+    if (njobs < 0 || (uint32_t)njobs > kBatchMaxJobs || (d_jobs == nullptr && njobs > 0) || !aligned(d_jobs, 8))
+        return fail(ctx, DQMC_EINVAL, "%s", "need 0 <= njobs <= 2^20 and an 8-byte aligned device job array");
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, DQMC_EDEVICE, "%s", "hipSetDevice failed");
+    if (njobs == 0) return DQMC_OK;
+    if ((uint32_t)njobs > ctx->batch_cap) {
+        // grow the context's batch scratch (the only allocation of this call;
+        // a call that does not grow it only enqueues)
+        if (ctx->batch_mem != nullptr) {
+            if (hipDeviceSynchronize() != hipSuccess) return fail(ctx, DQMC_EDEVICE, "%s", "synchronize failed");
+            (void)hipFree(ctx->batch_mem);
+            ctx->batch_mem = nullptr;
+            ctx->batch_cap = 0;
+        }
+        if (hipMalloc(&ctx->batch_mem, batch_scratch_bytes((uint32_t)njobs)) != hipSuccess)
+            return fail(ctx, DQMC_ENOMEM, "%s", "batch scratch allocation failed");
+        ctx->batch_cap = (uint32_t)njobs;
+    }
+    const BatchScratch bs = batch_scratch_at(ctx->batch_mem, ctx->batch_cap);
+    hipStream_t s = (hipStream_t)stream;
+    return run_pass(ctx, s, "batch", -1, 0.0, 8, [&] {
+        return launch_batch(d_jobs, (uint32_t)njobs, bs, 0, 0, s);
+    });
 }
 
 int dqmc_hash_words(dqmc_ctx *ctx, const uint32_t *d_words, uint64_t nwords, uint64_t *d_out, void *stream)

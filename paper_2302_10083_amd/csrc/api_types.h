@@ -2,8 +2,6 @@
 // dqmc_batch); shared by the entry points and the autotuner.
 #pragma once
 
-#include <vector>
-
 #include "dqmc.h"
 #include "launch.h"
 
@@ -19,6 +17,8 @@ struct dqmc_ctx {
     uint32_t *slice_tt;  // sliced path: truth table of one slice (2^20 words)
     uint32_t *split_tt;  // top-digit split: truth table of one third (2^19 words)
     uint64_t *run;       // sliced path: running prime counts (2)
+    void *batch_mem;     // dqmc_primes_batch: scratch for up to batch_cap jobs (grown on demand)
+    uint32_t batch_cap;
     char err[512];
     // per-pass timing (diagnostics)
     bool prof;
@@ -35,13 +35,11 @@ struct dqmc_ctx {
 
 struct dqmc_batch {
     dqmc_ctx *ctx;
-    dqmc::BatchJob *d_jobs;
-    uint32_t *d_order;
-    uint32_t *d_ticket;
-    std::vector<dqmc::BatchJob> small;  // n <= kBatchWholeMaxN, in job-table order
-    std::vector<dqmc::BatchJob> tiled;  // kBatchWholeMaxN < n <= kBatchTileMaxN
-    std::vector<dqmc::BatchJob> big;    // larger functions: single-function path
-    dqmc::TileBatch tb;                 // device tables of the tiled functions
-    int32_t grid;
-    int32_t order_mode;
+    dqmc_job *d_jobs;  // the caller's device-resident job array
+    int32_t njobs;
+    void *mem;               // the plan's scratch (one allocation)
+    dqmc::BatchScratch bs;   // laid out in mem
+    dqmc::BatchExpect ex;    // the jobs' sizes at creation: the launches' exact grids
+    int32_t col_cap;         // column-pass workgroups per CU (0: no cap)
+    int32_t order_mode;      // order of the first launch's items
 };

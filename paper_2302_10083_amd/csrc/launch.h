@@ -89,76 +89,57 @@ hipError_t launch_col(int gr, int gw, int mode, const ColArgs &a, hipStream_t s)
 hipError_t launch_col_chunked(int gr, int gw, int mode, const ColArgs &a, hipStream_t s);
 int col_lanes_per_block(int gw);  // l values per workgroup
 
-// One function of a batch as the batch kernel sees it (device memory).
-struct BatchJob {
-    const uint32_t *tt;
-    uint32_t *state;
-    uint64_t *list;
-    uint64_t cap;
-    uint64_t *count;
-    int32_t n;
-    int32_t pad;
+// Batch of many functions (k_batch.hip): jobs with n <= kBatchWholeMaxN run
+// whole in one workgroup; jobs with kBatchWholeMaxN < n <= kBatchMaxN run
+// tile-parallel, one launch per pass.
+constexpr int kBatchWholeMaxN = 12;
+constexpr int kBatchMaxN = 16;
+constexpr uint32_t kBatchMaxJobs = 1u << 20;
+constexpr int kBatchThreads = 768;
+constexpr int kBatchModes = 2;       // item orders of the first launch
+constexpr int kBatchMaxColCap = 4;   // column-launch workgroups per CU, as a cap (0: none)
+constexpr uint32_t kLdsPerCu = 160 * 1024;
+
+// Header of a batch's work items (uint32 words, written by the planner).
+constexpr int kBatchHdrWords = 256;
+
+// Device scratch of a batch of up to `cap` jobs, in one allocation.
+struct BatchScratch {
+    uint32_t *hdr;       // kBatchHdrWords words: ticket, segment sizes, bin bases
+    uint32_t *order;     // cap: job indices sorted by n, largest first (stable)
+    uint32_t *counts;    // 81 * cap: per tile, set bits of the prime bitmap
+    uint32_t *chunkmap;  // 81 * kMapWords * cap: per tile, non-zero chunks
+    uint64_t *offs;      // 81 * cap: per tile, list offset within its function
+    uint32_t cap;
 };
 
-constexpr int kBatchWholeMaxN = 12;  // one workgroup runs the whole function
-constexpr int kBatchTileMaxN = 16;   // tile-parallel; larger: the single-function path
+uint64_t batch_scratch_bytes(uint32_t cap);
+// Lay out a scratch of batch_scratch_bytes(cap) bytes at `base` (256-byte
+// aligned).
+BatchScratch batch_scratch_at(void *base, uint32_t cap);
+
+// The valid jobs per n that a batch's launches are sized for (exact = 1), or
+// nothing known (exact = 0: the launches are sized by bounds).
+struct BatchExpect {
+    uint32_t hist[kBatchMaxN + 1];
+    uint32_t exact;
+};
 
 hipError_t batch_setup();
-// Persistent launch over njobs jobs (n <= kBatchWholeMaxN) in the given
-// order (ticket zeroed first).
-hipError_t launch_batch(const BatchJob *jobs, const uint32_t *order, uint32_t njobs, uint32_t *ticket,
-                        uint32_t grid, hipStream_t s);
-
-// A function with 13 <= n <= kBatchTileMaxN of a batch, run tile-parallel.
-// Its 2^(n-12) tiles with binary digits 13..n are work items first_bin..,
-// its 3^(n-12) tiles are first_tile.. in the batch's per-tile arrays.
-struct TileJob {
-    const uint32_t *tt;
-    uint32_t *state;
-    uint64_t *list;
-    uint64_t cap;
-    uint64_t *count;
-    int32_t n;
-    uint32_t first_bin;
-    uint32_t first_tile;
-    uint32_t pad;
-};
-
-struct TileBatch {
-    const TileJob *jobs;
-    const uint32_t *bin_job;   // per binary-tile work item: its function
-    const uint32_t *tile_job;  // per tile: its function
-    uint32_t *counts;          // per tile: set bits of the prime bitmap
-    uint32_t *chunkmap;        // per tile: kMapWords words of non-zero chunks
-    uint64_t *offs;            // per tile: list offset within its function
-    uint32_t njobs;
-    uint32_t nbin;
-    uint32_t ntiles;
-};
-
-// The five launches of the tile-parallel batch path.
-hipError_t launch_tile_batch(const TileBatch &b, hipStream_t s);
-
-// Host: the work items of m functions with 13 <= n <= kBatchTileMaxN: fills
-// tj[0..m), bin_job (2^(n-12) entries per function) and tile_job (3^(n-12)
-// per function) and sets b.njobs, b.nbin, b.ntiles.
-inline void tile_layout(const BatchJob *jobs, uint32_t m, TileJob *tj, uint32_t *bin_job, uint32_t *tile_job,
-                        TileBatch &b)
-{
-    uint32_t nbin = 0, ntiles = 0;
-    for (uint32_t i = 0; i < m; ++i) {
-        const BatchJob &j = jobs[i];
-        const int h = j.n - 12;
-        tj[i] = TileJob{j.tt, j.state, j.list, j.cap, j.count, j.n, nbin, ntiles, 0};
-        for (uint32_t k = 0; k < (1u << h); ++k) bin_job[nbin++] = i;
-        uint32_t nt = 1;
-        for (int q = 0; q < h; ++q) nt *= 3;
-        for (uint32_t k = 0; k < nt; ++k) tile_job[ntiles++] = i;
-    }
-    b.njobs = m;
-    b.nbin = nbin;
-    b.ntiles = ntiles;
-}
+// Enqueue the planner and the five pass launches for the device-resident job
+// array `jobs` (njobs <= s.cap); col_cap = at most this many column-pass
+// workgroups per CU (0: no cap), mode 0: whole-function items before the
+// truth-table tiles, 1: after them.  With ex->exact the launches get exact
+// grids, and a
+// run whose jobs' sizes differ from ex->hist does nothing but set every
+// status to DQMC_EINVAL.
+hipError_t launch_batch(void *jobs, uint32_t njobs, const BatchScratch &s, int col_cap, int mode, hipStream_t st,
+                        const BatchExpect *ex = nullptr);
+// The planner alone (checks the jobs, writes their statuses and the header).
+hipError_t launch_batch_plan(void *jobs, uint32_t njobs, const BatchScratch &s, hipStream_t st);
+// The histogram a planner run left in the header (copied to the host).
+void batch_expect_from_header(const uint32_t *hdr_host, BatchExpect *ex);
+uint32_t batch_header_words();
 
 // Sliced path (k_slice.hip): the truth table of the restriction of f to the
 // cube of its top variables given by fixed (bits equal to 1) and stars (bits

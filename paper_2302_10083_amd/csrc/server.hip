@@ -5,10 +5,10 @@
 //   2. admits queued jobs first-fit in arrival order while their footprint
 //      fits the free budget (a job that has waited longer than kAgingSeconds
 //      at the head of the queue stops others from overtaking it);
-//   3. launches: all admitted jobs with n <= kBatchTileMaxN go into one
-//      batch on a free batch slot (the one-workgroup-per-function launch for
-//      n <= 12, the tile-parallel launches for 13..16), each larger job gets
-//      a free slot (stream + context) of its own.
+//   3. launches: all admitted jobs with n <= kBatchMaxN go into one batch on
+//      a free batch slot (the device-planned persistent launch of
+//      k_batch.hip), each larger job gets a free slot (stream + context) of
+//      its own.
 // Device memory is one arena of `budget` bytes allocated when the server is
 // created; each admitted job gets one block of its footprint from a host-side
 // first-fit allocator (large jobs from the low end, small ones from the high
@@ -142,18 +142,11 @@ struct Slot {
     hipEvent_t ev = nullptr;
     bool busy = false;
     std::vector<uint64_t> jobs;
-    // batch slots: job table staging
-    BatchJob *h_jobs = nullptr;
-    uint32_t *h_order = nullptr;
-    BatchJob *d_jobs = nullptr;
-    uint32_t *d_order = nullptr;
-    uint32_t *d_ticket = nullptr;
-    // batch slots: tile-parallel tables (functions with 13..16 variables)
-    BatchJob *h_tiled = nullptr;
-    TileJob *h_tj = nullptr;
-    uint32_t *h_bin = nullptr;
-    uint32_t *h_tile = nullptr;
-    TileBatch tb{};
+    // batch slots: job table (pinned staging, device copy) and batch scratch
+    dqmc_job *h_jobs = nullptr;
+    dqmc_job *d_jobs = nullptr;
+    void *d_scratch = nullptr;
+    BatchScratch bs{};
 };
 
 }  // namespace
@@ -221,45 +214,23 @@ void launch_small(dqmc_server *s, Slot &sl, const std::vector<uint64_t> &ids)
 {
     sl.busy = true;
     sl.jobs = ids;
-    uint32_t m = 0, mt = 0;
+    uint32_t m = 0;
+    BatchExpect ex{};  // every staged job is valid: its size is known here
+    ex.exact = 1;
     for (uint64_t id : ids) {
         SJob &j = s->jobs[id];
         if (!stage_job(s, j, sl.stream)) {
             j.status = DQMC_EDEVICE;
             continue;
         }
-        const BatchJob bj{j.d_tt, j.d_state, j.d_list, j.cap, j.d_count, j.n, 0};
-        if (j.n <= kBatchWholeMaxN) {
-            sl.h_jobs[m] = bj;
-            sl.h_order[m] = m;
-            ++m;
-        } else {
-            sl.h_tiled[mt++] = bj;
-        }
+        sl.h_jobs[m++] = dqmc_job{j.n, 0, j.d_tt, j.d_state, j.d_list, j.cap, j.d_count};
+        ++ex.hist[j.n];
     }
-    // largest first
-    std::stable_sort(sl.h_order, sl.h_order + m,
-                     [&](uint32_t a, uint32_t b) { return sl.h_jobs[a].n > sl.h_jobs[b].n; });
     bool ok = true;
     if (m > 0) {
-        ok = hipMemcpyAsync(sl.d_jobs, sl.h_jobs, m * sizeof(BatchJob), hipMemcpyHostToDevice, sl.stream) ==
-                 hipSuccess &&
-             hipMemcpyAsync(sl.d_order, sl.h_order, m * sizeof(uint32_t), hipMemcpyHostToDevice, sl.stream) ==
-                 hipSuccess;
-        int ncu = 256;
-        (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, s->device);
-        const uint32_t grid = m < (uint32_t)(2 * ncu) ? m : (uint32_t)(2 * ncu);
-        if (ok) ok = launch_batch(sl.d_jobs, sl.d_order, m, sl.d_ticket, grid, sl.stream) == hipSuccess;
-    }
-    if (ok && mt > 0) {
-        tile_layout(sl.h_tiled, mt, sl.h_tj, sl.h_bin, sl.h_tile, sl.tb);
-        ok = hipMemcpyAsync((void *)sl.tb.jobs, sl.h_tj, mt * sizeof(TileJob), hipMemcpyHostToDevice, sl.stream) ==
-                 hipSuccess &&
-             hipMemcpyAsync((void *)sl.tb.bin_job, sl.h_bin, sl.tb.nbin * sizeof(uint32_t), hipMemcpyHostToDevice,
-                            sl.stream) == hipSuccess &&
-             hipMemcpyAsync((void *)sl.tb.tile_job, sl.h_tile, sl.tb.ntiles * sizeof(uint32_t),
-                            hipMemcpyHostToDevice, sl.stream) == hipSuccess;
-        if (ok) ok = launch_tile_batch(sl.tb, sl.stream) == hipSuccess;
+        ok = hipMemcpyAsync(sl.d_jobs, sl.h_jobs, m * sizeof(dqmc_job), hipMemcpyHostToDevice, sl.stream) ==
+             hipSuccess;
+        if (ok) ok = launch_batch(sl.d_jobs, m, sl.bs, 0, 0, sl.stream, &ex) == hipSuccess;
     }
     for (uint64_t id : ids) {
         SJob &j = s->jobs[id];
@@ -324,7 +295,7 @@ void scheduler(dqmc_server *s)
         for (auto it = s->queue.begin(); it != s->queue.end();) {
             SJob &j = s->jobs[*it];
             const bool is_head = it == s->queue.begin();
-            const bool small = j.n <= kBatchTileMaxN;
+            const bool small = j.n <= kBatchMaxN;
             Slot *slot = nullptr;
             if (small) {
                 if (free_small && small_ids.size() < kBatchSlotJobs) slot = free_small;
@@ -398,22 +369,10 @@ int dqmc_server_create(int device, uint64_t budget_bytes, int32_t slots, dqmc_se
             ok = ok && dqmc_create(device, &sl.ctx) == DQMC_OK;
         }
     for (Slot &sl : s->small) {
-        ok = ok && hipHostMalloc((void **)&sl.h_jobs, kBatchSlotJobs * sizeof(BatchJob), 0) == hipSuccess;
-        ok = ok && hipHostMalloc((void **)&sl.h_order, kBatchSlotJobs * sizeof(uint32_t), 0) == hipSuccess;
-        ok = ok && hipMalloc((void **)&sl.d_jobs, kBatchSlotJobs * sizeof(BatchJob)) == hipSuccess;
-        ok = ok && hipMalloc((void **)&sl.d_order, kBatchSlotJobs * sizeof(uint32_t)) == hipSuccess;
-        ok = ok && hipMalloc((void **)&sl.d_ticket, 256) == hipSuccess;
-        const uint64_t mb = kBatchSlotJobs * 16ull, mt = kBatchSlotJobs * 81ull;
-        ok = ok && hipHostMalloc((void **)&sl.h_tiled, kBatchSlotJobs * sizeof(BatchJob), 0) == hipSuccess;
-        ok = ok && hipHostMalloc((void **)&sl.h_tj, kBatchSlotJobs * sizeof(TileJob), 0) == hipSuccess;
-        ok = ok && hipHostMalloc((void **)&sl.h_bin, mb * sizeof(uint32_t), 0) == hipSuccess;
-        ok = ok && hipHostMalloc((void **)&sl.h_tile, mt * sizeof(uint32_t), 0) == hipSuccess;
-        ok = ok && hipMalloc((void **)&sl.tb.jobs, kBatchSlotJobs * sizeof(TileJob)) == hipSuccess;
-        ok = ok && hipMalloc((void **)&sl.tb.bin_job, mb * sizeof(uint32_t)) == hipSuccess;
-        ok = ok && hipMalloc((void **)&sl.tb.tile_job, mt * sizeof(uint32_t)) == hipSuccess;
-        ok = ok && hipMalloc((void **)&sl.tb.counts, mt * sizeof(uint32_t)) == hipSuccess;
-        ok = ok && hipMalloc((void **)&sl.tb.chunkmap, mt * kMapWords * sizeof(uint32_t)) == hipSuccess;
-        ok = ok && hipMalloc((void **)&sl.tb.offs, mt * sizeof(uint64_t)) == hipSuccess;
+        ok = ok && hipHostMalloc((void **)&sl.h_jobs, kBatchSlotJobs * sizeof(dqmc_job), 0) == hipSuccess;
+        ok = ok && hipMalloc((void **)&sl.d_jobs, kBatchSlotJobs * sizeof(dqmc_job)) == hipSuccess;
+        ok = ok && hipMalloc(&sl.d_scratch, batch_scratch_bytes(kBatchSlotJobs)) == hipSuccess;
+        if (ok) sl.bs = batch_scratch_at(sl.d_scratch, kBatchSlotJobs);
     }
     if (!ok) {
         dqmc_server_destroy(s);
@@ -555,15 +514,8 @@ void dqmc_server_destroy(dqmc_server *s)
             if (sl.ev) (void)hipEventDestroy(sl.ev);
             if (sl.stream) (void)hipStreamDestroy(sl.stream);
             if (sl.h_jobs) (void)hipHostFree(sl.h_jobs);
-            if (sl.h_order) (void)hipHostFree(sl.h_order);
             if (sl.d_jobs) (void)hipFree(sl.d_jobs);
-            if (sl.d_order) (void)hipFree(sl.d_order);
-            if (sl.d_ticket) (void)hipFree(sl.d_ticket);
-            for (void *h : {(void *)sl.h_tiled, (void *)sl.h_tj, (void *)sl.h_bin, (void *)sl.h_tile})
-                if (h) (void)hipHostFree(h);
-            for (void *d : {(void *)sl.tb.jobs, (void *)sl.tb.bin_job, (void *)sl.tb.tile_job, (void *)sl.tb.counts,
-                            (void *)sl.tb.chunkmap, (void *)sl.tb.offs})
-                if (d) (void)hipFree(d);
+            if (sl.d_scratch) (void)hipFree(sl.d_scratch);
         }
     if (s->arena_base) (void)hipFree(s->arena_base);
     delete s;

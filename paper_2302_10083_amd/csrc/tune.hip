@@ -1,5 +1,5 @@
 // Autotuning of the launch choices that leave results unchanged: the
-// persistent grid and job order of a batch plan, and the digit-group plan of
+// column-pass occupancy cap and item order of a batch plan, and the digit-group plan of
 // the single-function pipeline.  Candidates are timed on the caller's own
 // buffers with HIP events on the caller's stream; the fastest is applied
 // through the public configuration calls (dqmc_batch_config, dqmc_set_plan).
@@ -78,39 +78,38 @@ void splits(int h, int k, std::vector<int> &cur, std::vector<std::vector<int>> &
 
 extern "C" {
 
-int dqmc_batch_autotune(dqmc_batch *plan, int32_t reps, void *stream, dqmc_batch_trial *trials, int32_t cap,
+int dqmc_batch_autotune(dqmc_batch *plan, int32_t reps, void *stream, dqmc_batch_trial *trials, int32_t cap_trials,
                         int32_t *ntrials)
 {
     if (ntrials != nullptr) *ntrials = 0;
-    if (plan == nullptr || reps < 1 || cap < 0 || (trials == nullptr && cap > 0)) return DQMC_EINVAL;
+    if (plan == nullptr || reps < 1 || cap_trials < 0 || (trials == nullptr && cap_trials > 0)) return DQMC_EINVAL;
     dqmc_ctx *ctx = plan->ctx;
     ctx->err[0] = 0;
     if (hipSetDevice(ctx->device) != hipSuccess) return tune_fail(ctx, DQMC_EDEVICE, "hipSetDevice failed");
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing((hipStream_t)stream, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
         return tune_fail(ctx, DQMC_EINVAL, "autotuning cannot run while the stream is captured");
-    const int per_cu[] = {1, 2, 4};
-    int32_t best_grid = plan->grid, best_order = plan->order_mode, n = 0;
+    const int caps[] = {0, 1, 2, 3};  // column-pass workgroups per CU (0: as many as the registers allow, 4)
+    int32_t best_cap = plan->col_cap, best_order = plan->order_mode, n = 0;
     float best = -1.0f;
-    for (int order = 0; order <= 1; ++order) {
-        for (int pc : per_cu) {
-            const int32_t grid = pc * ctx->ncu;
-            int rc = dqmc_batch_config(plan, grid, order);
+    for (int order = 0; order < dqmc::kBatchModes; ++order) {
+        for (int cap : caps) {
+            int rc = dqmc_batch_config(plan, cap, order);
             if (rc != DQMC_OK) return rc;
             const float ms = time_best((hipStream_t)stream, reps, &rc, [&] { return dqmc_batch_run(plan, stream); });
             if (rc != DQMC_OK) return rc;
             if (ms < 0.0f) return tune_fail(ctx, DQMC_EDEVICE, "timing a batch candidate failed");
-            if (n < cap) trials[n] = dqmc_batch_trial{grid, order, ms};
+            if (n < cap_trials) trials[n] = dqmc_batch_trial{cap, order, ms};
             ++n;
             if (best < 0.0f || ms < best) {
                 best = ms;
-                best_grid = grid;
+                best_cap = cap;
                 best_order = order;
             }
         }
     }
     if (ntrials != nullptr) *ntrials = n;
-    return dqmc_batch_config(plan, best_grid, best_order);
+    return dqmc_batch_config(plan, best_cap, best_order);
 }
 
 int dqmc_plan_autotune(dqmc_ctx *ctx, int n, const uint32_t *d_tt, uint32_t *d_state, uint64_t *d_count,

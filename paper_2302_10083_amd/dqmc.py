@@ -79,7 +79,7 @@ class dqmc_job(ctypes.Structure):
 
 
 class dqmc_batch_trial(ctypes.Structure):
-    _fields_ = [("grid", ctypes.c_int32), ("order", ctypes.c_int32), ("ms", ctypes.c_float)]
+    _fields_ = [("col_cap", ctypes.c_int32), ("order", ctypes.c_int32), ("ms", ctypes.c_float)]
 
 
 class dqmc_plan_trial(ctypes.Structure):
@@ -124,9 +124,9 @@ def load():
             "dqmc_primes_sliced_multi": (i32, [vp, i32, i32, vp, ctypes.c_uint32, vp, ctypes.POINTER(vp), i32, vp,
                                                u64, vp, vp]),
             "dqmc_bitmap_to_dense": (i32, [vp, i32, vp, vp, vp]),
-            "dqmc_primes_batch": (i32, [vp, ctypes.POINTER(dqmc_job), ctypes.c_int32, vp]),
+            "dqmc_primes_batch": (i32, [vp, vp, ctypes.c_int32, vp]),
             "dqmc_profile": (i32, [vp, i32]),
-            "dqmc_batch_create": (i32, [vp, ctypes.POINTER(dqmc_job), ctypes.c_int32, ctypes.POINTER(vp)]),
+            "dqmc_batch_create": (i32, [vp, vp, ctypes.c_int32, ctypes.POINTER(vp)]),
             "dqmc_batch_config": (i32, [vp, ctypes.c_int32, ctypes.c_int32]),
             "dqmc_batch_run": (i32, [vp, vp]),
             "dqmc_batch_destroy": (None, [vp]),
@@ -365,7 +365,9 @@ def _job_array(jobs):
     arr = (dqmc_job * max(1, len(jobs)))()
     for i, j in enumerate(jobs):
         n = int(j["n"])
-        nn = n if 0 <= n <= DQMC_MAX_N else 0
+        # sizes are checked for the n a batch accepts; other jobs are passed
+        # through for the library to reject
+        nn = n if 0 <= n <= 16 else 0
         lst = j.get("list")
         cap = 0 if lst is None else int(j.get("list_cap", lst.numel()))
         arr[i].n = n
@@ -378,41 +380,84 @@ def _job_array(jobs):
     return arr
 
 
-def dqmc_primes_batch(ctx, jobs, stream=None) -> list:
-    """``jobs``: list of dicts with keys n, tt, state, list (or None),
-    list_cap, count (device tensors).  Waits for completion; returns the
-    per-job status codes."""
+def job_table(jobs, device=None):
+    """The device-resident dqmc_job array for a list of job dicts (keys n, tt,
+    state, list (or None), list_cap, count; device tensors), as a uint8
+    device tensor.  Invalid jobs are passed through for the library to
+    reject."""
+    import torch
+
     arr = _job_array(jobs)
-    _check(ctx, load().dqmc_primes_batch(ctx, arr, len(jobs), _stream(stream)))
-    return [int(arr[i].status) for i in range(len(jobs))]
+    host = torch.frombuffer(bytearray(bytes(arr)), dtype=torch.uint8)
+    if device is None:
+        device = next((j[k].device for j in jobs for k in ("state", "tt", "count")
+                       if j.get(k) is not None), torch.device("cuda"))
+    return host.to(device)
+
+
+def job_status(table, njobs: int) -> list:
+    """The status fields of a device job table (waits for the copy)."""
+    import numpy as np
+
+    raw = table.cpu().numpy().view(np.uint8)
+    rec = np.frombuffer(raw.tobytes(), dtype=np.int32).reshape(-1, ctypes.sizeof(dqmc_job) // 4)
+    return [int(x) for x in rec[:njobs, 1]]
+
+
+def dqmc_primes_batch(ctx, jobs, stream=None, njobs=None):
+    """dqmc_primes_batch.  ``jobs`` is a device job table (from job_table;
+    then only enqueued, and None is returned) or a list of job dicts (then the
+    table is built, the call is enqueued, the stream is waited for, and the
+    per-job status codes are returned)."""
+    import torch
+
+    if isinstance(jobs, torch.Tensor):
+        k = int(njobs) if njobs is not None else jobs.numel() // ctypes.sizeof(dqmc_job)
+        _check(ctx, load().dqmc_primes_batch(ctx, ctypes.c_void_p(jobs.data_ptr()), k, _stream(stream)))
+        return None
+    table = job_table(jobs)
+    _check(ctx, load().dqmc_primes_batch(ctx, ctypes.c_void_p(table.data_ptr()), len(jobs), _stream(stream)))
+    torch.cuda.synchronize()
+    return job_status(table, len(jobs))
 
 
 class Batch:
-    """A batch plan (dqmc_batch_create / config / run / destroy).  The job
-    tensors must stay alive while the plan is used."""
+    """A batch plan (dqmc_batch_create / config / run / destroy) over a device
+    job table built from ``jobs``.  The job tensors must stay alive while the
+    plan is used; the statuses are written by every run."""
 
     def __init__(self, ctx, jobs):
         self.ctx = ctx
         self._jobs = jobs  # keep the tensors alive
-        arr = _job_array(jobs)
+        self.table = job_table(jobs)
+        self.njobs = len(jobs)
         out = ctypes.c_void_p()
-        _check(ctx, load().dqmc_batch_create(ctx, arr, len(jobs), ctypes.byref(out)))
+        _check(ctx, load().dqmc_batch_create(ctx, ctypes.c_void_p(self.table.data_ptr()), len(jobs),
+                                             ctypes.byref(out)))
         self.plan = out
-        self.status = [int(arr[i].status) for i in range(len(jobs))]
 
-    def config(self, grid: int = 0, order: int = 0):
-        _check(self.ctx, load().dqmc_batch_config(self.plan, grid, order))
+    @property
+    def status(self) -> list:
+        """Per-job status codes of the last run (waits for the device)."""
+        import torch
+
+        torch.cuda.synchronize()
+        return job_status(self.table, self.njobs)
+
+    def config(self, col_cap: int = 0, order: int = 0):
+        _check(self.ctx, load().dqmc_batch_config(self.plan, col_cap, order))
 
     def run(self, stream=None):
         _check(self.ctx, load().dqmc_batch_run(self.plan, _stream(stream)))
 
     def autotune(self, reps: int = 3, stream=None) -> list:
-        """dqmc_batch_autotune: time the grid/order candidates, keep the
-        fastest; returns the trials as dicts (grid, order, ms)."""
+        """dqmc_batch_autotune: time the column-cap/order candidates, keep the
+        fastest; returns the trials as dicts (col_cap, order, ms)."""
         arr = (dqmc_batch_trial * 16)()
         k = ctypes.c_int32(0)
         _check(self.ctx, load().dqmc_batch_autotune(self.plan, reps, _stream(stream), arr, 16, ctypes.byref(k)))
-        return [dict(grid=arr[i].grid, order=arr[i].order, ms=float(arr[i].ms)) for i in range(min(k.value, 16))]
+        return [dict(col_cap=arr[i].col_cap, order=arr[i].order, ms=float(arr[i].ms))
+                for i in range(min(k.value, 16))]
 
     def close(self):
         if self.plan is not None:

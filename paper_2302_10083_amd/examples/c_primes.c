@@ -1,7 +1,11 @@
 /*
  * c_primes - the C ABI of libdqmc used from plain C, without Python or torch:
  * device buffers from hipMalloc, one dqmc_primes call to size the list, a
- * second one to fill it, and dqmc_extract on the bitmap it leaves.
+ * second one to fill it, and dqmc_extract on the bitmap it leaves.  For
+ * n <= 16 it also runs dqmc_primes_batch on a device-resident job array of
+ * three jobs (the same function with a list, the same function count-only,
+ * and a job with n = 17 that the batch rejects), checks the statuses, counts
+ * and list against the single call, and prints "batch ok".
  *
  *   c_primes <n> <truth-table file> <output file>
  *
@@ -93,6 +97,51 @@ int main(int argc, char **argv)
     CHECK_DQMC(ctx, dqmc_extract(ctx, n, d_state, d_list, count, d_count, s));
     CHECK_HIP(hipStreamSynchronize(s));
     CHECK_HIP(hipMemcpy(list2, d_list, count * 8, hipMemcpyDeviceToHost));
+
+    if (n <= 16) {
+        /* the batch call: a device-resident job array, enqueue only */
+        uint32_t *d_state2;
+        uint64_t *d_list2, *d_count2;
+        dqmc_job h_jobs[3], *d_jobs;
+        CHECK_HIP(hipMalloc((void **)&d_state2, sw * 4));
+        CHECK_HIP(hipMalloc((void **)&d_list2, cap * 8));
+        CHECK_HIP(hipMalloc((void **)&d_count2, 16));
+        CHECK_HIP(hipMalloc((void **)&d_jobs, sizeof(h_jobs)));
+        dqmc_job a = {n, -9, d_tt, d_state2, d_list2, count, d_count2};
+        dqmc_job b = {n, -9, d_tt, d_state, NULL, 0, d_count2 + 1};
+        dqmc_job c = {17, -9, d_tt, d_state, NULL, 0, d_count};
+        h_jobs[0] = a;
+        h_jobs[1] = b;
+        h_jobs[2] = c;
+        CHECK_HIP(hipMemcpy(d_jobs, h_jobs, sizeof(h_jobs), hipMemcpyHostToDevice));
+        CHECK_DQMC(ctx, dqmc_primes_batch(ctx, d_jobs, 3, s));
+        CHECK_HIP(hipStreamSynchronize(s));
+        uint64_t bc[2];
+        CHECK_HIP(hipMemcpy(h_jobs, d_jobs, sizeof(h_jobs), hipMemcpyDeviceToHost));
+        CHECK_HIP(hipMemcpy(bc, d_count2, 16, hipMemcpyDeviceToHost));
+        CHECK_HIP(hipMemcpy(list2, d_list2, count * 8, hipMemcpyDeviceToHost));
+        if (h_jobs[0].status != DQMC_OK || h_jobs[1].status != DQMC_OK || h_jobs[2].status != DQMC_EINVAL ||
+            bc[0] != count || bc[1] != count) {
+            fprintf(stderr, "batch: statuses %d %d %d, counts %llu %llu (want %llu)\n", h_jobs[0].status,
+                    h_jobs[1].status, h_jobs[2].status, (unsigned long long)bc[0], (unsigned long long)bc[1],
+                    (unsigned long long)count);
+            return 5;
+        }
+        for (uint64_t i = 0; i < count; ++i)
+            if (list2[i] != list[i]) {
+                fprintf(stderr, "batch list differs at %llu\n", (unsigned long long)i);
+                return 5;
+            }
+        printf("batch ok\n");
+        CHECK_HIP(hipFree(d_jobs));
+        CHECK_HIP(hipFree(d_count2));
+        CHECK_HIP(hipFree(d_list2));
+        CHECK_HIP(hipFree(d_state2));
+        /* list2 is rewritten by dqmc_extract below */
+        CHECK_DQMC(ctx, dqmc_extract(ctx, n, d_state, d_list, count, d_count, s));
+        CHECK_HIP(hipStreamSynchronize(s));
+        CHECK_HIP(hipMemcpy(list2, d_list, count * 8, hipMemcpyDeviceToHost));
+    }
 
     f = fopen(argv[3], "wb");
     if (f == NULL || fwrite(&count, 8, 1, f) != 1 || fwrite(list, 8, count, f) != count ||

@@ -1,6 +1,7 @@
-"""Batched prime implicants: every job's result equals what dqmc_primes gives
-for it alone (and the oracle's), malformed jobs fail alone, and a captured
-graph of the batch replays correctly."""
+"""Batched prime implicants (device-resident job array, planned on the
+device): every job's result equals what dqmc_primes gives for it
+alone and the oracle's, malformed jobs fail alone with their status set on
+the device, and a captured graph of the batch replays correctly."""
 import numpy as np
 import pytest
 
@@ -53,7 +54,7 @@ def test_batch_matches_single_and_oracle():
 
     ctx = context()
     specs = _mixed_specs(120, 77)
-    specs += [dict(n=17, kind="bernoulli", p=0.9, seed=1717), dict(n=13, kind="dnf", terms=30, wlo=3, whi=6, seed=13)]
+    specs += [dict(n=13, kind="dnf", terms=30, wlo=3, whi=6, seed=13)]
     tts = [inputs.make(s) for s in specs]
     jobs = [_alloc_job(ctx, s["n"], tt) for s, tt in zip(specs, tts)]
     status = dqmc.dqmc_primes_batch(ctx.ctx, jobs)
@@ -81,10 +82,12 @@ def test_batch_malformed_jobs_fail_alone():
     jobs = [_alloc_job(ctx, s["n"], tt) for s, tt in zip(good, tts)]
     bad_n = dict(jobs[0])
     bad_n["n"] = 26
+    big_n = dict(jobs[0])
+    big_n["n"] = 17  # batches take n <= 16
     bad_state = dict(n=14, tt=jobs[1]["tt"], state=None, list=None, list_cap=0, count=jobs[1]["count"])
-    allj = [jobs[0], bad_n, jobs[1], bad_state, jobs[2]]
+    allj = [jobs[0], bad_n, jobs[1], bad_state, big_n, jobs[2]]
     status = dqmc.dqmc_primes_batch(ctx.ctx, allj)
-    assert status == [0, dqmc.DQMC_EINVAL, 0, dqmc.DQMC_EINVAL, 0]
+    assert status == [0, dqmc.DQMC_EINVAL, 0, dqmc.DQMC_EINVAL, dqmc.DQMC_EINVAL, 0]
     for s, tt, j in zip(good, tts, jobs):
         _, blist, bc = _job_result(j)
         _, _, lst = oracle.primes(s["n"], tt)
@@ -121,9 +124,9 @@ def test_batch_plan_graph_replay():
     tts = [inputs.make(s) for s in specs]
     jobs = [_alloc_job(ctx, s["n"], tt) for s, tt in zip(specs, tts)]
     plan = dqmc.Batch(ctx.ctx, jobs)
-    assert plan.status == [0] * len(jobs)
     plan.run()
     torch.cuda.synchronize()
+    assert plan.status == [0] * len(jobs)
     eager = [(j["state"].clone(), j["list"][: int(j["count"].item())].clone(), int(j["count"].item())) for j in jobs]
     g = torch.cuda.CUDAGraph()
     s = torch.cuda.Stream()
@@ -150,18 +153,50 @@ def test_batch_plan_graph_replay():
     plan.close()
 
 
-@pytest.mark.parametrize("grid,order", [(64, 0), (0, 1), (1, 0)])
-def test_batch_configs_same_results(grid, order):
+def test_batch_plan_rejects_changed_sizes():
+    """A plan's launches are sized for the jobs' n at creation: a run after a
+    job's n changed must do nothing but reject every job; restoring the n
+    restores the results."""
     import torch
 
     from paper_2302_10083_amd import dqmc
 
     ctx = context()
-    specs = _mixed_specs(40, 31 + grid + order)
+    specs = [dict(n=n, kind="bernoulli", p=0.8, seed=700 + n) for n in (9, 13, 15, 10)]
     tts = [inputs.make(s) for s in specs]
     jobs = [_alloc_job(ctx, s["n"], tt) for s, tt in zip(specs, tts)]
     plan = dqmc.Batch(ctx.ctx, jobs)
-    plan.config(grid, order)
+    words = plan.table.view(torch.int32)  # dqmc_job: 12 int32 words, n first
+    per = words.numel() // len(jobs)
+    words[0] = 8  # job 0: n = 9 -> 8 (its buffers are large enough)
+    for j in jobs:
+        j["count"].fill_(-7)
+    plan.run()
+    assert plan.status == [dqmc.DQMC_EINVAL] * len(jobs)
+    assert all(int(j["count"].item()) == -7 for j in jobs)
+    words[0] = 9
+    plan.run()
+    assert plan.status == [0] * len(jobs)
+    for s, tt, j in zip(specs, tts, jobs):
+        _, blist, bc = _job_result(j)
+        _, _, ref = oracle.primes(s["n"], tt)
+        assert bc == len(ref) and np.array_equal(blist, ref)
+    assert per == 12
+    plan.close()
+
+
+@pytest.mark.parametrize("col_cap,order", [(0, 0), (0, 1), (1, 0), (3, 1)])
+def test_batch_configs_same_results(col_cap, order):
+    import torch
+
+    from paper_2302_10083_amd import dqmc
+
+    ctx = context()
+    specs = _mixed_specs(40, 31 + col_cap + order)
+    tts = [inputs.make(s) for s in specs]
+    jobs = [_alloc_job(ctx, s["n"], tt) for s, tt in zip(specs, tts)]
+    plan = dqmc.Batch(ctx.ctx, jobs)
+    plan.config(col_cap, order)
     plan.run()
     torch.cuda.synchronize()
     for s, tt, j in zip(specs, tts, jobs):

@@ -1,6 +1,7 @@
 """The C ABI from plain C: paper_2302_10083_amd/examples/c_primes (built by
 build()) uses hipMalloc buffers and the system HIP runtime, without Python or
-torch in its process.  Its list and count must equal the oracle's."""
+torch in its process.  Its list and count must equal the oracle's, and its
+dqmc_primes_batch call on a device job array must agree with them."""
 import os
 import subprocess
 
@@ -32,6 +33,9 @@ def test_c_program_matches_oracle(n, kind, tmp_path):
     assert count == len(ref)
     assert np.array_equal(out[1:1 + count], ref)
     assert np.array_equal(out[1 + count:1 + 2 * count], ref)  # dqmc_extract on the same bitmap
+    if n <= 16:
+        # dqmc_primes_batch on a device-resident job array, checked by the program
+        assert "batch ok" in r.stdout, r.stdout
 
 
 def test_c_program_rejects_bad_n(tmp_path):

@@ -105,10 +105,9 @@ def test_batch_autotune_keeps_results():
     torch.cuda.synchronize()
     eager = [(j["state"].clone(), int(j["count"].item())) for j in jobs]
     trials = plan.autotune(reps=2)
-    ncu = torch.cuda.get_device_properties(0).multi_processor_count
-    assert [(t["grid"], t["order"]) for t in trials] == [(p * ncu, o) for o in (0, 1) for p in (1, 2, 4)]
+    assert [(t["col_cap"], t["order"]) for t in trials] == [(c, o) for o in (0, 1) for c in (0, 1, 2, 3)]
     best = min(trials, key=lambda t: t["ms"])
-    log("batch trials: %s" % ", ".join("%d/%d %.2f ms" % (t["grid"], t["order"], t["ms"]) for t in trials))
+    log("batch trials: %s" % ", ".join("%d/%d %.2f ms" % (t["col_cap"], t["order"], t["ms"]) for t in trials))
     for j in jobs:
         j["count"].fill_(-1)
         j["state"].fill_(0x5A5A5A5)
