@@ -377,7 +377,7 @@ def bench_configs(ctx, n24_tt=None, n24_list=None, oracle_threads=0):
     return out
 
 
-def bench_serving(nreq=200, seed=25):
+def bench_serving(nreq=2000, seed=25):
     """Serving mix (n in {10,14,18,22,25} with weights .4/.3/.15/.1/.05):
     saturation throughput from a closed loop, then Poisson arrivals at 0.5 and
     0.8 of it; latency = completion - submission on the server's clock.  The
@@ -479,6 +479,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--tune-extra-groups", type=int, default=1,
                     help="pass plans with up to this many groups beyond the fewest are timed (autotuner)")
     ap.add_argument("--no-tune", action="store_true")
@@ -668,7 +669,7 @@ def main():
 
     if not args.no_serving:
         torch.cuda.empty_cache()
-        out["serving"] = bench_serving()
+        out["serving"] = bench_serving(args.serving_requests)
         sv = out["serving"]
         print("bench: serving saturation %.1f jobs/s; p99 %.1f ms at 0.8 of it" % (
             sv["saturation_jobs_per_s"], sv["lambda_0.8"]["p99_ms"]), file=sys.stderr, flush=True)

@@ -322,7 +322,9 @@ int dqmc_primes_batch(dqmc_ctx *ctx, dqmc_job *d_jobs, int32_t njobs, void *stre
  *     nothing runs (the budget is held by results not yet released).
  *   dqmc_server_release: frees a finished job's device memory.
  *   dqmc_server_read: copies a finished job's list (up to cap entries) into
- *     host memory and returns the number copied (negative on error).
+ *     host memory and returns the number copied (negative on error).  The
+ *     copy runs without the server's lock (scheduling goes on meanwhile); a
+ *     read and a release of the same job must not overlap.
  *   dqmc_server_destroy: waits for running jobs, drops jobs that are
  *     still queued, frees everything; no other call on the server may be
  *     in progress.

@@ -263,11 +263,18 @@ void scheduler(dqmc_server *s)
         for (auto *pool : {&s->big, &s->small})
             for (Slot &sl : *pool) {
                 if (!sl.busy) continue;
-                if (hipEventQuery(sl.ev) == hipSuccess) {
+                const hipError_t q = hipEventQuery(sl.ev);
+                if (q == hipSuccess) {
                     retire(s, sl);
                     retired = true;
-                } else {
+                } else if (q == hipErrorNotReady) {
                     any_running = true;
+                } else {
+                    // the slot's work failed: its jobs finish with an error
+                    // instead of waiting forever
+                    for (uint64_t id : sl.jobs) s->jobs[id].status = DQMC_EDEVICE;
+                    retire(s, sl);
+                    retired = true;
                 }
             }
         if (retired) s->cv_done.notify_all();
@@ -463,13 +470,20 @@ int dqmc_server_wait(dqmc_server *s, uint64_t id, dqmc_result *out)
 int64_t dqmc_server_read(dqmc_server *s, uint64_t id, uint64_t *h_list, uint64_t cap)
 {
     if (s == nullptr || (h_list == nullptr && cap > 0)) return DQMC_EINVAL;
-    std::lock_guard<std::mutex> g(s->mu);
-    auto it = s->jobs.find(id);
-    if (it == s->jobs.end() || it->second.phase != kDone) return DQMC_EINVAL;
-    const SJob &j = it->second;
-    uint64_t k = j.count < j.cap ? j.count : j.cap;
-    if (k > cap) k = cap;
-    if (k > 0 && hipMemcpy(h_list, j.d_list, k * 8, hipMemcpyDeviceToHost) != hipSuccess) return DQMC_EDEVICE;
+    const uint64_t *src = nullptr;
+    uint64_t k = 0;
+    {
+        // the scheduler needs the lock every round: hold it only to look the
+        // job up, not during the copy
+        std::lock_guard<std::mutex> g(s->mu);
+        auto it = s->jobs.find(id);
+        if (it == s->jobs.end() || it->second.phase != kDone) return DQMC_EINVAL;
+        const SJob &j = it->second;
+        k = j.count < j.cap ? j.count : j.cap;
+        if (k > cap) k = cap;
+        src = j.d_list;
+    }
+    if (k > 0 && hipMemcpy(h_list, src, k * 8, hipMemcpyDeviceToHost) != hipSuccess) return DQMC_EDEVICE;
     return (int64_t)k;
 }
 

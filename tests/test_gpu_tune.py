@@ -125,3 +125,22 @@ def test_batch_autotune_keeps_results():
             assert np.array_equal(jobs[i]["list"][:c].cpu().numpy(), ref)
     assert best["ms"] > 0
     plan.close()
+
+
+def test_set_plan_rejects_group_starting_above_digit_24():
+    """A group's lanes address its rows with 32-bit offsets: a group starting
+    at digit 25 (rows 8 * 3^19 words apart) is refused, at n = 25 with the
+    plan [6, 6, 1]; other plans of 25 digits are accepted."""
+    from paper_2302_10083_amd import dqmc
+
+    ctx = context()
+    try:
+        with pytest.raises(dqmc.DqmcError) as e:
+            dqmc.dqmc_set_plan(ctx.ctx, 25, [6, 6, 1])
+        assert e.value.code == dqmc.DQMC_EINVAL
+        with pytest.raises(dqmc.DqmcError):
+            dqmc.dqmc_set_plan(ctx.ctx, 25, [1, 6, 5, 1])
+        dqmc.dqmc_set_plan(ctx.ctx, 25, [6, 6, 1][::-1])  # [1, 6, 6]: top group starts at digit 20
+        assert dqmc.dqmc_get_plan(ctx.ctx, 25) == [1, 6, 6]
+    finally:
+        dqmc.dqmc_set_plan(ctx.ctx, 25, [])
