@@ -38,10 +38,15 @@ __device__ __forceinline__ void lds_group(uint32_t *t, uint32_t tw, uint32_t s)
                 if constexpr (!all_binary(c, K)) col[c * s] = x[c];
             });
         } else {
+            uint32_t any = 0;
             static_for<C>([&](auto ci) {
                 constexpr int c = decltype(ci)::value;
                 x[c] = col[c * s];
+                any |= x[c];
             });
+            // a Reduce only clears bits: columns that are zero in the whole
+            // wavefront stay as they are (most of a prime bitmap is zero)
+            if (__ballot(any != 0u) == 0) continue;
             reg_reduce<K>(x);
             static_for<C - 1>([&](auto ci) {
                 constexpr int c = decltype(ci)::value;
@@ -179,12 +184,13 @@ __device__ __forceinline__ void last_round_to_hbm(uint32_t *t, uint32_t *dst, ui
     const uint32_t q = threadIdx.x;
     uint32_t c = 0;
     if (q < S) {
-        uint32_t x[27];
+        uint32_t x[27], any = 0;
         static_for<27>([&](auto ci) {
             constexpr int k = decltype(ci)::value;
             x[k] = t[q + k * S];
+            any |= x[k];
         });
-        reg_reduce<3>(x);
+        if (__ballot(any != 0u) != 0) reg_reduce<3>(x);  // zero columns stay zero
         const uint32_t q0 = q & ~63u;  // first column of this wavefront
         const uint32_t q1 = q0 + 63u < S ? q0 + 63u : S - 1u;
         static_for<27>([&](auto ci) {
@@ -247,22 +253,35 @@ __device__ __forceinline__ void reduce_full_tile(uint32_t *t, uint32_t *tile, ui
         }
         // digit 6 first (the order of the reduced dimensions is free): the
         // runs with digit 6 = 0 or 1 lose what the * run holds; then digits
-        // 1..5 inside each block, one block at a time
+        // 1..5 inside each block, one block at a time.  A wavefront whose
+        // runs are all zero (most of a prime bitmap) skips the arithmetic.
+        uint4 *dst = reinterpret_cast<uint4 *>(t + 24 * q);
+        auto put = [&](const uint32_t(&b)[kBlockWords], int k) {
+            dst[2 * k] = make_uint4(b[0], b[1], b[2], b[3]);
+            dst[2 * k + 1] = make_uint4(b[4], b[5], b[6], b[7]);
+        };
+        uint32_t any = 0;
         static_for<kBlockWords>([&](auto wi) {
             constexpr int w = decltype(wi)::value;
-            b0[w] &= ~b2[w];
-            b1[w] &= ~b2[w];
+            any |= b0[w] | b1[w] | b2[w];
         });
-        uint4 *dst = reinterpret_cast<uint4 *>(t + 24 * q);
-        block_reduce(b0);
-        dst[0] = make_uint4(b0[0], b0[1], b0[2], b0[3]);
-        dst[1] = make_uint4(b0[4], b0[5], b0[6], b0[7]);
-        block_reduce(b1);
-        dst[2] = make_uint4(b1[0], b1[1], b1[2], b1[3]);
-        dst[3] = make_uint4(b1[4], b1[5], b1[6], b1[7]);
-        block_reduce(b2);
-        dst[4] = make_uint4(b2[0], b2[1], b2[2], b2[3]);
-        dst[5] = make_uint4(b2[4], b2[5], b2[6], b2[7]);
+        if (__ballot(any != 0u) != 0) {
+            static_for<kBlockWords>([&](auto wi) {
+                constexpr int w = decltype(wi)::value;
+                b0[w] &= ~b2[w];
+                b1[w] &= ~b2[w];
+            });
+            block_reduce(b0);
+            put(b0, 0);
+            block_reduce(b1);
+            put(b1, 1);
+            block_reduce(b2);
+            put(b2, 2);
+        } else {
+            put(b0, 0);
+            put(b1, 1);
+            put(b2, 2);
+        }
     }
     __syncthreads();
     lds_group<3, false>(t, kMaxTileWords, 3 * kBlockWords);  // digits 7..9
