@@ -174,7 +174,7 @@ def bench_batch(ctx, reps=5):
     b.record()
     torch.cuda.synchronize()
     ms_single = a.elapsed_time(b)
-    state_bytes = sum(32 * 3 ** max(s["n"] - 5, 0) for s in specs)
+    state_bytes = sum(4 * dqmc.dqmc_state_words(s["n"]) for s in specs)
     del g
     plan.close()
     return {"workload": "8192 functions, n uniform 6..16, half Bernoulli half DNF (seed 8192)",
@@ -262,10 +262,10 @@ def bench_sliced(ctx, workload="c3x_n26_dnf2000_noise", ts=((2, 1), (2, 3), (1, 
     ttd = ctx.tt_to_device(tt)
     count = torch.zeros(1, dtype=torch.int64, device=dev)
     out = {"workload": workload, "n": n, "cubes": 3**n, "truth_table": spec,
-           "single_state_GB": 32 * 3 ** (n - 5) / 1e9, "rows": []}
+           "single_state_GB": 4 * 17504 * 3 ** (n - 12) / 1e9, "rows": []}  # 3^(n-12) padded tile slots
     lst = None
     for t, nm in ts:
-        need = (1 + nm) * 4 * 3 ** (n - t - 3)
+        need = (1 + nm) * 4 * dqmc.dqmc_state_words(n - t)
         try:
             o = ctx.new_state(n - t)
             m = [ctx.new_state(n - t) for _ in range(nm)]

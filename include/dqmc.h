@@ -21,11 +21,16 @@
  *  state     the 3^n-bit cube bitmap in the "H5" block layout (the bottom
  *            layer of Sec. 4.2 with h = 5): dqmc_state_words(n) uint32 words,
  *            grouped in 256-bit blocks of 8 words; cube rho lives in block
- *            rho/243 at bit p = rho%243, i.e. bit p%32 of word
- *            8*(rho/243) + p/32.  For n < 5 there is one block and cube rho
- *            is bit rho of it.  Bits 243..255 of every block (bits >= 3^n for
- *            n < 5) are always 0.  The order of the words is increasing
- *            rho.  States must be 16-byte aligned (DQMC_EINVAL otherwise).
+ *            rho/243 at bit p = rho%243, i.e. bit p%32 of the logical word
+ *            W = 8*(rho/243) + p/32.  For n <= 12 W is the state word.  For
+ *            n > 12 the state is 3^(n-12) slots of 17504 words: a tile of
+ *            17496 words (the 2187 blocks of one value of digits 13..n)
+ *            followed by 8 words that are always 0, so W lies at word
+ *            (W/17496)*17504 + W%17496 (every slot starts on a 128-byte
+ *            line).  For n < 5 there is one block and cube rho is bit rho
+ *            of it.  Bits 243..255 of every block (bits >= 3^n for n < 5)
+ *            are always 0.  The order of the words is increasing rho.
+ *            States must be 16-byte aligned (DQMC_EINVAL otherwise).
  *  list      uint64 cube indices rho, strictly increasing.
  *  stream    a hipStream_t passed as void* (NULL = the null stream).
  *
@@ -81,7 +86,7 @@ const char *dqmc_last_error(const dqmc_ctx *ctx);
 /* Sizes (pure functions; 0 when n is out of range). */
 uint64_t dqmc_num_cubes(int n);    /* 3^n (Sec. 4.1: the state has one bit per cube) */
 uint64_t dqmc_tt_words(int n);     /* max(1, 2^(n-5)) uint32 words */
-uint64_t dqmc_state_words(int n);  /* 8 * 3^max(n-5, 0) uint32 words */
+uint64_t dqmc_state_words(int n);  /* 8 * 3^max(n-5, 0) uint32 words up to n = 12, 17504 * 3^(n-12) above */
 uint64_t dqmc_dense_words(int n);  /* ceil(3^n / 64) uint64 words */
 
 /* Implicant bitmap M (Sec. 4.1, Lemma on MergeAll/ReduceAll; computed by the

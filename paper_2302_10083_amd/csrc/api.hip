@@ -104,7 +104,15 @@ int check_common(dqmc_ctx *ctx, int n)
     return DQMC_OK;
 }
 
-double state_bytes(int n) { return 4.0 * kBlockWords * (double)pow3(n > 5 ? n - 5 : 0); }
+// Words of a state: 3^(n-5) blocks of 8 words up to n = 12 (one tile), then
+// 3^(n-12) tile slots of kTileStride words.
+uint64_t state_words_of(int n)
+{
+    if (n > kLowDigits) return (uint64_t)kTileStride * pow3(n - kLowDigits);
+    return kBlockWords * pow3(n > 5 ? n - 5 : 0);
+}
+
+double state_bytes(int n) { return 4.0 * (double)state_words_of(n); }
 
 // States are read in 16-byte pieces (the final low pass loads a run of three
 // blocks per thread as four-word vectors).
@@ -137,6 +145,7 @@ LowArgs low_args(dqmc_ctx *ctx, int n)
     a.n = n;
     a.lw = n <= 5 ? 0 : (n - 5 < 7 ? n - 5 : 7);
     a.tw = kBlockWords * (uint32_t)pow3(a.lw);
+    a.ts = n > kLowDigits ? kTileStride : a.tw;
     a.ntiles = n <= kLowDigits ? 1 : pow3(n - kLowDigits);
     a.counts = ctx->counts;
     a.chunkmap = ctx->chunkmap;
@@ -148,7 +157,7 @@ ColArgs col_args(uint32_t *state, int n, const Group &g, bool outer_binary)
 {
     ColArgs c{};
     c.state = state;
-    c.L = kBlockWords * pow3(g.g0 - 6);
+    c.L = (uint64_t)kTileStride * pow3(g.g0 - kLowDigits - 1);
     const uint64_t lanes = (uint64_t)col_lanes_per_block(g.gw);
     c.nlb = (c.L + lanes - 1) / lanes;
     const int od = n - (g.g0 + g.size() - 1);
@@ -217,7 +226,7 @@ int enqueue_scan_list(dqmc_ctx *ctx, int n, const uint32_t *state, uint64_t *lis
     // dependent, so only the summaries are in the model) and writes 8 bytes
     // per listed prime
     return run_pass(ctx, s, "list", n, a.ntiles * 4.0 * (3 + kMapWords), 8, [&] {
-        return launch_list(n, state, a.tw, a.ntiles, ctx->counts, ctx->chunkmap, ctx->offs, list, cap, s, rho0);
+        return launch_list(n, state, a.tw, a.ts, a.ntiles, ctx->counts, ctx->chunkmap, ctx->offs, list, cap, s, rho0);
     });
 }
 
@@ -260,15 +269,25 @@ int enqueue_split_state(dqmc_ctx *ctx, int n, const uint32_t *tt, uint32_t flip,
                         hipStream_t s);
 bool use_split(const dqmc_ctx *ctx, int n);
 
+// The low-pass arguments of an m-variable slice state; `slot`: the state is a
+// tile slot of a larger state (a third of a split of m + 1 = 13 variables),
+// written whole, its padding zero.
+LowArgs slice_low_args(dqmc_ctx *ctx, int m, bool slot)
+{
+    LowArgs a = low_args(ctx, m);
+    if (slot) a.ts = kTileStride;
+    return a;
+}
+
 // Primes of the m-variable function `tt` into `state`, with the summaries;
 // by the top-digit split where it is on for m, except inside a split (one
 // level only: the thirds' truth tables share one buffer).
 int enqueue_slice_primes(dqmc_ctx *ctx, int m, const uint32_t *tt, uint32_t *state, uint64_t tile0, hipStream_t s,
-                         bool allow_split = true)
+                         bool allow_split = true, bool slot = false)
 {
     if (allow_split && use_split(ctx, m)) return enqueue_split_state(ctx, m, tt, 0u, state, tile0, s);
     if (m <= kLowDigits) {
-        LowArgs a = low_args(ctx, m);
+        LowArgs a = slice_low_args(ctx, m, slot);
         a.tt = tt;
         a.state = state;
         const int rc = run_pass(ctx, s, "low_primes_tt", m, tt_bytes(m) + state_bytes(m), 0,
@@ -280,10 +299,11 @@ int enqueue_slice_primes(dqmc_ctx *ctx, int m, const uint32_t *tt, uint32_t *sta
 }
 
 // Implicants of the m-variable function `tt` into `state`.
-int enqueue_slice_implicants(dqmc_ctx *ctx, int m, const uint32_t *tt, uint32_t *state, hipStream_t s)
+int enqueue_slice_implicants(dqmc_ctx *ctx, int m, const uint32_t *tt, uint32_t *state, hipStream_t s,
+                             bool slot = false)
 {
     if (m <= kLowDigits) {
-        LowArgs a = low_args(ctx, m);
+        LowArgs a = slice_low_args(ctx, m, slot);
         a.tt = tt;
         a.state = state;
         return run_pass(ctx, s, "low_merge_tt", m, tt_bytes(m) + state_bytes(m), 0,
@@ -299,7 +319,7 @@ int enqueue_slice_filter(dqmc_ctx *ctx, int m, uint32_t *o, const uint32_t *mask
     // data dependent (only the marked chunks are read); the model counts the
     // summaries
     return run_pass(ctx, s, "andnot_map", m, la.ntiles * 8.0 * (1 + kMapWords), 0, [&] {
-        return launch_andnot_map(o, mask, ctx->counts + tile0, ctx->chunkmap + tile0 * kMapWords, la.ntiles, la.tw,
+        return launch_andnot_map(o, mask, ctx->counts + tile0, ctx->chunkmap + tile0 * kMapWords, la.ntiles, la.tw, la.ts,
                                  s);
     });
 }
@@ -325,15 +345,16 @@ int enqueue_split_state(dqmc_ctx *ctx, int n, const uint32_t *tt, uint32_t flip,
                         hipStream_t s)
 {
     const int m = n - 1;
-    const uint64_t third = dqmc_state_words(m), tiles = low_args(ctx, m).ntiles;
+    // a third is 3^(m-12) tile slots (one slot, with its padding, at m = 12)
+    const uint64_t third = (uint64_t)kTileStride * pow3(m - kLowDigits), tiles = low_args(ctx, m).ntiles;
     uint32_t *star = state + 2 * third;
     int rc = enqueue_slice_tt(ctx, m, tt, 0u, 1u, flip, ctx->split_tt, s);
-    if (rc == DQMC_OK) rc = enqueue_slice_implicants(ctx, m, ctx->split_tt, star, s);
+    if (rc == DQMC_OK) rc = enqueue_slice_implicants(ctx, m, ctx->split_tt, star, s, true);
     for (uint32_t a = 0; a < 3 && rc == DQMC_OK; ++a) {
         uint32_t *o = state + a * third;
         const uint64_t t0 = tile0 + a * tiles;
         rc = enqueue_slice_tt(ctx, m, tt, a == 1 ? 1u : 0u, a == 2 ? 1u : 0u, flip, ctx->split_tt, s);
-        if (rc == DQMC_OK) rc = enqueue_slice_primes(ctx, m, ctx->split_tt, o, t0, s, false);
+        if (rc == DQMC_OK) rc = enqueue_slice_primes(ctx, m, ctx->split_tt, o, t0, s, false, true);
         if (rc == DQMC_OK && a < 2) rc = enqueue_slice_filter(ctx, m, o, star, t0, s);
     }
     return rc;
@@ -429,10 +450,7 @@ extern "C" {
 
 uint64_t dqmc_num_cubes(int n) { return (n < 0 || n > DQMC_MAX_N) ? 0 : pow3(n); }
 uint64_t dqmc_tt_words(int n) { return (n < 0 || n > DQMC_MAX_N) ? 0 : (n <= 5 ? 1 : (1ull << (n - 5))); }
-uint64_t dqmc_state_words(int n)
-{
-    return (n < 0 || n > DQMC_MAX_N) ? 0 : kBlockWords * pow3(n > 5 ? n - 5 : 0);
-}
+uint64_t dqmc_state_words(int n) { return (n < 0 || n > DQMC_MAX_N) ? 0 : state_words_of(n); }
 uint64_t dqmc_dense_words(int n) { return (n < 0 || n > DQMC_MAX_N) ? 0 : (pow3(n) + 63) / 64; }
 
 int dqmc_create(int device, dqmc_ctx **out)

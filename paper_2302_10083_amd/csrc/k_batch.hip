@@ -29,8 +29,9 @@
 namespace dqmc {
 
 constexpr uint32_t kTileL = kTileWords;  // words spanned by digits 1..12
+constexpr uint32_t kSlot = kTileStride;  // words between tiles in a state (the tile and its padding)
 constexpr uint32_t kColThreads = 256;
-constexpr uint32_t kColBlocks = (kTileL + kColThreads - 1) / kColThreads;  // column items per job
+constexpr uint32_t kColBlocks = (kSlot + kColThreads - 1) / kColThreads;  // column items per job
 
 // Work-item segments (one per pass).
 enum BatchSeg : uint32_t {
@@ -224,22 +225,23 @@ __device__ void merge_tile(const dqmc_job &j, uint32_t idx, uint32_t *t)
     uint32_t tile = 0;
     for (int q = 0; q < h; ++q)
         if ((idx >> q) & 1u) tile += pow3u(q);
-    uint32_t *dst = j.state + (uint64_t)tile * kTileL;
-    for (uint32_t w = threadIdx.x; w < kTileL; w += blockDim.x) dst[w] = t[w];
+    uint32_t *dst = j.state + (uint64_t)tile * kSlot;
+    for (uint32_t w = threadIdx.x; w < kSlot; w += blockDim.x) dst[w] = w < kTileL ? t[w] : 0u;
 }
 
 // Column pass of a function with 13 <= n <= 16: the digits 13..n (GR of them)
-// are merged, then reduced, in registers for state words l + kTileL * c.  The
-// column is processed in three chunks over its top digit: chunk 2 (top digit
-// *) is the AND of chunks 0 and 1 on the binary inputs; every chunk is merged
-// and reduced over the lower digits; then chunks 0 and 1 are reduced against
-// chunk 2 (the order merge-top, merge-lower, reduce-lower, reduce-top).
+// are merged, then reduced, in registers for state words l + kSlot * c (l runs
+// over the whole slot: the padding words are 0 in every binary tile and stay
+// 0).  The column is processed in three chunks over its top digit: chunk 2
+// (top digit *) is the AND of chunks 0 and 1 on the binary inputs; every chunk
+// is merged and reduced over the lower digits; then chunks 0 and 1 are reduced
+// against chunk 2 (the order merge-top, merge-lower, reduce-lower, reduce-top).
 template <int GR>
 __device__ __forceinline__ void batch_column(uint32_t *state, uint32_t l)
 {
     constexpr int CC = (int)pow3(GR - 1);  // combinations of the lower digits
     constexpr int BC = 1 << (GR - 1);
-    if (l >= kTileL) return;
+    if (l >= kSlot) return;
     uint32_t bin[2 * BC];
     static_for<2 * BC>([&](auto bi) {
         constexpr int b = decltype(bi)::value;
@@ -248,7 +250,7 @@ __device__ __forceinline__ void batch_column(uint32_t *state, uint32_t l)
             for (int r = 0; r < GR; ++r, p *= 3) cc += ((b >> r) & 1) * p;
             return cc;
         }();
-        bin[b] = (state + (uint64_t)kTileL * c)[l];
+        bin[b] = (state + (uint64_t)kSlot * c)[l];
     });
     auto chunk = [&](uint32_t(&y)[CC], auto ki) {
         constexpr int k = decltype(ki)::value;
@@ -269,7 +271,7 @@ __device__ __forceinline__ void batch_column(uint32_t *state, uint32_t l)
     chunk(y2, std::integral_constant<int, 2>{});
     static_for<CC>([&](auto ji) {
         constexpr int j = decltype(ji)::value;
-        (state + (uint64_t)kTileL * (j + 2 * CC))[l] = y2[j];
+        (state + (uint64_t)kSlot * (j + 2 * CC))[l] = y2[j];
     });
     static_for<2>([&](auto ki) {
         constexpr int k = decltype(ki)::value;
@@ -277,7 +279,7 @@ __device__ __forceinline__ void batch_column(uint32_t *state, uint32_t l)
         chunk(y, ki);
         static_for<CC>([&](auto ji) {
             constexpr int j = decltype(ji)::value;
-            (state + (uint64_t)kTileL * (j + k * CC))[l] = y[j] & ~y2[j];
+            (state + (uint64_t)kSlot * (j + k * CC))[l] = y[j] & ~y2[j];
         });
     });
 }
@@ -343,7 +345,7 @@ void batch_reduce_kernel(const dqmc_job *jobs, BatchScratch s)
     __shared__ uint32_t red[2 * kMapWords + 1];  // the upper half is unused here
     const Item it = decode(hl, kSegReduce, blockIdx.x);
     const uint32_t tile = first_tile(hl, it) + it.idx;
-    reduce_full_tile<false>(t, jobs[s.order[it.pos]].state + (uint64_t)it.idx * kTileL, s.counts + tile,
+    reduce_full_tile<false>(t, jobs[s.order[it.pos]].state + (uint64_t)it.idx * kSlot, s.counts + tile,
                             s.chunkmap + (uint64_t)tile * kMapWords, red);
 }
 
@@ -385,7 +387,7 @@ __global__ __launch_bounds__(256) void batch_list_kernel(const dqmc_job *jobs, B
     const uint64_t off = s.offs[tile];
     const uint64_t cap = j.list != nullptr ? j.list_cap : 0;
     if (c == 0 || off >= cap) return;
-    list_tile(j.state + (uint64_t)it.idx * kTileL, kTileL, (uint64_t)it.idx * kTileL, off,
+    list_tile(j.state + (uint64_t)it.idx * kSlot, kTileL, (uint64_t)it.idx * kTileL, off,
               s.chunkmap + (uint64_t)tile * kMapWords, j.list, cap, nzs[wv]);
 }
 

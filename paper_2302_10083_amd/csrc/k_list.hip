@@ -113,6 +113,7 @@ struct ListArgs {
     uint64_t ntiles;
     uint64_t rho0;
     uint32_t tw;
+    uint32_t ts;
     int n;
 };
 
@@ -129,16 +130,16 @@ __global__ __launch_bounds__(kListThreads) void list_kernel(ListArgs a)
         const uint32_t c = a.counts[tile];
         const uint64_t off = a.offs[tile];
         if (c == 0 || off >= a.cap) continue;
-        list_tile(a.state + tile * a.tw, a.tw, tile * a.tw, off, a.chunkmap + tile * kMapWords, a.list, a.cap, nzs[wv],
+        list_tile(a.state + tile * a.ts, a.tw, tile * a.tw, off, a.chunkmap + tile * kMapWords, a.list, a.cap, nzs[wv],
                   a.rho0);
     }
 }
 
-hipError_t launch_list(int n, const uint32_t *state, uint32_t tw, uint64_t ntiles, const uint32_t *counts,
+hipError_t launch_list(int n, const uint32_t *state, uint32_t tw, uint32_t ts, uint64_t ntiles, const uint32_t *counts,
                        const uint32_t *chunkmap, const uint64_t *offs, uint64_t *list, uint64_t cap, hipStream_t s,
                        uint64_t rho0)
 {
-    ListArgs a{state, counts, chunkmap, offs, list, cap, ntiles, rho0, tw, n};
+    ListArgs a{state, counts, chunkmap, offs, list, cap, ntiles, rho0, tw, ts, n};
     // workgroups of four tile-waves, at most 32768 (grid-stride beyond): at
     // n = 24 the pass took 1.66 ms with 8192, 1.51 ms with 32768 and 1.57 ms
     // with one workgroup per four tiles

@@ -62,12 +62,15 @@ __global__ __launch_bounds__(low_threads<MODE>()) __attribute__((amdgpu_waves_pe
         for (int j = 0, nh = a.n - 12; j < nh; ++j)
             if ((bh >> j) & 1) tile += pow3(j);
         if constexpr (MODE == kLowMergeTT) {
-            uint32_t *dst = a.state + tile * a.tw;
-            for (uint32_t w = threadIdx.x; w < a.tw; w += blockDim.x) dst[w] = t[w];
+            // the whole slot: the tile and its zero padding
+            uint32_t *dst = a.state + tile * a.ts;
+            for (uint32_t w = threadIdx.x; w < a.ts; w += blockDim.x) dst[w] = w < a.tw ? t[w] : 0u;
         } else {
             lds_inblock_reduce(t, a.tw);
             lds_all_digits<false>(t, a.tw, a.lw);
-            for (uint32_t w = threadIdx.x; w < a.tw; w += blockDim.x) a.state[w] = t[w];
+            // the state (a.ts >= a.tw words: a tile slot with its padding
+            // when the state is a third of a split state)
+            for (uint32_t w = threadIdx.x; w < a.ts; w += blockDim.x) a.state[w] = w < a.tw ? t[w] : 0u;
             const uint64_t total = tile_list(t, a.tw, 0, a.list, a.cap, 0, sh);
             if (threadIdx.x == 0 && a.count != nullptr) *a.count = total;
         }
@@ -78,10 +81,10 @@ __global__ __launch_bounds__(low_threads<MODE>()) __attribute__((amdgpu_waves_pe
         // tile here is a full read of equal cost; the list pass and the batch
         // kernels, whose work per tile varies, keep round-robin tiles.
         const uint64_t tile = xcd_remap(blockIdx.x, gridDim.x);
-        const uint32_t *src = a.state + tile * a.tw;
+        const uint32_t *src = a.state + tile * a.ts;
         if constexpr (MODE == kLowReduceCount) {
             // always a full tile here (n > 12)
-            reduce_full_tile<true>(t, a.state + tile * a.tw, a.counts + tile, a.chunkmap + tile * kMapWords, red);
+            reduce_full_tile<true>(t, a.state + tile * a.ts, a.counts + tile, a.chunkmap + tile * kMapWords, red);
             return;
         } else {
             load_tile<THREADS>(t, src, a.tw);

@@ -40,10 +40,12 @@ hipError_t launch_fill_u32(uint32_t *p, uint64_t count, uint32_t value, hipStrea
 }
 
 // Output word j holds cubes 64j .. 64j+63.  Cube rho is bit rho % 243 of
-// block rho / 243, i.e. bit (rho % 243) % 32 of state word
-// 8 * (rho / 243) + (rho % 243) / 32; a run of cubes inside one word is
-// copied at once.
-__global__ void to_dense_kernel(const uint32_t *state, uint64_t *dense, uint64_t nwords, uint64_t ncubes)
+// block rho / 243, i.e. bit (rho % 243) % 32 of logical word
+// W = 8 * (rho / 243) + (rho % 243) / 32; with tile slots (padded) the word
+// lies at (W / kTileWords) * kTileStride + W % kTileWords.  A run of cubes
+// inside one word is copied at once.
+__global__ void to_dense_kernel(const uint32_t *state, uint64_t *dense, uint64_t nwords, uint64_t ncubes,
+                                int slots)
 {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < nwords; j += stride) {
@@ -56,7 +58,9 @@ __global__ void to_dense_kernel(const uint32_t *state, uint64_t *dense, uint64_t
             uint32_t take = 32u - b;
             if ((uint32_t)kBlockCubes - p < take) take = (uint32_t)kBlockCubes - p;
             if (rend - r < take) take = (uint32_t)(rend - r);
-            const uint64_t bits = ((uint64_t)state[kBlockWords * blk + (p >> 5)] >> b) & ((1ull << take) - 1ull);
+            const uint64_t W = kBlockWords * blk + (p >> 5);
+            const uint64_t mem = slots ? (W / kTileWords) * kTileStride + W % kTileWords : W;
+            const uint64_t bits = ((uint64_t)state[mem] >> b) & ((1ull << take) - 1ull);
             out |= bits << filled;
             filled += take;
             r += take;
@@ -68,7 +72,8 @@ __global__ void to_dense_kernel(const uint32_t *state, uint64_t *dense, uint64_t
 hipError_t launch_to_dense(int n, const uint32_t *state, uint64_t *dense, hipStream_t s)
 {
     const uint64_t ncubes = pow3(n), nwords = (ncubes + 63) / 64;
-    hipLaunchKernelGGL(to_dense_kernel, dim3(fill_grid(nwords)), dim3(256), 0, s, state, dense, nwords, ncubes);
+    hipLaunchKernelGGL(to_dense_kernel, dim3(fill_grid(nwords)), dim3(256), 0, s, state, dense, nwords, ncubes,
+                       n > 12 ? 1 : 0);
     return hipGetLastError();
 }
 

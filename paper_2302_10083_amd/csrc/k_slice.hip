@@ -67,7 +67,8 @@ constexpr int kAndNotThreads = 256;
 constexpr int kAndNotBatch = 8;
 
 __global__ __launch_bounds__(kAndNotThreads) void andnot_map_kernel(uint32_t *o, const uint32_t *mask,
-                                                                     uint32_t *counts, uint32_t *chunkmap, uint32_t tw)
+                                                                     uint32_t *counts, uint32_t *chunkmap, uint32_t tw,
+                                                                     uint32_t ts)
 {
     constexpr uint32_t NW = kAndNotThreads / 64;
     __shared__ uint32_t red[kMapWords + 1];
@@ -91,8 +92,8 @@ __global__ __launch_bounds__(kAndNotThreads) void andnot_map_kernel(uint32_t *o,
     }
     __syncthreads();
     const uint32_t total = nnz;
-    uint32_t *ot = o + tile * tw;
-    const uint32_t *mt = mask + tile * tw;
+    uint32_t *ot = o + tile * ts;
+    const uint32_t *mt = mask + tile * ts;
     uint32_t c = 0;
     for (uint32_t r0 = wv * kAndNotBatch; r0 < total; r0 += NW * kAndNotBatch) {
         uint32_t ov[kAndNotBatch], mv[kAndNotBatch];
@@ -122,10 +123,10 @@ __global__ __launch_bounds__(kAndNotThreads) void andnot_map_kernel(uint32_t *o,
 }
 
 hipError_t launch_andnot_map(uint32_t *o, const uint32_t *mask, uint32_t *counts, uint32_t *chunkmap, uint64_t ntiles,
-                             uint32_t tw, hipStream_t s)
+                             uint32_t tw, uint32_t ts, hipStream_t s)
 {
     hipLaunchKernelGGL(andnot_map_kernel, dim3((uint32_t)ntiles), dim3(kAndNotThreads), 0, s, o, mask, counts,
-                       chunkmap, tw);
+                       chunkmap, tw, ts);
     return hipGetLastError();
 }
 

@@ -18,6 +18,11 @@ enum LowMode : int {
 
 constexpr uint32_t kTileBlocks = 2187;            // 3^7 blocks: digits 6..12
 constexpr uint32_t kTileWords = 8 * kTileBlocks;  // 17496 words (69,984 bytes)
+// Memory slot of a tile in a state of n >= 13 variables: the tile's words
+// and 8 padding words that are always 0, so that the slot (70,016 bytes) is a
+// multiple of 128 bytes and every row of a column pass (rows lie a multiple
+// of the slot apart) starts on a 128-byte line.
+constexpr uint32_t kTileStride = kTileWords + 8;  // 17504 words
 
 // Per-tile summary written by kLowReduceCount / kLowCount: the number of set
 // bits, and a bitmap of the 64-word chunks that hold any set bit.
@@ -35,6 +40,7 @@ struct LowArgs {
     uint32_t *chunkmap; // per tile: kMapWords words, bit k = chunk k non-zero
     uint64_t ntiles;
     uint32_t tw;        // words per tile
+    uint32_t ts;        // words per tile slot in the state (kTileStride, or tw for one tile)
     int n;
     int lw;             // block digits inside a tile (tw = 8 * 3^lw)
     uint32_t flip;      // XOR applied to the truth-table words (~0u: complement)
@@ -54,7 +60,7 @@ uint64_t scan_scratch_words(uint64_t ntiles);  // size of `sums`
 // summaries and offsets (only chunks marked non-zero are read).
 // rho0 is added to every listed cube index (a slice's place in a larger
 // function).
-hipError_t launch_list(int n, const uint32_t *state, uint32_t tw, uint64_t ntiles, const uint32_t *counts,
+hipError_t launch_list(int n, const uint32_t *state, uint32_t tw, uint32_t ts, uint64_t ntiles, const uint32_t *counts,
                        const uint32_t *chunkmap, const uint64_t *offs, uint64_t *list, uint64_t cap, hipStream_t s,
                        uint64_t rho0 = 0);
 hipError_t launch_low(int mode, const LowArgs &a, uint64_t nblocks, hipStream_t s);
@@ -69,13 +75,13 @@ enum ColMode : int {
 };
 
 // Highest first digit of a group: a group starting at digit g0 has rows
-// L = 8 * 3^(g0-6) words apart, and lanes address a row with 32-bit offsets
-// (L < 2^32 up to g0 = 24).
+// L = kTileStride * 3^(g0-13) words apart, and lanes address a row with 32-bit
+// offsets (L < 2^32 up to g0 = 24: 3.1e9 words).
 constexpr int kMaxGroupStart = 24;
 
 struct ColArgs {
     uint32_t *state;
-    uint64_t L;          // 8 * 3^(g0-6): words spanned by digits 1..g0-1
+    uint64_t L;          // words spanned by digits 1..g0-1 (kTileStride * 3^(g0-13))
     uint64_t nlb;        // l-blocks
     uint64_t nouter;     // outer (above the group) combinations launched
     uint64_t nblocks;    // nlb * nouter
@@ -148,7 +154,7 @@ uint32_t batch_header_words();
 hipError_t launch_slice_tt(const uint32_t *tt, int m, uint32_t fixed, uint32_t stars, uint32_t flip, uint32_t *out,
                            hipStream_t s);
 hipError_t launch_andnot_map(uint32_t *o, const uint32_t *mask, uint32_t *counts, uint32_t *chunkmap, uint64_t ntiles,
-                             uint32_t tw, hipStream_t s);
+                             uint32_t tw, uint32_t ts, hipStream_t s);
 
 hipError_t launch_fill_u64(uint64_t *p, uint64_t count, uint64_t value, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint64_t count, uint32_t value, hipStream_t s);

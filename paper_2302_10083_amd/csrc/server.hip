@@ -52,7 +52,10 @@ uint64_t list_reserve(int n)
 }
 
 uint64_t tt_words_of(int n) { return n <= 5 ? 1 : (1ull << (n - 5)); }
-uint64_t state_words_of(int n) { return kBlockWords * pow3(n > 5 ? n - 5 : 0); }
+uint64_t state_words_of(int n)
+{
+    return n > 12 ? (uint64_t)kTileStride * pow3(n - 12) : kBlockWords * pow3(n > 5 ? n - 5 : 0);
+}
 
 uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
 

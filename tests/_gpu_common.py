@@ -20,13 +20,29 @@ def context():
     return dqmc.Context(0)
 
 
+TILE_WORDS = 8 * 3**7  # digits 1..12: 2187 blocks of 8 words
+SLOT_WORDS = TILE_WORDS + 8  # a tile and its 8 zero words, n > 12
+
+
+def state_words(n):
+    """Words of a state: 8 * 3^(n-5) up to n = 12, then 3^(n-12) slots."""
+    return SLOT_WORDS * 3 ** (n - 12) if n > 12 else 8 * 3 ** max(n - 5, 0)
+
+
 def h5_to_dense(n, state_u32):
     """Host conversion of a block state (uint32 words; cube rho at bit
-    rho % 243 of the 256-bit block rho // 243) into the exact 3^n-bit bitmap
+    rho % 243 of the 256-bit block rho // 243; for n > 12 the blocks of digits
+    13..n lie in slots of SLOT_WORDS words) into the exact 3^n-bit bitmap
     (uint64 words), written independently of the library's repack.  Checks
-    that every padding bit is 0."""
+    that every padding bit and word is 0."""
     N = 3**n
     w = np.ascontiguousarray(state_u32, dtype=np.uint32)
+    assert w.size == state_words(n)
+    if n > 12:
+        w = w.reshape(-1, SLOT_WORDS)
+        if np.any(w[:, TILE_WORDS:]):
+            raise AssertionError("slot padding words set")
+        w = np.ascontiguousarray(w[:, :TILE_WORDS]).reshape(-1)
     assert w.size % 8 == 0
     bits = np.unpackbits(w.view(np.uint8), bitorder="little").reshape(-1, 256)
     if np.any(bits[:, 243:]):
@@ -42,10 +58,14 @@ def h5_to_dense(n, state_u32):
     return buf.view(np.uint64)
 
 
-def word_and_bit(rho):
-    """State word and bit of cube rho (numpy or torch integer arrays)."""
+def word_and_bit(rho, n):
+    """State word and bit of cube rho in a state of n variables (numpy or
+    torch integer arrays)."""
     blk, p = rho // 243, rho % 243
-    return 8 * blk + p // 32, p % 32
+    w = 8 * blk + p // 32
+    if n > 12:
+        w = (w // TILE_WORDS) * SLOT_WORDS + w % TILE_WORDS
+    return w, p % 32
 
 
 def dev_to_u32(t):

@@ -37,10 +37,15 @@ def test_library_exports_every_declared_function():
 def test_sizes(n):
     assert dqmc.dqmc_num_cubes(n) == 3**n
     assert dqmc.dqmc_tt_words(n) == max(1, 2 ** (n - 5)) if n >= 5 else dqmc.dqmc_tt_words(n) == 1
-    assert dqmc.dqmc_state_words(n) == 8 * 3 ** max(n - 5, 0)
+    # one tile of 8-word blocks up to n = 12, then 3^(n-12) slots of the tile
+    # (17,496 words) and 8 zero words
+    assert dqmc.dqmc_state_words(n) == (17504 * 3 ** (n - 12) if n > 12 else 8 * 3 ** max(n - 5, 0))
+    if n > 12:
+        assert dqmc.dqmc_state_words(n) * 4 % 128 == 0  # slots start on 128-byte lines
     assert dqmc.dqmc_dense_words(n) == (3**n + 63) // 64
-    # every cube has a slot: 243 per 8-word block (or all of them in one block)
-    assert dqmc.dqmc_state_words(n) // 8 * 243 >= 3**n
+    # every cube has a place: 243 per 8-word block (or all of them in one block)
+    blocks = 2187 * 3 ** (n - 12) if n > 12 else dqmc.dqmc_state_words(n) // 8
+    assert blocks * 243 >= 3**n
 
 
 @pytest.mark.parametrize("n", [-1, 26, 100])

@@ -118,7 +118,7 @@ def test_negate_n24_equals_complemented_table():
     rng = np.random.default_rng(2424)
     rhos = rng.integers(0, 3**n, size=200_000, dtype=np.int64)
     r = torch.from_numpy(rhos).to(s1.device)
-    w, b = word_and_bit(r)
+    w, b = word_and_bit(r, n)
     got = (s1[w].to(torch.int64) >> b) & 1
     got = got.cpu().numpy().astype(bool)
     want, _ = oracle.sample(n, comp, rhos.astype(np.uint64), "prime")

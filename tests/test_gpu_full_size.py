@@ -21,7 +21,7 @@ def _bits_at(state, n, rhos):
     import torch
 
     r = torch.from_numpy(np.asarray(rhos, dtype=np.int64)).to(state.device)
-    w, b = word_and_bit(r)
+    w, b = word_and_bit(r, n)
     return ((state[w].to(torch.int64) >> b) & 1).cpu().numpy().astype(bool)
 
 

@@ -10,7 +10,7 @@ import pytest
 import oracle
 from paper_2302_10083_amd import inputs
 
-from _gpu_common import context, log
+from _gpu_common import context, log, state_words
 
 pytestmark = pytest.mark.gpu
 
@@ -22,7 +22,7 @@ def list_reserve(n):
 def footprint(n):
     tt = 1 if n <= 5 else 1 << (n - 5)
     a = lambda x: (x + 255) // 256 * 256
-    return a(32 * 3 ** max(n - 5, 0)) + a(8 * list_reserve(n)) + a(4 * tt) + 256
+    return a(4 * state_words(n)) + a(8 * list_reserve(n)) + a(4 * tt) + 256
 
 
 def _hash(ctx, addr, nwords):
@@ -58,7 +58,7 @@ def _served(srv, jid):
     r = srv.wait(jid)
     assert r["status"] == 0
     n = r["n"]
-    sw = 8 * 3 ** max(n - 5, 0)
+    sw = state_words(n)
     return r, (r["count"], _hash(ctx, r["state"], sw), _hash(ctx, r["list"], 2 * r["listed"]))
 
 
