@@ -8,10 +8,12 @@
 // is bit p % 32 of its word p / 32.  So the five lowest ternary digits are
 // inside a block (the bottom layer of Sec. 4.2 with h = 5: 243 of 256 bits
 // used, the paper's own AVX2 choice), and digit i >= 6 moves the block index
-// by 3^(i-6), i.e. the word index by 8 * 3^(i-6) (the top layer).  Bits
-// 243..255 of a block (bits 19..31 of its last word) are always 0.  For
-// n < 5 the state is one block holding bits 0..3^n-1.  Memory order is rho
-// order.
+// by 3^(i-6), i.e. the logical word index by 8 * 3^(i-6) (the top layer).
+// Bits 243..255 of a block (bits 19..31 of its last word) are always 0.  For
+// n < 5 the state is one block holding bits 0..3^n-1.  For n > 12 the blocks
+// of each value of digits 13..n (a tile of 3^7 blocks) sit in a slot of
+// kTileStride words whose last 8 words are 0, so digit i >= 13 moves the word
+// index by kTileStride * 3^(i-13).  Memory order is rho order.
 //
 // Merge (Sec. 4.1, Def. of Merge) for dimension i maps the triple of cubes
 // (s, t, u) with s_i = 0, t_i = 1, u_i = * and equal elsewhere to

@@ -342,7 +342,7 @@ void batch_reduce_kernel(const dqmc_job *jobs, BatchScratch s)
     const uint32_t nitems = hl[kHSegSize + kSegReduce];
     if (blockIdx.x >= nitems) return;
     extern __shared__ __align__(16) uint32_t t[];
-    __shared__ uint32_t red[2 * kMapWords + 1];  // the upper half is unused here
+    __shared__ uint32_t red[kRedWords];  // the chunk flags and list length are unused here
     const Item it = decode(hl, kSegReduce, blockIdx.x);
     const uint32_t tile = first_tile(hl, it) + it.idx;
     reduce_full_tile<false>(t, jobs[s.order[it.pos]].state + (uint64_t)it.idx * kSlot, s.counts + tile,

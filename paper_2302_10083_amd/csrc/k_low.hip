@@ -75,7 +75,7 @@ __global__ __launch_bounds__(low_threads<MODE>()) __attribute__((amdgpu_waves_pe
             if (threadIdx.x == 0 && a.count != nullptr) *a.count = total;
         }
     } else {
-        __shared__ uint32_t red[2 * kMapWords + 1];
+        __shared__ uint32_t red[kRedWords];
         // Consecutive tiles on one XCD, as in the column passes (n = 24, the
         // final reduce: 16.6 -> 14.6 ms against round-robin tiles).  Every
         // tile here is a full read of equal cost; the list pass and the batch
@@ -96,8 +96,8 @@ __global__ __launch_bounds__(low_threads<MODE>()) __attribute__((amdgpu_waves_pe
 
 static size_t low_lds_bytes(int mode, uint32_t tw)
 {
-    (void)mode;
-    return (size_t)tw * 4;
+    // the final reduce also lists the tile's non-zero blocks after the tile
+    return (size_t)tw * 4 + (mode == kLowReduceCount ? kBlockListBytes : 0);
 }
 
 hipError_t low_setup()
@@ -111,7 +111,8 @@ hipError_t low_setup()
                                  hipFuncAttributeMaxDynamicSharedMemorySize, bytes)) != hipSuccess)
         return e;
     if ((e = hipFuncSetAttribute((const void *)low_kernel<kLowReduceCount>,
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, bytes)) != hipSuccess)
+                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)low_lds_bytes(kLowReduceCount, kTileWords))) != hipSuccess)
         return e;
     return hipFuncSetAttribute((const void *)low_kernel<kLowCount>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes);

@@ -15,6 +15,11 @@ namespace dqmc {
 
 constexpr uint32_t kMaxTileWords = kTileWords;  // 17496
 constexpr uint32_t kTileTriples = kTileBlocks / 3;  // 729 runs of digit 6 = 0, 1, *
+// LDS words of a tile's reduce bookkeeping: set-bit count, map of non-zero
+// chunks, map of chunks non-zero as loaded, length of the non-zero block list
+constexpr uint32_t kRedWords = 2 * kMapWords + 2;
+// LDS bytes after the tile for the list of its non-zero blocks (uint16)
+constexpr uint32_t kBlockListBytes = (kTileBlocks * 2 + 15) / 16 * 16;
 
 // Apply Merge (MERGE) or Reduce to the K tile digits of every column of the
 // tile, the first of them at word stride s.
@@ -177,116 +182,230 @@ __device__ __forceinline__ void load_tile(uint32_t *t, const uint32_t *src, uint
 // only clears bits, so a wavefront's 64-word store is skipped when every
 // 64-word chunk it overlaps was zero as loaded (`innz`): those words are zero
 // already.
+// A wavefront's words of row k are q0 + 648k .. q0 + 648k + 63 (q0 a multiple
+// of 64), so they start at 8 (k mod 8) inside a chunk and lie in chunks c(k)
+// and c(k) + 1.  The store decision of every row is taken once per
+// wavefront (lane k decides row k, one ballot), and the chunk map is
+// gathered as two bits per row in scalar registers and written at the end by
+// lane k for row k.
 template <bool SKIP_ZERO>
 __device__ __forceinline__ void last_round_to_hbm(uint32_t *t, uint32_t *dst, uint32_t *red, const uint32_t *innz)
 {
     constexpr uint32_t S = kTileWords / 27;  // 648
-    const uint32_t q = threadIdx.x;
-    uint32_t c = 0;
-    if (q < S) {
-        uint32_t x[27], any = 0;
-        static_for<27>([&](auto ci) {
-            constexpr int k = decltype(ci)::value;
-            x[k] = t[q + k * S];
-            any |= x[k];
-        });
-        if (__ballot(any != 0u) != 0) reg_reduce<3>(x);  // zero columns stay zero
-        const uint32_t q0 = q & ~63u;  // first column of this wavefront
-        const uint32_t q1 = q0 + 63u < S ? q0 + 63u : S - 1u;
-        static_for<27>([&](auto ci) {
-            constexpr int k = decltype(ci)::value;
-            const uint32_t c0 = (q0 + k * S) / kChunkWords, c1 = (q1 + k * S) / kChunkWords;
-            if (!SKIP_ZERO || (((innz[c0 / 32] >> (c0 % 32)) | (innz[c1 / 32] >> (c1 % 32))) & 1u)) dst[q + k * S] = x[k];
-            c += __popc(x[k]);
-            if (x[k] != 0u) {
-                const uint32_t chunk = (q + k * S) / kChunkWords;
-                atomicOr(&red[1 + chunk / 32], 1u << (chunk % 32));
-            }
-        });
+    const uint32_t q = threadIdx.x, lane = lane_id();
+    const uint32_t q0 = __builtin_amdgcn_readfirstlane(q & ~63u);  // the wavefront's first column
+    if (q0 >= S) return;                                         // wave-uniform
+    const bool mine = q < S;                                     // the last wavefront holds 8 columns
+    const uint32_t qn = (S - q0 < 64 ? S - q0 : 64) - 1;         // its last column, relative
+    uint32_t x[27], any = 0;
+    static_for<27>([&](auto ci) {
+        constexpr int k = decltype(ci)::value;
+        x[k] = mine ? t[q + k * S] : 0u;
+        any |= x[k];
+    });
+    if (__ballot(any != 0u) != 0) reg_reduce<3>(x);  // zero columns stay zero
+    // row lk = lane (lanes 0..26): its chunks, and whether it is stored
+    const uint32_t lk = lane < 27u ? lane : 0u;
+    const uint32_t ck = (q0 + lk * S) / kChunkWords;
+    uint64_t rows = ~0ull;  // bit k: store row k
+    if constexpr (SKIP_ZERO) {
+        const uint32_t ce = (q0 + lk * S + qn) / kChunkWords;
+        const uint32_t f = (innz[ck / 32] >> (ck % 32)) | (innz[ce / 32] >> (ce % 32));
+        rows = __ballot(lane < 27u && (f & 1u) != 0u);
     }
+    uint64_t nzc = 0;  // bit 2k: chunk c(k) holds a set bit; bit 2k + 1: chunk c(k) + 1
+    uint32_t c = 0;
+    static_for<27>([&](auto ci) {
+        constexpr uint32_t k = decltype(ci)::value;
+        constexpr uint32_t split = 64 - 8 * (k % 8);  // lanes below it are in chunk c(k)
+        constexpr uint64_t lo = split >= 64 ? ~0ull : (1ull << split) - 1ull;
+        if (((rows >> k) & 1ull) && mine) dst[q + k * S] = x[k];
+        c += __popc(x[k]);
+        const uint64_t m = __ballot(x[k] != 0u);
+        nzc |= ((m & lo) != 0 ? 1ull : 0ull) << (2 * k);
+        nzc |= ((m & ~lo) != 0 ? 1ull : 0ull) << (2 * k + 1);
+    });
+    const uint32_t two = (uint32_t)(nzc >> (2 * lk)) & 3u;
+    if (lane < 27u && (two & 1u)) atomicOr(&red[1 + ck / 32], 1u << (ck % 32));
+    if (lane < 27u && (two & 2u)) atomicOr(&red[1 + (ck + 1) / 32], 1u << ((ck + 1) % 32));
     c = wave_sum32(c);
-    if (lane_id() == 0 && c != 0) atomicAdd(&red[0], c);
+    if (lane == 0 && c != 0) atomicAdd(&red[0], c);
+}
+
+// Run q of a full tile (q < 729): its three blocks with digit 6 = 0, 1, *,
+// 96 contiguous bytes of the tile in HBM (16-byte aligned).
+struct TileRun {
+    uint4 u[6];
+};
+
+__device__ __forceinline__ void load_run(TileRun &r, const uint32_t *tile, uint32_t q)
+{
+    const uint4 *src = reinterpret_cast<const uint4 *>(tile + 24 * q);
+    static_for<6>([&](auto ki) { r.u[decltype(ki)::value] = src[decltype(ki)::value]; });
+}
+
+// Run q as three blocks b[0..2] of eight words.
+__device__ __forceinline__ void unpack_run(const TileRun &r, uint32_t (&b0)[kBlockWords], uint32_t (&b1)[kBlockWords],
+                                           uint32_t (&b2)[kBlockWords])
+{
+    static_for<2>([&](auto hi) {
+        constexpr int h = decltype(hi)::value;
+        b0[4 * h] = r.u[h].x; b0[4 * h + 1] = r.u[h].y; b0[4 * h + 2] = r.u[h].z; b0[4 * h + 3] = r.u[h].w;
+        b1[4 * h] = r.u[2 + h].x; b1[4 * h + 1] = r.u[2 + h].y; b1[4 * h + 2] = r.u[2 + h].z;
+        b1[4 * h + 3] = r.u[2 + h].w;
+        b2[4 * h] = r.u[4 + h].x; b2[4 * h + 1] = r.u[4 + h].y; b2[4 * h + 2] = r.u[4 + h].z;
+        b2[4 * h + 3] = r.u[4 + h].w;
+    });
+}
+
+// Marks in `innz` the 64-word chunks in which run q holds a non-zero word.
+// The run's 24 words start at word 24q; 24q mod 64 repeats with period 8 in
+// q, and only runs with q mod 8 = 2 (blocks 0, 1 | 2) and q mod 8 = 5 (block
+// 0 | 1, 2) cross a chunk boundary, between two blocks.
+__device__ __forceinline__ void mark_run_chunks(const uint32_t (&b0)[kBlockWords], const uint32_t (&b1)[kBlockWords],
+                                                const uint32_t (&b2)[kBlockWords], uint32_t q, uint32_t *innz)
+{
+    uint32_t r0 = 0, r1 = 0, r2 = 0;
+    static_for<kBlockWords>([&](auto wi) {
+        constexpr uint32_t w = decltype(wi)::value;
+        r0 |= b0[w];
+        r1 |= b1[w];
+        r2 |= b2[w];
+    });
+    const uint32_t m8 = q % 8;
+    const uint32_t in0 = m8 == 2 ? (r0 | r1) : m8 == 5 ? r0 : (r0 | r1 | r2);
+    const uint32_t in1 = m8 == 2 ? r2 : m8 == 5 ? (r1 | r2) : 0u;
+    const uint32_t c0 = 24 * q / kChunkWords;
+    if (in0 != 0u) atomicOr(&innz[c0 / 32], 1u << (c0 % 32));
+    if (in1 != 0u) atomicOr(&innz[(c0 + 1) / 32], 1u << ((c0 + 1) % 32));
+}
+
+__device__ __forceinline__ void put_block(uint32_t *t, uint32_t blk, const uint32_t (&b)[kBlockWords])
+{
+    uint4 *dst = reinterpret_cast<uint4 *>(t + kBlockWords * blk);
+    dst[0] = make_uint4(b[0], b[1], b[2], b[3]);
+    dst[1] = make_uint4(b[4], b[5], b[6], b[7]);
+}
+
+// Reduce of digit 6 across the three blocks of run q and of digits 1..5
+// inside each block, into words 24q .. 24q+23 of the LDS tile.  Digit 6 comes
+// first (the order of the reduced dimensions is free): the blocks with digit
+// 6 = 0 or 1 lose what the * block holds.  A wavefront whose runs are all
+// zero skips the arithmetic.
+__device__ __forceinline__ void reduce_run_to_lds(uint32_t *t, const TileRun &r, uint32_t q)
+{
+    uint32_t b0[kBlockWords], b1[kBlockWords], b2[kBlockWords];
+    unpack_run(r, b0, b1, b2);
+    uint32_t any = 0;
+    static_for<kBlockWords>([&](auto wi) {
+        constexpr int w = decltype(wi)::value;
+        any |= b0[w] | b1[w] | b2[w];
+    });
+    if (__ballot(any != 0u) != 0) {
+        static_for<kBlockWords>([&](auto wi) {
+            constexpr int w = decltype(wi)::value;
+            b0[w] &= ~b2[w];
+            b1[w] &= ~b2[w];
+        });
+        block_reduce(b0);
+        put_block(t, 3 * q, b0);
+        block_reduce(b1);
+        put_block(t, 3 * q + 1, b1);
+        block_reduce(b2);
+        put_block(t, 3 * q + 2, b2);
+    } else {
+        put_block(t, 3 * q, b0);
+        put_block(t, 3 * q + 1, b1);
+        put_block(t, 3 * q + 2, b2);
+    }
+}
+
+// Reduce of digit 6 across the three blocks of run q into the LDS tile, the
+// chunk flags of the run as loaded, and the run's blocks that are non-zero
+// after it appended to `blist` (length *nlist).  Every thread of the
+// workgroup calls it (ballots); threads without a run pass has_run = false.
+__device__ __forceinline__ void run_digit6_to_lds(uint32_t *t, const TileRun &r, uint32_t q, bool has_run,
+                                                  uint32_t *innz, uint16_t *blist, uint32_t *nlist)
+{
+    uint32_t nzb = 0;  // bit k: block 3q + k is non-zero
+    if (has_run) {
+        uint32_t b0[kBlockWords], b1[kBlockWords], b2[kBlockWords];
+        unpack_run(r, b0, b1, b2);
+        mark_run_chunks(b0, b1, b2, q, innz);
+        uint32_t o0 = 0, o1 = 0, o2 = 0;
+        static_for<kBlockWords>([&](auto wi) {
+            constexpr int w = decltype(wi)::value;
+            b0[w] &= ~b2[w];
+            b1[w] &= ~b2[w];
+            o0 |= b0[w];
+            o1 |= b1[w];
+            o2 |= b2[w];
+        });
+        put_block(t, 3 * q, b0);
+        put_block(t, 3 * q + 1, b1);
+        put_block(t, 3 * q + 2, b2);
+        nzb = (o0 != 0u ? 1u : 0u) | (o1 != 0u ? 2u : 0u) | (o2 != 0u ? 4u : 0u);
+    }
+    const uint64_t m0 = __ballot(nzb & 1u), m1 = __ballot(nzb & 2u), m2 = __ballot(nzb & 4u);
+    const uint32_t c0 = (uint32_t)__popcll(m0), c1 = (uint32_t)__popcll(m1), c2 = (uint32_t)__popcll(m2);
+    if (c0 + c1 + c2 == 0) return;
+    uint32_t base = 0;
+    const uint32_t lane = lane_id();
+    if (lane == 0) base = atomicAdd(nlist, c0 + c1 + c2);
+    base = __shfl(base, 0, 64);
+    const uint64_t lt = (1ull << lane) - 1ull;  // lanes below this one
+    if (nzb & 1u) blist[base + (uint32_t)__popcll(m0 & lt)] = (uint16_t)(3 * q);
+    if (nzb & 2u) blist[base + c0 + (uint32_t)__popcll(m1 & lt)] = (uint16_t)(3 * q + 1);
+    if (nzb & 4u) blist[base + c0 + c1 + (uint32_t)__popcll(m2 & lt)] = (uint16_t)(3 * q + 2);
 }
 
 // Final Reduce of a full tile in HBM (kTileWords words at `tile`, 16-byte
-// aligned; 768 threads): thread q < 729 loads the three blocks of run q
-// (digit 6 = 0, 1, *; 96 contiguous bytes) and reduces digit 6 across them
-// and digits 1..5 inside each block on the way into LDS; digits 7..9 are
-// reduced in LDS; digits 10..12 in the last round straight back to HBM (the
-// prime bitmap).  It also writes the tile summary: *count = its set bits,
-// map[0..kMapWords) = its non-zero 64-word chunks.  `red` is
-// 2 * kMapWords + 1 words of LDS.  SKIP_ZERO leaves out the stores of chunks
-// that were zero as loaded (see last_round_to_hbm); it pays where most of the
-// tile is zero (a single large function) and costs more than it saves on the
-// small tiles of a batch.
-template <bool SKIP_ZERO>
+// aligned; 768 threads): thread q < 729 loads run q; digit 6 and digits 1..5
+// are reduced on the way into LDS, digits 7..9 in LDS, digits 10..12 in the
+// last round straight back to HBM (the prime bitmap).  It also writes the
+// tile summary: *count = its set bits, map[0..kMapWords) = its non-zero
+// 64-word chunks.  `red` is kRedWords words of LDS.
+// SPARSE is for a single large function, whose tiles are mostly zero by this
+// pass: the in-block reduce of digits 1..5 runs only on the blocks that are
+// non-zero after digit 6 (a Reduce leaves a zero block zero), taken from a
+// list that needs kBlockListBytes of LDS after the tile; and the stores of
+// chunks that were zero as loaded are left out (see last_round_to_hbm).  On
+// the denser small tiles of a batch both cost more than they save.
+template <bool SPARSE>
 __device__ __forceinline__ void reduce_full_tile(uint32_t *t, uint32_t *tile, uint32_t *count, uint32_t *map,
                                                  uint32_t *red)
 {
-    // red[kMapWords + 1 ..] holds the input-chunk flags
     uint32_t *innz = red + kMapWords + 1;
-    if (threadIdx.x < 2 * kMapWords + 1) red[threadIdx.x] = 0;
-    if constexpr (SKIP_ZERO) __syncthreads();  // flags zeroed before they are set
+    if (threadIdx.x < kRedWords) red[threadIdx.x] = 0;
     const uint32_t q = threadIdx.x;
-    if (q < kTileTriples) {
-        uint32_t b0[kBlockWords], b1[kBlockWords], b2[kBlockWords];
-        const uint4 *src = reinterpret_cast<const uint4 *>(tile + 24 * q);
-        const uint4 u0 = src[0], u1 = src[1], u2 = src[2], u3 = src[3], u4 = src[4], u5 = src[5];
-        b0[0] = u0.x; b0[1] = u0.y; b0[2] = u0.z; b0[3] = u0.w;
-        b0[4] = u1.x; b0[5] = u1.y; b0[6] = u1.z; b0[7] = u1.w;
-        b1[0] = u2.x; b1[1] = u2.y; b1[2] = u2.z; b1[3] = u2.w;
-        b1[4] = u3.x; b1[5] = u3.y; b1[6] = u3.z; b1[7] = u3.w;
-        b2[0] = u4.x; b2[1] = u4.y; b2[2] = u4.z; b2[3] = u4.w;
-        b2[4] = u5.x; b2[5] = u5.y; b2[6] = u5.z; b2[7] = u5.w;
-        if constexpr (SKIP_ZERO) {
-            // words 24q .. 24q+23 lie in at most two 64-word chunks
-            const uint32_t w0 = 24 * q, c0 = w0 / kChunkWords, c1 = (w0 + 23) / kChunkWords;
-            const uint32_t split = (c0 + 1) * kChunkWords - w0;  // words of the run in chunk c0
-            uint32_t nz0 = 0, nz1 = 0;
-            static_for<kBlockWords>([&](auto wi) {
-                constexpr uint32_t w = decltype(wi)::value;
-                nz0 |= (w < split ? b0[w] : 0u) | (w + 8 < split ? b1[w] : 0u) | (w + 16 < split ? b2[w] : 0u);
-                nz1 |= (w < split ? 0u : b0[w]) | (w + 8 < split ? 0u : b1[w]) | (w + 16 < split ? 0u : b2[w]);
-            });
-            if (nz0 != 0u) atomicOr(&innz[c0 / 32], 1u << (c0 % 32));
-            if (nz1 != 0u) atomicOr(&innz[c1 / 32], 1u << (c1 % 32));
+    if constexpr (SPARSE) {
+        uint16_t *blist = reinterpret_cast<uint16_t *>(t + kTileWords);
+        uint32_t *nlist = red + kRedWords - 1;
+        __syncthreads();  // flags and list length zeroed before they are set
+        TileRun r;
+        if (q < kTileTriples) load_run(r, tile, q);
+        run_digit6_to_lds(t, r, q, q < kTileTriples, innz, blist, nlist);
+        __syncthreads();
+        const uint32_t nb = *nlist;
+        for (uint32_t i = threadIdx.x; i < nb; i += blockDim.x) {
+            const uint32_t blk = blist[i];
+            const uint4 *src = reinterpret_cast<const uint4 *>(t + kBlockWords * blk);
+            const uint4 lo = src[0], hi = src[1];
+            uint32_t v[kBlockWords] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+            block_reduce(v);
+            put_block(t, blk, v);
         }
-        // digit 6 first (the order of the reduced dimensions is free): the
-        // runs with digit 6 = 0 or 1 lose what the * run holds; then digits
-        // 1..5 inside each block, one block at a time.  A wavefront whose
-        // runs are all zero (most of a prime bitmap) skips the arithmetic.
-        uint4 *dst = reinterpret_cast<uint4 *>(t + 24 * q);
-        auto put = [&](const uint32_t(&b)[kBlockWords], int k) {
-            dst[2 * k] = make_uint4(b[0], b[1], b[2], b[3]);
-            dst[2 * k + 1] = make_uint4(b[4], b[5], b[6], b[7]);
-        };
-        uint32_t any = 0;
-        static_for<kBlockWords>([&](auto wi) {
-            constexpr int w = decltype(wi)::value;
-            any |= b0[w] | b1[w] | b2[w];
-        });
-        if (__ballot(any != 0u) != 0) {
-            static_for<kBlockWords>([&](auto wi) {
-                constexpr int w = decltype(wi)::value;
-                b0[w] &= ~b2[w];
-                b1[w] &= ~b2[w];
-            });
-            block_reduce(b0);
-            put(b0, 0);
-            block_reduce(b1);
-            put(b1, 1);
-            block_reduce(b2);
-            put(b2, 2);
-        } else {
-            put(b0, 0);
-            put(b1, 1);
-            put(b2, 2);
+    } else {
+        if (q < kTileTriples) {
+            TileRun r;
+            load_run(r, tile, q);
+            reduce_run_to_lds(t, r, q);
         }
     }
     __syncthreads();
     lds_group<3, false>(t, kMaxTileWords, 3 * kBlockWords);  // digits 7..9
     __syncthreads();
-    last_round_to_hbm<SKIP_ZERO>(t, tile, red, innz);  // digits 10..12
+    last_round_to_hbm<SPARSE>(t, tile, red, innz);  // digits 10..12
     __syncthreads();
     if (threadIdx.x == 0) *count = red[0];
     if (threadIdx.x < kMapWords) map[threadIdx.x] = red[1 + threadIdx.x];
