@@ -438,7 +438,8 @@ hipError_t batch_setup()
         e = hipFuncSetAttribute((const void *)batch_col_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)col_cap_pad(1));
     if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void *)batch_reduce_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    return hipFuncSetAttribute((const void *)batch_reduce_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)kReduceTileBytes);
 }
 
 hipError_t launch_batch(void *jobs, uint32_t njobs, const BatchScratch &s, int col_cap, int mode, hipStream_t st,
@@ -468,7 +469,7 @@ hipError_t launch_batch(void *jobs, uint32_t njobs, const BatchScratch &s, int c
     hipLaunchKernelGGL(batch_plan_kernel, dim3(1), dim3(kPlanThreads), 0, st, j, njobs, s, e);
     hipLaunchKernelGGL(batch_tt_kernel, g(first), dim3(kBatchThreads), lds, st, j, s, mode == 0 ? 1 : 0);
     hipLaunchKernelGGL(batch_col_kernel, g(ncol), dim3(kColThreads), col_cap_pad(col_cap), st, j, s);
-    hipLaunchKernelGGL(batch_reduce_kernel, g(ntiles), dim3(kBatchThreads), lds, st, j, s);
+    hipLaunchKernelGGL(batch_reduce_kernel, g(ntiles), dim3(kBatchThreads), kReduceTileBytes, st, j, s);
     hipLaunchKernelGGL(batch_scan_kernel, dim3(ncu), dim3(256), 0, st, j, s);
     hipLaunchKernelGGL(batch_list_kernel, g((ntiles + 3) / 4), dim3(256), 0, st, j, s);
     return hipGetLastError();

@@ -96,8 +96,9 @@ __global__ __launch_bounds__(low_threads<MODE>()) __attribute__((amdgpu_waves_pe
 
 static size_t low_lds_bytes(int mode, uint32_t tw)
 {
-    // the final reduce also lists the tile's non-zero blocks after the tile
-    return (size_t)tw * 4 + (mode == kLowReduceCount ? kBlockListBytes : 0);
+    // the final reduce holds the tile with padded rows, then the list of its
+    // non-zero blocks
+    return mode == kLowReduceCount ? (size_t)kReduceTileBytes + kBlockListBytes : (size_t)tw * 4;
 }
 
 hipError_t low_setup()

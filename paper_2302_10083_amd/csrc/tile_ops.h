@@ -18,8 +18,20 @@ constexpr uint32_t kTileTriples = kTileBlocks / 3;  // 729 runs of digit 6 = 0, 
 // LDS words of a tile's reduce bookkeeping: set-bit count, map of non-zero
 // chunks, map of chunks non-zero as loaded, length of the non-zero block list
 constexpr uint32_t kRedWords = 2 * kMapWords + 2;
-// LDS bytes after the tile for the list of its non-zero blocks (uint16)
+// LDS layout of a full tile in the final reduce: its 27 rows of 648 words
+// (one value of digits 10..12 each) lie kRowStride words apart.  The round of
+// digits 7..9 has thread q read column q at words 648 (q / 24) + q % 24 + 24 c
+// (c < 27); with rows 664 (= 24 mod 32) words apart those words lie in bank
+// q + 24 c mod 32, so every 32 consecutive threads hit 32 different banks
+// (648 = 8 mod 32 would pair them two to a bank).
+constexpr uint32_t kRowWords = kTileWords / 27;                  // 648
+constexpr uint32_t kRowStride = kRowWords + 16;                 // 664
+constexpr uint32_t kPaddedTileWords = 27 * kRowStride;          // 17928
+__device__ __forceinline__ uint32_t padded_word(uint32_t w) { return w + 16 * (w / kRowWords); }
+// LDS bytes after the padded tile for the list of its non-zero blocks (uint16)
 constexpr uint32_t kBlockListBytes = (kTileBlocks * 2 + 15) / 16 * 16;
+// LDS bytes of the final reduce of a full tile (SPARSE adds the block list)
+constexpr uint32_t kReduceTileBytes = kPaddedTileWords * 4;
 
 // Apply Merge (MERGE) or Reduce to the K tile digits of every column of the
 // tile, the first of them at word stride s.
@@ -174,8 +186,9 @@ __device__ __forceinline__ void load_tile(uint32_t *t, const uint32_t *src, uint
     });
 }
 
-// Last Reduce round of a full tile (digits 10..12, word stride 648): thread q
-// owns column q, reduces it, and writes it to HBM (the prime bitmap);
+// Last Reduce round of a full tile (digits 10..12, rows of 648 words, padded
+// in LDS): thread q owns column q, reduces it, and writes it to HBM (the prime
+// bitmap);
 // consecutive threads write consecutive words.  It also builds the tile
 // summary in `red` (zeroed before): red[0] = set bits, red[1..] = map of the
 // non-zero 64-word chunks.  The tile is reduced in place in HBM and a Reduce
@@ -200,7 +213,7 @@ __device__ __forceinline__ void last_round_to_hbm(uint32_t *t, uint32_t *dst, ui
     uint32_t x[27], any = 0;
     static_for<27>([&](auto ci) {
         constexpr int k = decltype(ci)::value;
-        x[k] = mine ? t[q + k * S] : 0u;
+        x[k] = mine ? t[q + k * kRowStride] : 0u;
         any |= x[k];
     });
     if (__ballot(any != 0u) != 0) reg_reduce<3>(x);  // zero columns stay zero
@@ -280,15 +293,16 @@ __device__ __forceinline__ void mark_run_chunks(const uint32_t (&b0)[kBlockWords
     if (in1 != 0u) atomicOr(&innz[(c0 + 1) / 32], 1u << ((c0 + 1) % 32));
 }
 
+// Block blk of a padded LDS tile.
 __device__ __forceinline__ void put_block(uint32_t *t, uint32_t blk, const uint32_t (&b)[kBlockWords])
 {
-    uint4 *dst = reinterpret_cast<uint4 *>(t + kBlockWords * blk);
+    uint4 *dst = reinterpret_cast<uint4 *>(t + padded_word(kBlockWords * blk));
     dst[0] = make_uint4(b[0], b[1], b[2], b[3]);
     dst[1] = make_uint4(b[4], b[5], b[6], b[7]);
 }
 
 // Reduce of digit 6 across the three blocks of run q and of digits 1..5
-// inside each block, into words 24q .. 24q+23 of the LDS tile.  Digit 6 comes
+// inside each block, into blocks 3q .. 3q+2 of the padded LDS tile.  Digit 6 comes
 // first (the order of the reduced dimensions is free): the blocks with digit
 // 6 = 0 or 1 lose what the * block holds.  A wavefront whose runs are all
 // zero skips the arithmetic.
@@ -360,7 +374,8 @@ __device__ __forceinline__ void run_digit6_to_lds(uint32_t *t, const TileRun &r,
 }
 
 // Final Reduce of a full tile in HBM (kTileWords words at `tile`, 16-byte
-// aligned; 768 threads): thread q < 729 loads run q; digit 6 and digits 1..5
+// aligned; 768 threads; kReduceTileBytes of LDS at t, rows padded as
+// described at kRowStride): thread q < 729 loads run q; digit 6 and digits 1..5
 // are reduced on the way into LDS, digits 7..9 in LDS, digits 10..12 in the
 // last round straight back to HBM (the prime bitmap).  It also writes the
 // tile summary: *count = its set bits, map[0..kMapWords) = its non-zero
@@ -368,7 +383,7 @@ __device__ __forceinline__ void run_digit6_to_lds(uint32_t *t, const TileRun &r,
 // SPARSE is for a single large function, whose tiles are mostly zero by this
 // pass: the in-block reduce of digits 1..5 runs only on the blocks that are
 // non-zero after digit 6 (a Reduce leaves a zero block zero), taken from a
-// list that needs kBlockListBytes of LDS after the tile; and the stores of
+// list that needs kBlockListBytes of LDS after the padded tile; and the stores of
 // chunks that were zero as loaded are left out (see last_round_to_hbm).  On
 // the denser small tiles of a batch both cost more than they save.
 template <bool SPARSE>
@@ -379,7 +394,7 @@ __device__ __forceinline__ void reduce_full_tile(uint32_t *t, uint32_t *tile, ui
     if (threadIdx.x < kRedWords) red[threadIdx.x] = 0;
     const uint32_t q = threadIdx.x;
     if constexpr (SPARSE) {
-        uint16_t *blist = reinterpret_cast<uint16_t *>(t + kTileWords);
+        uint16_t *blist = reinterpret_cast<uint16_t *>(t + kPaddedTileWords);
         uint32_t *nlist = red + kRedWords - 1;
         __syncthreads();  // flags and list length zeroed before they are set
         TileRun r;
@@ -389,7 +404,7 @@ __device__ __forceinline__ void reduce_full_tile(uint32_t *t, uint32_t *tile, ui
         const uint32_t nb = *nlist;
         for (uint32_t i = threadIdx.x; i < nb; i += blockDim.x) {
             const uint32_t blk = blist[i];
-            const uint4 *src = reinterpret_cast<const uint4 *>(t + kBlockWords * blk);
+            const uint4 *src = reinterpret_cast<const uint4 *>(t + padded_word(kBlockWords * blk));
             const uint4 lo = src[0], hi = src[1];
             uint32_t v[kBlockWords] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
             block_reduce(v);
@@ -403,7 +418,22 @@ __device__ __forceinline__ void reduce_full_tile(uint32_t *t, uint32_t *tile, ui
         }
     }
     __syncthreads();
-    lds_group<3, false>(t, kMaxTileWords, 3 * kBlockWords);  // digits 7..9
+    // digits 7..9: column q < 648 of the padded tile (see kRowStride)
+    for (uint32_t q = threadIdx.x; q < kRowWords; q += blockDim.x) {
+        uint32_t *col = t + (q / 24) * kRowStride + q % 24;
+        uint32_t x[27], any = 0;
+        static_for<27>([&](auto ci) {
+            constexpr int c = decltype(ci)::value;
+            x[c] = col[24 * c];
+            any |= x[c];
+        });
+        if (__ballot(any != 0u) == 0) continue;  // zero columns stay zero
+        reg_reduce<3>(x);
+        static_for<26>([&](auto ci) {
+            constexpr int c = decltype(ci)::value;
+            col[24 * c] = x[c];
+        });
+    }
     __syncthreads();
     last_round_to_hbm<SPARSE>(t, tile, red, innz);  // digits 10..12
     __syncthreads();
