@@ -112,6 +112,30 @@ def cpu_baseline(n, tt, sub_n, threads):
     return 3**sub_n / det["total_s"], threads, det, sub_tt, lst
 
 
+BATCH_WORKLOAD = "8192_n6_16"
+SLOT_BYTES = 4 * 17504  # a tile of a state with n > 12 and its padding
+
+
+def batch_model_bytes(ns, counts):
+    """Algorithmic HBM bytes of one run of the batch launches, per job:
+    n <= 12 (one workgroup): the truth table, the state and the list;
+    13 <= n <= 16 (h = n - 12, 3^h tiles): the truth table, the 2^h binary
+    tiles written and read back, every slot written by the column pass, every
+    tile read and written by the final reduce, 40 B of summary per tile, the
+    scan's 12 B per tile and the list.  The list pass's reads of non-zero
+    chunks depend on the data and are not counted."""
+    total = 0
+    for n, c in zip(ns, counts):
+        tt = 4 * max(1, 2 ** (n - 5)) if n >= 5 else 4
+        if n <= 12:
+            total += tt + 4 * 8 * 3 ** max(n - 5, 0) + 8 * c + 8
+        else:
+            h = n - 12
+            total += (tt + 2 * 2**h * SLOT_BYTES + 3**h * SLOT_BYTES + 3**h * 2 * (SLOT_BYTES - 32)
+                      + 3**h * (40 + 12) + 8 * c + 8)
+    return total
+
+
 def bench_batch(ctx, reps=5):
     """Batched workload (8192 functions, n uniform 6..16): the graph-replayed
     batch plan (a device-resident job array, planned on the device) against
@@ -175,6 +199,8 @@ def bench_batch(ctx, reps=5):
     torch.cuda.synchronize()
     ms_single = a.elapsed_time(b)
     state_bytes = sum(4 * dqmc.dqmc_state_words(s["n"]) for s in specs)
+    model = batch_model_bytes([s["n"] for s in specs], [int(j["count"].item()) for j in jobs])
+    traffic = read_traffic("batch", BATCH_WORKLOAD)
     del g
     plan.close()
     return {"workload": "8192 functions, n uniform 6..16, half Bernoulli half DNF (seed 8192)",
@@ -183,6 +209,13 @@ def bench_batch(ctx, reps=5):
             "dqmc_primes_batch_call_ms": ms_call,
             "per_fn_launch_ms": ms_single, "per_fn_launch_fns_per_s": len(specs) / (ms_single / 1e3),
             "speedup_vs_per_fn_launch": ms_single / ms_batch, "graph_captured": True,
+            # byte model of one run (batch_model_bytes) and, when profiles/
+            # holds counters for these sources, the HBM bytes they measured
+            "roofline": {"bound": "hbm", "model_GB": model / 1e9, "model_GBps": model / (ms_batch / 1e3) / 1e9,
+                         "frac_model": model / (ms_batch / 1e3) / 1e9 / HBM_PEAK_GBPS,
+                         "traffic_GB": traffic / 1e9 if traffic else None,
+                         "traffic_GBps": traffic / (ms_batch / 1e3) / 1e9 if traffic else None,
+                         "frac_traffic": traffic / (ms_batch / 1e3) / 1e9 / HBM_PEAK_GBPS if traffic else None},
             "autotune": {"col_cap": best["col_cap"], "order": best["order"],
                          "trials": [[t["col_cap"], t["order"], round(t["ms"], 3)] for t in trials]}}
 

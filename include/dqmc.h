@@ -64,7 +64,8 @@ typedef enum {
     DQMC_EINVAL = -1,  /* bad argument (n out of range, NULL, bad size) */
     DQMC_ENOMEM = -2,  /* device allocation failed (context creation only) */
     DQMC_EDEVICE = -3, /* a HIP runtime call failed */
-    DQMC_ESCRATCH = -4 /* beyond the fixed scratch of dqmc_primes_noalloc */
+    DQMC_ESCRATCH = -4, /* beyond the fixed scratch of dqmc_primes_noalloc */
+    DQMC_EIO = -5       /* a tuning file could not be opened, read or written */
 } dqmc_status;
 
 typedef struct dqmc_ctx dqmc_ctx;
@@ -437,6 +438,28 @@ typedef struct {
 int dqmc_plan_autotune(dqmc_ctx *ctx, int n, const uint32_t *d_tt, uint32_t *d_state, uint64_t *d_count,
                        int32_t extra_groups, int32_t reps, void *stream, dqmc_plan_trial *trials, int32_t cap,
                        int32_t *ntrials);
+
+/* Tuning cache: a context's per-n settings (group plan and top-digit split)
+ * as a JSON file, so that what dqmc_plan_autotune chose on one machine is
+ * reused by later processes instead of timed again.  Entries are keyed by
+ * the device architecture (hipDeviceProp_t::gcnArchName), n and the setting:
+ *
+ *   {"format": "dqmc-tune-1", "arch": "gfx950:sramecc+:xnack-",
+ *    "plans": [{"n": 24, "groups": [6, 6], "split": -1}, ...]}
+ *
+ * groups = [] is the default plan, split is the dqmc_set_split mode.
+ * dqmc_tune_save writes every n (13..25) whose plan or split is not the
+ * default.  dqmc_tune_load applies every entry of a file written for the
+ * context's architecture, as dqmc_set_plan and dqmc_set_split would, and
+ * stores the number applied in *napplied (may be NULL); a file for another
+ * architecture applies nothing and returns DQMC_OK.  Whitespace and the
+ * order of keys are free; unknown keys are an error.  Errors: DQMC_EINVAL for
+ * NULL arguments, malformed JSON or an entry that dqmc_set_plan /
+ * dqmc_set_split would reject (nothing is applied then); DQMC_EIO when the
+ * file cannot be opened, read or written; DQMC_EDEVICE when the device's
+ * properties cannot be read. */
+int dqmc_tune_save(const dqmc_ctx *ctx, const char *path);
+int dqmc_tune_load(dqmc_ctx *ctx, const char *path, int32_t *napplied);
 
 /* ---------------------------------------------------------------------------
  * Diagnostics: per-pass device timing.

@@ -18,17 +18,18 @@
 //      level w-1 (the extra pass over the new implicants of Sec. 5);
 //   4. the unmarked entries of level w-1 are its prime implicants
 //      (Sec. 5, two-stage custom hash set: elements are marked, never removed).
-// The primes are finally converted to cube indices rho and sorted, so the
-// output is the same list as the dense path's.
+// The primes are finally converted to cube indices rho and sorted (a radix
+// sort of their own, below), so the output is the same list as the dense
+// path's.
 #include <stdio.h>
 
 #include <algorithm>
-#include <rocprim/device/device_radix_sort.hpp>
 #include <vector>
 
 #include "api_types.h"
 #include "dqmc.h"
 #include "h5.h"
+#include "launch.h"
 
 namespace dqmc {
 
@@ -247,6 +248,108 @@ __global__ __launch_bounds__(kSpThreads) void sp_to_rho_kernel(uint64_t *keys, u
     }
 }
 
+// LSD radix sort of 64-bit keys on their low end_bit bits, 8 bits per pass.
+// A pass counts the digits of every tile of kSortTile consecutive keys
+// (sort_hist_kernel, counts stored digit-major: all tiles' counts of digit 0,
+// then of digit 1, ...), scans the counts into output offsets with the
+// library's count scan, and moves every key to its digit's offset plus its
+// rank among the equal digits before it in the tile (sort_scatter_kernel).
+// Keys of equal digit keep their order, so after the passes over digits of
+// increasing weight the keys are sorted.
+constexpr int kSortThreads = 256;
+constexpr int kSortRounds = 8;                                 // keys per thread and tile
+constexpr uint64_t kSortTile = kSortThreads * kSortRounds;    // 2048 keys
+constexpr int kSortBins = 256;
+static_assert(kSortBins == kSortThreads, "one bin per thread");
+
+__global__ __launch_bounds__(kSortThreads) void sort_hist_kernel(const uint64_t *keys, uint64_t n, int shift,
+                                                                 uint32_t *counts, uint64_t ntiles)
+{
+    __shared__ uint32_t h[kSortBins];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const uint64_t t0 = (uint64_t)blockIdx.x * kSortTile;
+    for (int j = 0; j < kSortRounds; ++j) {
+        const uint64_t i = t0 + (uint64_t)j * kSortThreads + threadIdx.x;
+        if (i < n) atomicAdd(&h[(uint32_t)(keys[i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    counts[(uint64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
+}
+
+// Keys are taken in index order: round j, then wavefront, then lane.  In a
+// round, a lane's rank among the lanes of its wavefront with the same digit
+// comes from eight ballots (one per digit bit); the wavefronts' counts per
+// digit go through LDS.
+__global__ __launch_bounds__(kSortThreads) void sort_scatter_kernel(const uint64_t *keys, uint64_t *out, uint64_t n,
+                                                                    int shift, const uint64_t *offs, uint64_t ntiles)
+{
+    constexpr int W = kSortThreads / 64;
+    __shared__ uint64_t base[kSortBins];  // next output position of each digit
+    __shared__ uint32_t wc[W][kSortBins];  // this round: keys per wavefront and digit
+    const uint32_t wv = threadIdx.x / 64, lane = lane_id();
+    base[threadIdx.x] = offs[(uint64_t)threadIdx.x * ntiles + blockIdx.x];
+    const uint64_t t0 = (uint64_t)blockIdx.x * kSortTile;
+    const uint64_t below = (1ull << lane) - 1ull;
+    for (int j = 0; j < kSortRounds; ++j) {
+        for (int w = 0; w < W; ++w) wc[w][threadIdx.x] = 0;
+        __syncthreads();
+        const uint64_t i = t0 + (uint64_t)j * kSortThreads + threadIdx.x;
+        const bool live = i < n;
+        const uint64_t k = live ? keys[i] : 0ull;
+        const uint32_t d = (uint32_t)(k >> shift) & 255u;
+        uint64_t peers = __ballot(live);
+        for (int b = 0; b < 8; ++b) {
+            const uint64_t m = __ballot((d >> b) & 1u);
+            peers &= ((d >> b) & 1u) ? m : ~m;
+        }
+        const uint32_t rank = (uint32_t)__popcll(peers & below);
+        if (live && rank == 0) wc[wv][d] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        if (live) {
+            uint64_t pos = base[d] + rank;
+            for (uint32_t w = 0; w < wv; ++w) pos += wc[w][d];
+            out[pos] = k;
+        }
+        __syncthreads();
+        uint32_t add = 0;
+        for (int w = 0; w < W; ++w) add += wc[w][threadIdx.x];
+        base[threadIdx.x] += add;
+    }
+}
+
+// Scratch of sort_keys for n keys: the digit counts, their offsets and the
+// scan's block sums, each 256-byte aligned.
+static uint64_t sort_scratch_bytes(uint64_t n)
+{
+    auto a = [](uint64_t x) { return (x + 255) & ~uint64_t(255); };
+    const uint64_t nt = (n + kSortTile - 1) / kSortTile, m = (uint64_t)kSortBins * nt;
+    return a(4 * m) + a(8 * m) + a(8 * scan_scratch_words(m));
+}
+
+// Sorts keys[0..n) on bits 0..end_bit-1, using tmp (n keys) and `scratch`
+// (sort_scratch_bytes(n), 256-byte aligned); returns the buffer that holds
+// the sorted keys (keys or tmp), or nullptr on a launch error.
+static uint64_t *sort_keys(uint64_t *keys, uint64_t *tmp, uint64_t n, int end_bit, void *scratch, hipStream_t s)
+{
+    auto a = [](uint64_t x) { return (x + 255) & ~uint64_t(255); };
+    const uint64_t nt = (n + kSortTile - 1) / kSortTile, m = (uint64_t)kSortBins * nt;
+    uint32_t *counts = (uint32_t *)scratch;
+    uint64_t *offs = (uint64_t *)((uint8_t *)scratch + a(4 * m));
+    uint64_t *sums = (uint64_t *)((uint8_t *)scratch + a(4 * m) + a(8 * m));
+    uint64_t *src = keys, *dst = tmp;
+    for (int shift = 0; shift < end_bit; shift += 8) {
+        hipLaunchKernelGGL(sort_hist_kernel, dim3((uint32_t)nt), dim3(kSortThreads), 0, s, src, n, shift, counts, nt);
+        if (hipGetLastError() != hipSuccess) return nullptr;
+        if (launch_scan_counts(counts, m, offs, nullptr, sums, s, nullptr) != hipSuccess) return nullptr;
+        hipLaunchKernelGGL(sort_scatter_kernel, dim3((uint32_t)nt), dim3(kSortThreads), 0, s, src, dst, n, shift, offs,
+                           nt);
+        if (hipGetLastError() != hipSuccess) return nullptr;
+        std::swap(src, dst);
+    }
+    return src;
+}
+
 static uint32_t sp_grid(uint64_t items)
 {
     uint64_t g = (items + kSpThreads - 1) / kSpThreads;
@@ -292,14 +395,12 @@ uint64_t dqmc_sparse_workspace_bytes(int n, uint64_t max_level, uint64_t max_pri
     // dqmc_sparse_primes splits what follows its 4 KiB of counters and
     // alignment 3/8 : 3/8 : 1/4 into the two level regions (a list entry and
     // at most four set slots per implicant, 40 bytes) and the prime region
-    // (keys and their sorted copy, 16 bytes per prime); the sort's scratch
-    // reuses the level regions.
+    // (keys and the sort's second buffer, 16 bytes per prime); the sort's
+    // counts and offsets reuse the level regions.
     const uint64_t lv = std::max<uint64_t>(max_level, 1), np = std::max<uint64_t>(max_primes, 1);
-    size_t sort_tmp = 0;
-    (void)rocprim::radix_sort_keys(nullptr, sort_tmp, (uint64_t *)nullptr, (uint64_t *)nullptr, (size_t)np, 0, 64);
     const uint64_t for_levels = (40 * lv + 1024) * 8 / 3 + 8;
     const uint64_t for_primes = (16 * np + 1024) * 4 + 8;
-    const uint64_t for_sort = ((uint64_t)sort_tmp + 1024) * 4 / 3 + 8;
+    const uint64_t for_sort = (sort_scratch_bytes(np) + 1024) * 4 / 3 + 8;
     return 4096 + std::max(for_levels, std::max(for_primes, for_sort));
 }
 
@@ -422,21 +523,18 @@ int dqmc_sparse_primes(dqmc_ctx *ctx, int n, const uint32_t *d_tt, uint64_t *d_l
     // rho order
     if (np > 0) {
         hipLaunchKernelGGL(sp_to_rho_kernel, dim3(sp_grid(np)), dim3(kSpThreads), 0, s, pkeys, np, n);
-        size_t tmp_bytes = 0;
-        int end_bit = 1;
+        int end_bit = 1;  // rho < 3^n
         {
             uint64_t top = 1;
             for (int i = 0; i < n; ++i) top *= 3;
             while (end_bit < 64 && (1ull << end_bit) < top) ++end_bit;
         }
-        if (!hip_ok(rocprim::radix_sort_keys(nullptr, tmp_bytes, pkeys, psorted, (size_t)np, 0, end_bit, s)))
-            return sp_fail(ctx, DQMC_EDEVICE, "sort size query failed");
-        // the sort's scratch reuses the level regions (free by now)
-        if (tmp_bytes > 2 * region) return sp_fail(ctx, DQMC_ENOMEM, "workspace too small for the sort");
-        if (!hip_ok(rocprim::radix_sort_keys((void *)levA, tmp_bytes, pkeys, psorted, (size_t)np, 0, end_bit, s)))
-            return sp_fail(ctx, DQMC_EDEVICE, "sort failed");
+        // the sort's counts and offsets reuse the level regions (free by now)
+        if (sort_scratch_bytes(np) > 2 * region) return sp_fail(ctx, DQMC_ENOMEM, "workspace too small for the sort");
+        const uint64_t *sorted = sort_keys(pkeys, psorted, np, end_bit, (void *)levA, s);
+        if (sorted == nullptr) return sp_fail(ctx, DQMC_EDEVICE, "sort failed");
         const uint64_t k = std::min(np, d_list ? list_cap : 0);
-        if (k > 0 && !hip_ok(hipMemcpyAsync(d_list, psorted, k * 8, hipMemcpyDeviceToDevice, s)))
+        if (k > 0 && !hip_ok(hipMemcpyAsync(d_list, sorted, k * 8, hipMemcpyDeviceToDevice, s)))
             return sp_fail(ctx, DQMC_EDEVICE, "list copy failed");
     }
     uint64_t npv = np;

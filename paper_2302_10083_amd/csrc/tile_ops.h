@@ -231,7 +231,7 @@ __device__ __forceinline__ void last_round_to_hbm(uint32_t *t, uint32_t *dst, ui
     static_for<27>([&](auto ci) {
         constexpr uint32_t k = decltype(ci)::value;
         constexpr uint32_t split = 64 - 8 * (k % 8);  // lanes below it are in chunk c(k)
-        constexpr uint64_t lo = split >= 64 ? ~0ull : (1ull << split) - 1ull;
+        constexpr uint64_t lo = split >= 64 ? ~0ull : (1ull << (split & 63u)) - 1ull;
         if (((rows >> k) & 1ull) && mine) dst[q + k * S] = x[k];
         c += __popc(x[k]);
         const uint64_t m = __ballot(x[k] != 0u);

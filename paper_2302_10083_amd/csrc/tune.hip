@@ -4,8 +4,10 @@
 // buffers with HIP events on the caller's stream; the fastest is applied
 // through the public configuration calls (dqmc_batch_config, dqmc_set_plan).
 #include <stdio.h>
+#include <string.h>
 
 #include <algorithm>
+#include <string>
 #include <vector>
 
 #include "api_types.h"
@@ -72,6 +74,97 @@ void splits(int h, int k, std::vector<int> &cur, std::vector<std::vector<int>> &
         splits(h - s, k - 1, cur, out, limit);
         cur.pop_back();
     }
+}
+
+// Reader of the tuning file's JSON subset: objects, arrays, strings (escapes
+// \\ and \" only) and integers.
+struct JsonReader {
+    const char *p, *end;
+    bool ok = true;
+
+    void ws()
+    {
+        while (p < end && (*p == ' ' || *p == '\t' || *p == '\n' || *p == '\r')) ++p;
+    }
+    bool peek(char c)
+    {
+        ws();
+        return p < end && *p == c;
+    }
+    bool take(char c)
+    {
+        if (!peek(c)) return ok = false;
+        ++p;
+        return true;
+    }
+    bool str(std::string &out)
+    {
+        out.clear();
+        if (!take('"')) return false;
+        while (p < end && *p != '"') {
+            if (*p == '\\') {
+                if (++p >= end || (*p != '"' && *p != '\\')) return ok = false;
+            }
+            out.push_back(*p++);
+        }
+        if (p >= end) return ok = false;
+        ++p;
+        return true;
+    }
+    bool integer(long &v)
+    {
+        ws();
+        const char *q = p;
+        bool neg = false;
+        if (q < end && *q == '-') {
+            neg = true;
+            ++q;
+        }
+        if (q >= end || *q < '0' || *q > '9') return ok = false;
+        long x = 0;
+        while (q < end && *q >= '0' && *q <= '9') {
+            x = x * 10 + (*q++ - '0');
+            if (x > 1000000) return ok = false;
+        }
+        p = q;
+        v = neg ? -x : x;
+        return true;
+    }
+    // key-value pairs of an object: f(key) reads the value, false on error
+    template <typename F>
+    bool object(F &&f)
+    {
+        if (!take('{')) return false;
+        if (peek('}')) return take('}');
+        std::string key;
+        do {
+            if (!str(key) || !take(':') || !f(key)) return ok = false;
+        } while (peek(',') && take(','));
+        return take('}');
+    }
+    template <typename F>
+    bool array(F &&f)
+    {
+        if (!take('[')) return false;
+        if (peek(']')) return take(']');
+        do {
+            if (!f()) return ok = false;
+        } while (peek(',') && take(','));
+        return take(']');
+    }
+};
+
+struct TuneEntry {
+    long n = -1, split = -1;
+    std::vector<int32_t> groups;
+};
+
+int device_arch(const dqmc_ctx *ctx, std::string &arch)
+{
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, ctx->device) != hipSuccess) return DQMC_EDEVICE;
+    arch = prop.gcnArchName;
+    return DQMC_OK;
 }
 
 }  // namespace
@@ -187,6 +280,109 @@ int dqmc_plan_autotune(dqmc_ctx *ctx, int n, const uint32_t *d_tt, uint32_t *d_s
     ctx->split[n] = ms_split < best ? 1 : 0;
     std::vector<int32_t> win(cands[best_i].begin(), cands[best_i].end());
     return dqmc_set_plan(ctx, n, win.data(), (int)win.size());
+}
+
+int dqmc_tune_save(const dqmc_ctx *ctx, const char *path)
+{
+    if (ctx == nullptr || path == nullptr) return DQMC_EINVAL;
+    std::string arch;
+    if (device_arch(ctx, arch) != DQMC_OK) return DQMC_EDEVICE;
+    std::string out = "{\"format\": \"dqmc-tune-1\", \"arch\": \"";
+    for (char c : arch) {
+        if (c == '"' || c == '\\') out.push_back('\\');
+        out.push_back(c);
+    }
+    out += "\",\n \"plans\": [";
+    bool first = true;
+    for (int n = kLowDigits + 1; n <= DQMC_MAX_N; ++n) {
+        if (ctx->plan_len[n] == 0 && ctx->split[n] < 0) continue;
+        char buf[64];
+        snprintf(buf, sizeof(buf), "%s\n  {\"n\": %d, \"groups\": [", first ? "" : ",", n);
+        out += buf;
+        for (int g = 0; g < ctx->plan_len[n]; ++g) {
+            snprintf(buf, sizeof(buf), "%s%d", g ? ", " : "", ctx->plan[n][g]);
+            out += buf;
+        }
+        snprintf(buf, sizeof(buf), "], \"split\": %d}", ctx->split[n]);
+        out += buf;
+        first = false;
+    }
+    out += "]}\n";
+    FILE *f = fopen(path, "wb");
+    if (f == nullptr) return DQMC_EIO;
+    const bool ok = fwrite(out.data(), 1, out.size(), f) == out.size();
+    return (fclose(f) == 0 && ok) ? DQMC_OK : DQMC_EIO;
+}
+
+int dqmc_tune_load(dqmc_ctx *ctx, const char *path, int32_t *napplied)
+{
+    if (ctx == nullptr || path == nullptr) return DQMC_EINVAL;
+    if (napplied != nullptr) *napplied = 0;
+    FILE *f = fopen(path, "rb");
+    if (f == nullptr) return tune_fail(ctx, DQMC_EIO, "cannot open the tuning file");
+    std::string text;
+    char buf[4096];
+    size_t got;
+    while ((got = fread(buf, 1, sizeof(buf), f)) > 0) {
+        text.append(buf, got);
+        if (text.size() > (1u << 20)) break;
+    }
+    const bool read_ok = !ferror(f) && text.size() <= (1u << 20);
+    fclose(f);
+    if (!read_ok) return tune_fail(ctx, DQMC_EIO, "cannot read the tuning file");
+    JsonReader r{text.data(), text.data() + text.size()};
+    std::string format, arch;
+    std::vector<TuneEntry> entries;
+    r.object([&](const std::string &key) {
+        if (key == "format") return r.str(format);
+        if (key == "arch") return r.str(arch);
+        if (key != "plans") return false;
+        return r.array([&] {
+            TuneEntry e;
+            const bool ok = r.object([&](const std::string &k) {
+                if (k == "n") return r.integer(e.n);
+                if (k == "split") return r.integer(e.split);
+                if (k != "groups") return false;
+                return r.array([&] {
+                    long g;
+                    if (!r.integer(g)) return false;
+                    e.groups.push_back((int32_t)g);
+                    return e.groups.size() <= (size_t)DQMC_MAX_N;
+                });
+            });
+            entries.push_back(e);
+            return ok;
+        });
+    });
+    r.ws();
+    if (!r.ok || r.p != r.end || format != "dqmc-tune-1")
+        return tune_fail(ctx, DQMC_EINVAL, "malformed tuning file");
+    std::string mine;
+    if (device_arch(ctx, mine) != DQMC_OK) return tune_fail(ctx, DQMC_EDEVICE, "cannot read the device properties");
+    if (arch != mine) return DQMC_OK;  // written for another architecture
+    // apply all or nothing
+    int plan_len[DQMC_MAX_N + 1], split[DQMC_MAX_N + 1], plan[DQMC_MAX_N + 1][DQMC_MAX_N];
+    memcpy(plan_len, ctx->plan_len, sizeof(plan_len));
+    memcpy(split, ctx->split, sizeof(split));
+    memcpy(plan, ctx->plan, sizeof(plan));
+    int rc = DQMC_OK;
+    for (const TuneEntry &e : entries) {
+        if (e.n <= kLowDigits || e.n > DQMC_MAX_N) {
+            rc = tune_fail(ctx, DQMC_EINVAL, "tuning entry with n outside 13..25");
+            break;
+        }
+        rc = dqmc_set_plan(ctx, (int)e.n, e.groups.data(), (int)e.groups.size());
+        if (rc == DQMC_OK) rc = dqmc_set_split(ctx, (int)e.n, (int)e.split);
+        if (rc != DQMC_OK) break;
+    }
+    if (rc != DQMC_OK) {
+        memcpy(ctx->plan_len, plan_len, sizeof(plan_len));
+        memcpy(ctx->split, split, sizeof(split));
+        memcpy(ctx->plan, plan, sizeof(plan));
+        return rc;
+    }
+    if (napplied != nullptr) *napplied = (int32_t)entries.size();
+    return DQMC_OK;
 }
 
 }  // extern "C"

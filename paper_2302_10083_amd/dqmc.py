@@ -20,7 +20,7 @@ import threading
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdqmc.so")
 
-DQMC_OK, DQMC_EINVAL, DQMC_ENOMEM, DQMC_EDEVICE, DQMC_ESCRATCH = 0, -1, -2, -3, -4
+DQMC_OK, DQMC_EINVAL, DQMC_ENOMEM, DQMC_EDEVICE, DQMC_ESCRATCH, DQMC_EIO = 0, -1, -2, -3, -4, -5
 DQMC_MAX_N = 25
 
 _lib = None
@@ -142,6 +142,8 @@ def load():
             "dqmc_get_plan": (i32, [vp, i32, ctypes.POINTER(ctypes.c_int32), i32]),
             "dqmc_set_split": (i32, [vp, i32, i32]),
             "dqmc_get_split": (i32, [vp, i32]),
+            "dqmc_tune_save": (i32, [vp, ctypes.c_char_p]),
+            "dqmc_tune_load": (i32, [vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int32)]),
             "dqmc_profile_read": (i32, [vp, ctypes.POINTER(dqmc_pass_record), i32]),
             "dqmc_batch_autotune": (i32, [vp, ctypes.c_int32, vp, ctypes.POINTER(dqmc_batch_trial), ctypes.c_int32,
                                           ctypes.POINTER(ctypes.c_int32)]),
@@ -590,6 +592,20 @@ def dqmc_set_split(ctx, n: int, mode: int) -> None:
 
 def dqmc_get_split(ctx, n: int) -> bool:
     return load().dqmc_get_split(ctx, n) == 1
+
+
+def dqmc_tune_save(ctx, path: str) -> None:
+    """Write the context's non-default plans and split modes (JSON, keyed by
+    the device architecture and n)."""
+    _check(ctx, load().dqmc_tune_save(ctx, os.fsencode(path)))
+
+
+def dqmc_tune_load(ctx, path: str) -> int:
+    """Apply a tuning file written for this device's architecture; returns
+    the number of entries applied (0 for a file of another architecture)."""
+    k = ctypes.c_int32(0)
+    _check(ctx, load().dqmc_tune_load(ctx, os.fsencode(path), ctypes.byref(k)))
+    return int(k.value)
 
 
 def dqmc_profile(ctx, enable: bool) -> None:

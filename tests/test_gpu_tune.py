@@ -144,3 +144,69 @@ def test_set_plan_rejects_group_starting_above_digit_24():
         assert dqmc.dqmc_get_plan(ctx.ctx, 25) == [1, 6, 6]
     finally:
         dqmc.dqmc_set_plan(ctx.ctx, 25, [])
+
+
+def test_tune_cache_round_trip(tmp_path):
+    """dqmc_tune_save writes the non-default settings keyed by architecture
+    and n; dqmc_tune_load applies a file of this architecture all or nothing
+    and ignores one of another architecture."""
+    import json
+
+    import torch
+
+    from paper_2302_10083_amd import dqmc
+
+    ctx = context()
+    c = ctx.ctx
+    path = str(tmp_path / "tune.json")
+    want = {19: ([], 1), 20: ([1, 1, 6], -1), 22: ([6, 4], 0)}
+
+    def reset():
+        for n in range(13, 26):
+            dqmc.dqmc_set_plan(c, n, [])
+            dqmc.dqmc_set_split(c, n, -1)
+
+    def state():
+        return {n: (dqmc.dqmc_get_plan(c, n), dqmc.dqmc_get_split(c, n)) for n in range(13, 26)}
+
+    try:
+        reset()
+        default = state()
+        assert default[20][0] != [1, 1, 6] and default[22][0] != [6, 4]
+        for n, (g, sp) in want.items():
+            dqmc.dqmc_set_plan(c, n, g)
+            dqmc.dqmc_set_split(c, n, sp)
+        tuned = state()
+        dqmc.dqmc_tune_save(c, path)
+        doc = json.load(open(path))
+        assert doc["format"] == "dqmc-tune-1"
+        assert doc["arch"] == torch.cuda.get_device_properties(0).gcnArchName
+        assert {e["n"]: (e["groups"], e["split"]) for e in doc["plans"]} == {n: (g, sp) for n, (g, sp) in want.items()}
+        reset()
+        assert dqmc.dqmc_tune_load(c, path) == 3
+        assert state() == tuned
+        # another architecture: nothing applied
+        reset()
+        other = dict(doc, arch="gfx000")
+        json.dump(other, open(path, "w"))
+        assert dqmc.dqmc_tune_load(c, path) == 0
+        assert state() == default
+        # an invalid entry after a valid one: nothing applied
+        bad = dict(doc, plans=[{"n": 20, "groups": [2, 6], "split": 0}, {"n": 21, "groups": [4, 4], "split": 0}])
+        json.dump(bad, open(path, "w"))
+        with pytest.raises(dqmc.DqmcError) as e:
+            dqmc.dqmc_tune_load(c, path)
+        assert e.value.code == dqmc.DQMC_EINVAL
+        assert state() == default
+        # malformed JSON, an unknown key, a missing file
+        for text in ('{"format": "dqmc-tune-1", "arch": "x", "plans": [', '{"format": "dqmc-tune-1", "plans": [], "z": 1}'):
+            open(path, "w").write(text)
+            with pytest.raises(dqmc.DqmcError) as e:
+                dqmc.dqmc_tune_load(c, path)
+            assert e.value.code == dqmc.DQMC_EINVAL
+        with pytest.raises(dqmc.DqmcError) as e:
+            dqmc.dqmc_tune_load(c, str(tmp_path / "missing.json"))
+        assert e.value.code == dqmc.DQMC_EIO
+        assert state() == default
+    finally:
+        reset()
