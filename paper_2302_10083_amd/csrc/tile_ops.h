@@ -186,57 +186,68 @@ __device__ __forceinline__ void load_tile(uint32_t *t, const uint32_t *src, uint
     });
 }
 
+// Word 3 of a raw buffer resource on CDNA (gfx9 family): DATA_FORMAT = 4
+// (32 bit) in bits 15..18, every other field 0.
+constexpr int kRawBufferWord3 = 0x00020000;
+
 // Last Reduce round of a full tile (digits 10..12, rows of 648 words, padded
 // in LDS): thread q owns column q, reduces it, and writes it to HBM (the prime
-// bitmap);
-// consecutive threads write consecutive words.  It also builds the tile
-// summary in `red` (zeroed before): red[0] = set bits, red[1..] = map of the
-// non-zero 64-word chunks.  The tile is reduced in place in HBM and a Reduce
-// only clears bits, so a wavefront's 64-word store is skipped when every
-// 64-word chunk it overlaps was zero as loaded (`innz`): those words are zero
-// already.
+// bitmap); consecutive threads write consecutive words.  It also builds the
+// tile summary in `red` (zeroed before): red[0] = set bits, red[1..] = map of
+// the non-zero 64-word chunks.  The tile is reduced in place in HBM and a
+// Reduce only clears bits, so a wavefront's 64-word store is skipped when
+// every 64-word chunk it overlaps was zero as loaded (`innz`): those words are
+// zero already.
 // A wavefront's words of row k are q0 + 648k .. q0 + 648k + 63 (q0 a multiple
 // of 64), so they start at 8 (k mod 8) inside a chunk and lie in chunks c(k)
-// and c(k) + 1.  The store decision of every row is taken once per
-// wavefront (lane k decides row k, one ballot), and the chunk map is
-// gathered as two bits per row in scalar registers and written at the end by
-// lane k for row k.
+// and c(k) + 1.  Everything per row is wave-uniform: the store decisions are
+// taken once per wavefront (lane k decides row k, one ballot), the stores are
+// raw buffer stores with the row offset in a scalar register, and the chunk
+// map is gathered as two bits per row in scalar registers (work only for rows
+// with a set bit), written at the end by lane k for row k.
 template <bool SKIP_ZERO>
 __device__ __forceinline__ void last_round_to_hbm(uint32_t *t, uint32_t *dst, uint32_t *red, const uint32_t *innz)
 {
-    constexpr uint32_t S = kTileWords / 27;  // 648
+    constexpr uint32_t S = kRowWords;  // 648
     const uint32_t q = threadIdx.x, lane = lane_id();
     const uint32_t q0 = __builtin_amdgcn_readfirstlane(q & ~63u);  // the wavefront's first column
     if (q0 >= S) return;                                         // wave-uniform
     const bool mine = q < S;                                     // the last wavefront holds 8 columns
     const uint32_t qn = (S - q0 < 64 ? S - q0 : 64) - 1;         // its last column, relative
     uint32_t x[27], any = 0;
-    static_for<27>([&](auto ci) {
-        constexpr int k = decltype(ci)::value;
-        x[k] = mine ? t[q + k * kRowStride] : 0u;
-        any |= x[k];
-    });
+    // lanes past the last column read column q0's words and are zeroed
+    const uint32_t qc = mine ? q : q0;
+    static_for<27>([&](auto ci) { x[decltype(ci)::value] = t[qc + decltype(ci)::value * kRowStride]; });
+    if (q0 + 64 > S) static_for<27>([&](auto ci) { x[decltype(ci)::value] = mine ? x[decltype(ci)::value] : 0u; });
+    static_for<27>([&](auto ci) { any |= x[decltype(ci)::value]; });
     if (__ballot(any != 0u) != 0) reg_reduce<3>(x);  // zero columns stay zero
     // row lk = lane (lanes 0..26): its chunks, and whether it is stored
     const uint32_t lk = lane < 27u ? lane : 0u;
     const uint32_t ck = (q0 + lk * S) / kChunkWords;
-    uint64_t rows = ~0ull;  // bit k: store row k
+    uint32_t rows = ~0u;  // bit k: store row k
     if constexpr (SKIP_ZERO) {
         const uint32_t ce = (q0 + lk * S + qn) / kChunkWords;
         const uint32_t f = (innz[ck / 32] >> (ck % 32)) | (innz[ce / 32] >> (ce % 32));
-        rows = __ballot(lane < 27u && (f & 1u) != 0u);
+        rows = (uint32_t)__ballot(lane < 27u && (f & 1u) != 0u);
     }
+    // the tile's words in HBM as a raw buffer: row k at scalar offset 2592 k;
+    // lanes past the last column get an offset beyond the tile, so their
+    // stores are dropped by the buffer's range check
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(dst, 0, (int)(kTileWords * 4), kRawBufferWord3);
+    const int voff = mine ? (int)(4 * q) : 0x40000000;
     uint64_t nzc = 0;  // bit 2k: chunk c(k) holds a set bit; bit 2k + 1: chunk c(k) + 1
     uint32_t c = 0;
     static_for<27>([&](auto ci) {
         constexpr uint32_t k = decltype(ci)::value;
         constexpr uint32_t split = 64 - 8 * (k % 8);  // lanes below it are in chunk c(k)
         constexpr uint64_t lo = split >= 64 ? ~0ull : (1ull << (split & 63u)) - 1ull;
-        if (((rows >> k) & 1ull) && mine) dst[q + k * S] = x[k];
+        if ((rows >> k) & 1u) __builtin_amdgcn_raw_buffer_store_b32(x[k], rs, voff, (int)(4 * k * S), 0);
         c += __popc(x[k]);
         const uint64_t m = __ballot(x[k] != 0u);
-        nzc |= ((m & lo) != 0 ? 1ull : 0ull) << (2 * k);
-        nzc |= ((m & ~lo) != 0 ? 1ull : 0ull) << (2 * k + 1);
+        if (m != 0) {
+            nzc |= ((m & lo) != 0 ? 1ull : 0ull) << (2 * k);
+            nzc |= ((m & ~lo) != 0 ? 1ull : 0ull) << (2 * k + 1);
+        }
     });
     const uint32_t two = (uint32_t)(nzc >> (2 * lk)) & 3u;
     if (lane < 27u && (two & 1u)) atomicOr(&red[1 + ck / 32], 1u << (ck % 32));
