@@ -20,6 +20,27 @@ __device__ __forceinline__ int star_slot(int cw)
     return k;
 }
 
+// The next row of a column: rows are L words apart, and a column's rows are
+// visited in order, so each costs one 64-bit scalar add.  The empty asm keeps
+// the compiler from rewriting the chain into products c * L (a 64-bit
+// multiply of a runtime value per row).
+// The walk runs on a global-address-space pointer, so that the accesses stay
+// global loads and stores (scalar base + lane offset), not flat ones.
+typedef __attribute__((address_space(1))) uint32_t global_u32;
+
+__device__ __forceinline__ global_u32 *next_row(global_u32 *row, uint64_t L)
+{
+    row += L;
+    asm volatile("" : "+s"(row));
+    return row;
+}
+
+// Word of a row at byte offset off (32 bits: scalar base + lane offset).
+__device__ __forceinline__ global_u32 &row_word(global_u32 *row, uint32_t off)
+{
+    return *(global_u32 *)((__attribute__((address_space(1))) char *)row + off);
+}
+
 template <int GW>
 __host__ __device__ constexpr int col_threads()
 {

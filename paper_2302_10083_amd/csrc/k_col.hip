@@ -92,8 +92,9 @@ __global__ __launch_bounds__(col_threads<GW>()) void col_kernel(ColArgs a)
     constexpr int XSZ = XM > XR ? XM : XR;
     __shared__ uint32_t xch[XSZ];
 
-    const uint64_t logical = xcd_remap(blockIdx.x, a.nblocks);
-    const uint64_t lb = logical % a.nlb, ob = logical / a.nlb;
+    // grids stay below 2^32 workgroups: 32-bit division
+    const uint32_t logical = (uint32_t)xcd_remap(blockIdx.x, a.nblocks), nlb = (uint32_t)a.nlb;
+    const uint32_t lb = logical % nlb, ob = logical / nlb;
     uint64_t o = ob;
     if (a.outer_binary) {
         o = 0;
@@ -105,11 +106,11 @@ __global__ __launch_bounds__(col_threads<GW>()) void col_kernel(ColArgs a)
     const int cw = GW == 0 ? 0 : __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64));
     const uint32_t lane = GW == 0 ? threadIdx.x : (threadIdx.x & 63);
     const uint64_t L = a.L;
-    const uint64_t l64 = lb * LANES + lane;
+    const uint64_t l64 = (uint64_t)lb * LANES + lane;
     const bool active = l64 < L;
     const uint32_t l = (uint32_t)l64;  // L < 2^32: plans keep g0 <= 24
+    const uint32_t l4 = 4 * l;          // byte offset in a row (rows of the lanes' blocks are below 2^32 bytes)
     uint32_t *rows = a.state + L * (uint64_t)CR * ((uint64_t)cw + (uint64_t)CW * o);
-#define ROW(c) (rows + (uint64_t)(c) * L)
 
     uint32_t x[CR];
     bool cw_binary = true;
@@ -122,9 +123,11 @@ __global__ __launch_bounds__(col_threads<GW>()) void col_kernel(ColArgs a)
         // 1. binary cubes of the group come from earlier passes
         static_for<CR>([&](auto ci) { x[decltype(ci)::value] = 0u; });
         if (cw_binary && active) {
+            global_u32 *row = (global_u32 *)rows;
             static_for<CR>([&](auto ci) {
                 constexpr int c = decltype(ci)::value;
-                if constexpr (all_binary(c, GR)) x[c] = ROW(c)[l];
+                if constexpr (all_binary(c, GR)) x[c] = row_word(row, l4);
+                row = next_row(row, L);
             });
         }
         // 2. wave digits: u = s AND t across wavefronts (on binary cr only)
@@ -161,24 +164,30 @@ __global__ __launch_bounds__(col_threads<GW>()) void col_kernel(ColArgs a)
             // one branch per wave kind, none per row: per-row conditions on
             // cw_binary let the compiler merge stores of different rows into
             // one indexed load, which moves x to scratch memory
+            global_u32 *row = (global_u32 *)rows;
             if (active && cw_binary) {
                 static_for<CR>([&](auto ci) {
                     constexpr int c = decltype(ci)::value;
-                    if constexpr (!all_binary(c, GR)) ROW(c)[l] = x[c];
+                    if constexpr (!all_binary(c, GR)) row_word(row, l4) = x[c];
+                    row = next_row(row, L);
                 });
             } else if (active) {
                 static_for<CR>([&](auto ci) {
-                    constexpr int c = decltype(ci)::value;
-                    ROW(c)[l] = x[c];
+                    row_word(row, l4) = x[decltype(ci)::value];
+                    row = next_row(row, L);
                 });
             }
             return;
         }
     } else {
-        static_for<CR>([&](auto ci) {
-            constexpr int c = decltype(ci)::value;
-            x[c] = active ? ROW(c)[l] : 0u;
-        });
+        static_for<CR>([&](auto ci) { x[decltype(ci)::value] = 0u; });
+        if (active) {
+            global_u32 *row = (global_u32 *)rows;
+            static_for<CR>([&](auto ci) {
+                x[decltype(ci)::value] = row_word(row, l4);
+                row = next_row(row, L);
+            });
+        }
     }
     // Reduce-only mode works in place and only clears bits: a row whose 64
     // words are all zero as loaded stays zero and is not stored again.
@@ -233,16 +242,16 @@ __global__ __launch_bounds__(col_threads<GW>()) void col_kernel(ColArgs a)
         reg_reduce<GR>(x);
         if (active) {
             const bool cw_allstar = (GW == 0) || (cw == CW - 1);
+            global_u32 *row = (global_u32 *)rows;
             static_for<CR>([&](auto ci) {
                 constexpr int c = decltype(ci)::value;
                 if (MODE == kColMergeReduce || (!(cw_allstar && c == CR - 1) && ((live[c / 32] >> (c % 32)) & 1u)))
-                    ROW(c)[l] = x[c];
+                    row_word(row, l4) = x[c];
+                row = next_row(row, L);
             });
         }
     }
 }
-
-#undef ROW
 
 int col_lanes_per_block(int gw) { return gw == 0 ? 256 : 64; }
 

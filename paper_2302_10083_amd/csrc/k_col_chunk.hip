@@ -37,7 +37,8 @@ __global__ __launch_bounds__(col_threads<GW>()) void col_chunk_kernel(ColArgs a)
     __shared__ uint32_t xch[XSZ];
 
     const uint64_t logical = xcd_remap(blockIdx.x, a.nblocks);
-    const uint64_t lb = logical % a.nlb, ob = logical / a.nlb;
+    // grids stay below 2^32 workgroups: 32-bit division
+    const uint32_t lb = (uint32_t)logical % (uint32_t)a.nlb, ob = (uint32_t)logical / (uint32_t)a.nlb;
     uint64_t o = ob;
     if (a.outer_binary) {
         o = 0;
@@ -49,11 +50,13 @@ __global__ __launch_bounds__(col_threads<GW>()) void col_chunk_kernel(ColArgs a)
     const int cw = GW == 0 ? 0 : __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64));
     const uint32_t lane = GW == 0 ? threadIdx.x : (threadIdx.x & 63);
     const uint64_t L = a.L;
-    const uint64_t l64 = lb * LANES + lane;
+    const uint64_t l64 = (uint64_t)lb * LANES + lane;
     const bool active = l64 < L;
     const uint32_t l = (uint32_t)l64;  // L < 2^32: plans keep g0 <= 24
+    const uint32_t l4 = 4 * l;          // byte offset in a row
     uint32_t *rows = a.state + L * (uint64_t)CR * ((uint64_t)cw + (uint64_t)CW * o);
-#define ROW(c) (rows + (uint64_t)(c) * L)
+    // first row of chunk k (register combinations CC k .. CC k + CC - 1)
+    auto chunk_rows = [&](int k) { return (global_u32 *)(rows + (uint64_t)(CC * k) * L); };
 
     bool cw_binary = true;
     if constexpr (GW > 0) {
@@ -72,7 +75,7 @@ __global__ __launch_bounds__(col_threads<GW>()) void col_chunk_kernel(ColArgs a)
                 for (int r = 0; r < GR; ++r, p *= 3) cc += ((b >> r) & 1) * p;
                 return cc;
             }();
-            bin[b] = (cw_binary && active) ? ROW(c)[l] : 0u;
+            bin[b] = (cw_binary && active) ? row_word((global_u32 *)(rows + (uint64_t)c * L), l4) : 0u;
         });
         // wave digits: u = s AND t across wavefronts, on the binary inputs
         if constexpr (GW > 0) {
@@ -129,9 +132,12 @@ __global__ __launch_bounds__(col_threads<GW>()) void col_chunk_kernel(ColArgs a)
     };
     auto load_chunk = [&](uint32_t(&y)[CC], auto ki) {
         constexpr int k = decltype(ki)::value;
+        static_for<CC>([&](auto ji) { y[decltype(ji)::value] = 0u; });
+        if (!active) return;
+        global_u32 *row = chunk_rows(k);
         static_for<CC>([&](auto ji) {
-            constexpr int j = decltype(ji)::value;
-            y[j] = active ? ROW(j + CC * k)[l] : 0u;
+            y[decltype(ji)::value] = row_word(row, l4);
+            row = next_row(row, L);
         });
     };
     // Wave digits of the group: every binary wave digit kills with the star
@@ -162,11 +168,13 @@ __global__ __launch_bounds__(col_threads<GW>()) void col_chunk_kernel(ColArgs a)
     auto store_chunk = [&](const uint32_t(&y)[CC], auto ki, bool skip_binary, bool skip_allstar) {
         constexpr int k = decltype(ki)::value;
         if (!active) return;
+        global_u32 *row = chunk_rows(k);
         static_for<CC>([&](auto ji) {
             constexpr int j = decltype(ji)::value;
             const bool bin_combo = k < 2 && all_binary(j, GR - 1);
             const bool star_combo = k == 2 && j == CC - 1;
-            if (!(skip_binary && bin_combo) && !(skip_allstar && star_combo)) ROW(j + CC * k)[l] = y[j];
+            if (!(skip_binary && bin_combo) && !(skip_allstar && star_combo)) row_word(row, l4) = y[j];
+            row = next_row(row, L);
         });
     };
     constexpr std::integral_constant<int, 0> K0{};
@@ -207,8 +215,6 @@ __global__ __launch_bounds__(col_threads<GW>()) void col_chunk_kernel(ColArgs a)
         });
     }
 }
-
-#undef ROW
 
 // Dynamic LDS per mode for the four-register-digit groups (the large ones),
 // set by chunk_setup to cap the workgroups per CU.  Measured at n = 25
