@@ -75,8 +75,11 @@ __device__ __forceinline__ void reduce_by_sibling(uint32_t (&x)[pow3(GR)], const
     });
 }
 
+// The reduce-only mode holds two workgroups of 3^GW waves per CU (its LDS
+// exchange allows two), so its registers are capped for five waves per SIMD.
 template <int GR, int GW, int MODE>
-__global__ __launch_bounds__(col_threads<GW>()) void col_kernel(ColArgs a)
+__global__ __launch_bounds__(col_threads<GW>())
+__attribute__((amdgpu_waves_per_eu(MODE == kColReduce && GW == 2 ? 5 : 1))) void col_kernel(ColArgs a)
 {
     constexpr int CR = (int)pow3(GR);
     constexpr int CW = (int)pow3(GW);
@@ -88,7 +91,8 @@ __global__ __launch_bounds__(col_threads<GW>()) void col_kernel(ColArgs a)
     // LDS: merge exchange of binary waves' binary combos; the reduce-only
     // mode exchanges the star waves' full columns
     constexpr int XM = GW > 0 ? BW * BR * 64 : 1;
-    constexpr int XR = (GW > 0 && !NEED_MERGE) ? (CW - BW) * CR * 64 : 1;
+    // (one wave digit per round: the 3^(GW-1) waves whose digit r is *)
+    constexpr int XR = (GW > 0 && !NEED_MERGE) ? (int)pow3(GW - 1) * CR * 64 : 1;
     constexpr int XSZ = XM > XR ? XM : XR;
     __shared__ uint32_t xch[XSZ];
 
@@ -219,23 +223,29 @@ __global__ __launch_bounds__(col_threads<GW>()) void col_kernel(ColArgs a)
                 reduce_by_sibling<GR, GW>(x, xch, binary_cover<GW>(sib), lane);
             }
         } else if constexpr (GW > 0) {
-            if (!cw_binary) {
-                const int ss = star_slot<GW>(cw);
-                static_for<CR>([&](auto ci) {
-                    constexpr int c = decltype(ci)::value;
-                    xch[(ss * CR + c) * 64 + lane] = x[c];
-                });
-            }
-            __syncthreads();
-            int cc = cw, p = 1;
-            for (int r = 0; r < GW; ++r, cc /= 3, p *= 3) {
-                const int d = cc % 3;
-                if (d == 2) continue;
-                const int ss = star_slot<GW>(cw + (2 - d) * p);  // star neighbour in digit r
-                static_for<CR>([&](auto ci) {
-                    constexpr int c = decltype(ci)::value;
-                    x[c] &= ~xch[(ss * CR + c) * 64 + lane];
-                });
+            // Reduce only: one wave digit per round.  The waves whose digit r
+            // is * put their rows in LDS, the others clear what their star
+            // neighbour holds.  Later rounds see the values earlier rounds
+            // left (the dimensions reduced one after another, Alg. 3).
+            int p = 1;
+            for (int r = 0; r < GW; ++r, p *= 3) {
+                const int d = (cw / p) % 3;
+                // index of this wave among those with the same digits except r
+                const int other = (cw / (p * 3)) * p + cw % p;
+                if (r > 0) __syncthreads();  // the previous round's readers are done
+                if (d == 2) {
+                    static_for<CR>([&](auto ci) {
+                        constexpr int c = decltype(ci)::value;
+                        xch[(other * CR + c) * 64 + lane] = x[c];
+                    });
+                }
+                __syncthreads();
+                if (d != 2) {
+                    static_for<CR>([&](auto ci) {
+                        constexpr int c = decltype(ci)::value;
+                        x[c] &= ~xch[(other * CR + c) * 64 + lane];
+                    });
+                }
             }
         }
         // 5. register digits, one after another
