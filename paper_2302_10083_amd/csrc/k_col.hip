@@ -199,7 +199,11 @@ __attribute__((amdgpu_waves_per_eu(MODE == kColReduce && GW == 2 ? 5 : 1))) void
     if constexpr (!NEED_MERGE) {
         static_for<CR>([&](auto ci) {
             constexpr int c = decltype(ci)::value;
-            if (__ballot(x[c] != 0u) != 0) live[c / 32] |= 1u << (c % 32);
+            // packed now (a scalar word): otherwise the 81 ballots stay
+            // live in scalar registers until the stores and spill
+            live[c / 32] = __builtin_amdgcn_readfirstlane(live[c / 32] |
+                                                          (__ballot(x[c] != 0u) != 0 ? 1u << (c % 32) : 0u));
+            asm volatile("" : "+s"(live[c / 32]));
         });
     }
 
