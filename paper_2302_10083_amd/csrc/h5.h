@@ -212,16 +212,40 @@ __device__ __forceinline__ void reg_merge(uint32_t (&x)[pow3(K)])
     });
 }
 
-// Reduce of K dimensions on a register column, one dimension after another.
+// Number of digits of combination c (base 3, k digits) that are 2 (*).
+__host__ __device__ constexpr int star_count(int c, int k)
+{
+    int s = 0;
+    for (int r = 0; r < k; ++r) s += tdigit(c, r) == 2 ? 1 : 0;
+    return s;
+}
+
+// Reduce of K dimensions on a register column in one step (the Lemma of
+// Sec. 4.1 applied to the K dimensions): combination c loses every bit that
+// one of its star neighbours c[r <- *] (r over the digits of c that are not
+// *) holds at the start.  Combinations are visited by increasing number of
+// stars, so a neighbour (one star more) still holds its starting value when
+// it is read.  On a column that is M with some other dimensions already
+// reduced, this equals reducing the K dimensions one after another: a bit
+// that a neighbour lost to one of those other dimensions is lost by c to the
+// same dimension (the larger cube contains c's extension).  Two neighbours
+// fold into one three-input bit operation.
 template <int K>
 __device__ __forceinline__ void reg_reduce(uint32_t (&x)[pow3(K)])
 {
-    static_for<K>([&](auto ri) {
-        constexpr int r = decltype(ri)::value;
+    static_for<K>([&](auto si) {
+        constexpr int s = decltype(si)::value;
         static_for<(int)pow3(K)>([&](auto ci) {
             constexpr int c = decltype(ci)::value;
-            constexpr int d = tdigit(c, r);
-            if constexpr (d != 2) x[c] &= ~x[c + (2 - d) * (int)pow3(r)];
+            if constexpr (star_count(c, K) == s) {
+                uint32_t kill = 0u;
+                static_for<K>([&](auto ri) {
+                    constexpr int r = decltype(ri)::value;
+                    constexpr int d = tdigit(c, r);
+                    if constexpr (d != 2) kill |= x[c + (2 - d) * (int)pow3(r)];
+                });
+                x[c] &= ~kill;
+            }
         });
     });
 }
