@@ -454,55 +454,73 @@ __device__ __forceinline__ void reduce_full_tile(uint32_t *t, uint32_t *tile, ui
 
 // Ordered list of the set bits of one tile of a bitmap in HBM, by one
 // wavefront: the tile's non-zero chunks (bit k of map = chunk k, from the
-// tile summary) are listed in order, their words are loaded kListBatch chunks
-// at a time, and each chunk's set bits are written at `off` plus the running
-// count (word-major, then bit) as cube indices rho0 + rho_of_word(wbase +
-// word) + bit.  Entries at or past cap are dropped.  nz holds kTileChunks
-// entries private to the wave.
-constexpr int kListBatch = 16;  // chunks whose words are loaded together
-
+// tile summary) are listed in order, and taken sixteen at a time: lane l
+// holds words 16 (l mod 4) .. 16 (l mod 4) + 15 of the (l / 4)-th chunk of
+// the batch, so lane order is word order.  One wave scan of the lanes' bit
+// counts places every lane's bits, which it writes in order at `off` plus the
+// running count as cube indices rho0 + rho_of_word(wbase + word) + bit
+// (wbase a multiple of 8).  Entries at or past cap are dropped.  nz holds
+// kTileChunks entries private to the wave.
 __device__ __forceinline__ void list_tile(const uint32_t *src, uint32_t tw, uint64_t wbase, uint64_t off,
                                           const uint32_t *map, uint64_t *list, uint64_t cap, uint16_t *nz,
                                           uint64_t rho0 = 0)
 {
+    constexpr int kSpan = 16;  // words per lane
     const uint32_t lane = lane_id();
     const uint32_t mw = lane < (uint32_t)kMapWords ? map[lane] : 0u;
     const uint32_t pc = __popc(mw);
-    const uint32_t incl = wave_inclusive_scan32(pc);
-    const uint32_t m = __shfl(incl, 63, 64);
-    uint32_t pos = incl - pc, bits = mw;
+    const uint32_t incl0 = wave_inclusive_scan32(pc);
+    const uint32_t m = __shfl(incl0, 63, 64);
+    uint32_t pos0 = incl0 - pc, bits = mw;
     while (bits != 0u) {
         const uint32_t b = __builtin_ctz(bits);
         bits &= bits - 1u;
-        nz[pos++] = (uint16_t)(lane * 32 + b);
+        nz[pos0++] = (uint16_t)(lane * 32 + b);
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
+    const uint32_t slot = lane / 4, qw = (lane % 4) * kSpan;
     uint64_t run = off;
-    for (uint32_t r0 = 0; r0 < m && run < cap; r0 += kListBatch) {
-        uint32_t v[kListBatch];
-        static_for<kListBatch>([&](auto ii) {
-            constexpr int i = decltype(ii)::value;
-            const uint32_t w = (r0 + i < m) ? (uint32_t)nz[r0 + i] * kChunkWords + lane : tw;
-            v[i] = w < tw ? src[w] : 0u;
-        });
-        static_for<kListBatch>([&](auto ii) {
-            constexpr int i = decltype(ii)::value;
-            if (r0 + i < m) {
-                uint32_t x = v[i];
-                const uint32_t cc = __popc(x);
-                const uint32_t inc = wave_inclusive_scan32(cc);
-                uint64_t p = run + (inc - cc);
-                const uint64_t w = (uint64_t)nz[r0 + i] * kChunkWords + lane;
-                const uint64_t rbase = rho0 + rho_of_word(wbase + w);
-                while (x != 0u && p < cap) {
-                    const uint32_t b = __builtin_ctz(x);
-                    x &= x - 1u;
-                    list[p++] = rbase + b;
-                }
-                run += __shfl(inc, 63, 64);
+    for (uint32_t r0 = 0; r0 < m && run < cap; r0 += 64 / 4) {
+        uint32_t v[kSpan];
+        uint32_t w0 = 0;
+        static_for<kSpan>([&](auto ji) { v[decltype(ji)::value] = 0u; });
+        if (r0 + slot < m) {
+            w0 = (uint32_t)nz[r0 + slot] * kChunkWords + qw;
+            if (w0 + kSpan <= tw) {
+                const uint4 *p = reinterpret_cast<const uint4 *>(src + w0);  // 64-byte aligned
+                static_for<kSpan / 4>([&](auto ki) {
+                    constexpr int k = decltype(ki)::value;
+                    const uint4 u = p[k];
+                    v[4 * k] = u.x;
+                    v[4 * k + 1] = u.y;
+                    v[4 * k + 2] = u.z;
+                    v[4 * k + 3] = u.w;
+                });
+            } else {
+                // the tile's last chunk is partial
+                static_for<kSpan>([&](auto ji) {
+                    constexpr int j = decltype(ji)::value;
+                    v[j] = w0 + j < tw ? src[w0 + j] : 0u;
+                });
+            }
+        }
+        uint32_t cnt = 0;
+        static_for<kSpan>([&](auto ji) { cnt += __popc(v[decltype(ji)::value]); });
+        const uint32_t incl = wave_inclusive_scan32(cnt);
+        uint64_t p = run + (incl - cnt);
+        const uint64_t rb = rho0 + rho_of_word(wbase + w0);  // w0 is a multiple of 8
+        static_for<kSpan>([&](auto ji) {
+            constexpr int j = decltype(ji)::value;
+            uint32_t x = v[j];
+            const uint64_t rj = rb + (uint64_t)(kBlockCubes * (j / 8) + 32 * (j % 8));
+            while (x != 0u && p < cap) {
+                const uint32_t b = __builtin_ctz(x);
+                x &= x - 1u;
+                list[p++] = rj + b;
             }
         });
+        run += __shfl(incl, 63, 64);
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();  // nz is reused by the wave's next tile
