@@ -167,6 +167,16 @@ ColArgs col_args(uint32_t *state, int n, const Group &g, bool outer_binary)
     return c;
 }
 
+// Row flags between the top group's merge+reduce and the reduce of the group
+// below it: n = 24 with the plan [6, 6] (both column passes of 729 rows per
+// block), when the context has the flag buffers.
+bool use_row_flags(const dqmc_ctx *ctx, int n, const std::vector<Group> &gs)
+{
+    return ctx->flags_top != nullptr && ctx->flags_low != nullptr && ctx->flags_tile != nullptr && n == 24 &&
+           gs.size() == 2 && gs[0].gr == 4 &&
+           gs[0].gw == 2 && gs[1].gr == 4 && gs[1].gw == 2;
+}
+
 // Steps 1-2 (and the top group's merge when reduce == false).
 int enqueue_merge(dqmc_ctx *ctx, int n, const uint32_t *tt, uint32_t flip, uint32_t *state, bool fuse_top_reduce,
                   hipStream_t s)
@@ -184,7 +194,8 @@ int enqueue_merge(dqmc_ctx *ctx, int n, const uint32_t *tt, uint32_t flip, uint3
     for (size_t j = 0; j < gs.size(); ++j) {
         const bool top = j + 1 == gs.size();
         const int mode = (top && fuse_top_reduce) ? kColMergeReduce : kColMerge;
-        const ColArgs c = col_args(state, n, gs[j], true);
+        ColArgs c = col_args(state, n, gs[j], true);
+        if (mode == kColMergeReduce && use_row_flags(ctx, n, gs)) c.flags = ctx->flags_top;
         const int od = n - (gs[j].g0 + gs[j].size() - 1);
         const double fo = std::pow(2.0 / 3.0, od), fg = std::pow(2.0 / 3.0, gs[j].size());
         const double bytes = mode == kColMerge ? S * fo * (fg + (1.0 - fg)) : S * fo * (fg + 1.0);
@@ -199,10 +210,12 @@ int enqueue_merge(dqmc_ctx *ctx, int n, const uint32_t *tt, uint32_t flip, uint3
 
 // The low-tile pass that ends a prime bitmap: reduce of digits 1..12 with the
 // tile summaries, or the summaries alone.
-int enqueue_summary(dqmc_ctx *ctx, int n, int mode, uint32_t *state, hipStream_t s, uint64_t tile0 = 0)
+int enqueue_summary(dqmc_ctx *ctx, int n, int mode, uint32_t *state, hipStream_t s, uint64_t tile0 = 0,
+                    const uint32_t *tile_flags = nullptr)
 {
     LowArgs a = low_args(ctx, n);
     a.state = state;
+    a.tile_flags = tile_flags;
     a.counts += tile0;  // the summaries of a slice start at tile0 of a larger state
     a.chunkmap += tile0 * kMapWords;
     const double S = state_bytes(n);
@@ -233,9 +246,9 @@ int enqueue_scan_list(dqmc_ctx *ctx, int n, const uint32_t *state, uint64_t *lis
 // Final low-tile pass (reduce or plain count), scan of the tile counts, and
 // the list pass.
 int enqueue_extract_tiles(dqmc_ctx *ctx, int n, int mode, uint32_t *state, uint64_t *list, uint64_t cap,
-                          uint64_t *count, hipStream_t s)
+                          uint64_t *count, hipStream_t s, const uint32_t *tile_flags = nullptr)
 {
-    const int rc = enqueue_summary(ctx, n, mode, state, s);
+    const int rc = enqueue_summary(ctx, n, mode, state, s, 0, tile_flags);
     if (rc != DQMC_OK) return rc;
     return enqueue_scan_list(ctx, n, state, list, cap, count, nullptr, 0, s);
 }
@@ -243,19 +256,38 @@ int enqueue_extract_tiles(dqmc_ctx *ctx, int n, int mode, uint32_t *state, uint6
 // Steps 1-4 for n > 12: merges, the top group's merge and reduce, and the
 // reduces of the other high groups (the low digits are reduced by the
 // summary pass).
-int enqueue_reduce_high(dqmc_ctx *ctx, int n, const uint32_t *tt, uint32_t flip, uint32_t *state, hipStream_t s)
+// *tile_flags (may be NULL): chunk flags for the final reduce, or nullptr.
+int enqueue_reduce_high(dqmc_ctx *ctx, int n, const uint32_t *tt, uint32_t flip, uint32_t *state, hipStream_t s,
+                        const uint32_t **tile_flags = nullptr)
 {
+    if (tile_flags != nullptr) *tile_flags = nullptr;
     int rc = enqueue_merge(ctx, n, tt, flip, state, true, s);
     if (rc != DQMC_OK) return rc;
     const std::vector<Group> gs = groups_of(plan_sizes(ctx, n));
+    const bool flags = use_row_flags(ctx, n, gs);
+    if (flags) {
+        // 18 MB read, 18 MB written
+        rc = run_pass(ctx, s, "flag_transpose", n, 8.0 * 729 * kFlagLowBlocks * kFlagWords, 0,
+                      [&] { return launch_flag_transpose(ctx->flags_top, ctx->flags_low, s); });
+        if (rc != DQMC_OK) return rc;
+    }
     for (int j = (int)gs.size() - 2; j >= 0; --j) {
-        const ColArgs c = col_args(state, n, gs[j], false);
+        ColArgs c = col_args(state, n, gs[j], false);
+        if (flags && j == 0) c.flags = ctx->flags_low;
         const double S = state_bytes(n);
         char name[40];
         snprintf(name, sizeof(name), "col_reduce_g%d_%d", gs[j].g0, gs[j].size());
         rc = run_pass(ctx, s, name, n, S * (2.0 - std::pow(3.0, -gs[j].size())), 0,
                       [&] { return launch_col(gs[j].gr, gs[j].gw, kColReduce, c, s); });
         if (rc != DQMC_OK) return rc;
+    }
+    if (flags && tile_flags != nullptr) {
+        // the reduce pass's row flags as chunk flags of the tiles (18 MB
+        // read, 19 MB written)
+        rc = run_pass(ctx, s, "tile_flags", n, 4.0 * 729 * kFlagLowBlocks * kFlagWords + 4.0 * pow3(12) * kMapWords,
+                      0, [&] { return launch_tile_flags(ctx->flags_low, ctx->flags_tile, s); });
+        if (rc != DQMC_OK) return rc;
+        *tile_flags = ctx->flags_tile;
     }
     return DQMC_OK;
 }
@@ -294,8 +326,9 @@ int enqueue_slice_primes(dqmc_ctx *ctx, int m, const uint32_t *tt, uint32_t *sta
                                 [&] { return launch_low(kLowPrimesTT, a, 1, s); });
         return rc != DQMC_OK ? rc : enqueue_summary(ctx, m, kLowCount, state, s, tile0);
     }
-    const int rc = enqueue_reduce_high(ctx, m, tt, 0u, state, s);
-    return rc != DQMC_OK ? rc : enqueue_summary(ctx, m, kLowReduceCount, state, s, tile0);
+    const uint32_t *tf = nullptr;
+    const int rc = enqueue_reduce_high(ctx, m, tt, 0u, state, s, &tf);
+    return rc != DQMC_OK ? rc : enqueue_summary(ctx, m, kLowReduceCount, state, s, tile0, tf);
 }
 
 // Implicants of the m-variable function `tt` into `state`.
@@ -473,6 +506,9 @@ int dqmc_create(int device, dqmc_ctx **out)
     c->slice_tt = nullptr;
     c->split_tt = nullptr;
     c->run = nullptr;
+    c->flags_top = nullptr;
+    c->flags_low = nullptr;
+    c->flags_tile = nullptr;
     c->batch_mem = nullptr;
     c->batch_cap = 0;
     c->err[0] = 0;
@@ -489,7 +525,10 @@ int dqmc_create(int device, dqmc_ctx **out)
         hipMalloc((void **)&c->sums, scan_scratch_words(c->tiles_cap) * sizeof(uint64_t)) != hipSuccess ||
         hipMalloc((void **)&c->slice_tt, dqmc_tt_words(DQMC_MAX_N) * sizeof(uint32_t)) != hipSuccess ||
         hipMalloc((void **)&c->split_tt, dqmc_tt_words(DQMC_MAX_N - 1) * sizeof(uint32_t)) != hipSuccess ||
-        hipMalloc((void **)&c->run, 2 * sizeof(uint64_t)) != hipSuccess) {
+        hipMalloc((void **)&c->run, 2 * sizeof(uint64_t)) != hipSuccess ||
+        hipMalloc((void **)&c->flags_top, kFlagTopBlocks * kFlagWords * sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc((void **)&c->flags_low, 729 * kFlagLowBlocks * kFlagWords * sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc((void **)&c->flags_tile, pow3(12) * kMapWords * sizeof(uint32_t)) != hipSuccess) {
         dqmc_destroy(c);
         return DQMC_ENOMEM;
     }
@@ -510,6 +549,9 @@ void dqmc_destroy(dqmc_ctx *ctx)
     if (ctx->slice_tt) (void)hipFree(ctx->slice_tt);
     if (ctx->split_tt) (void)hipFree(ctx->split_tt);
     if (ctx->run) (void)hipFree(ctx->run);
+    if (ctx->flags_top) (void)hipFree(ctx->flags_top);
+    if (ctx->flags_low) (void)hipFree(ctx->flags_low);
+    if (ctx->flags_tile) (void)hipFree(ctx->flags_tile);
     if (ctx->batch_mem) (void)hipFree(ctx->batch_mem);
     delete ctx;
 }
@@ -571,9 +613,10 @@ int dqmc_primes_ex(dqmc_ctx *ctx, int n, const uint32_t *d_tt, uint32_t flags, u
                         [&] { return launch_low(kLowPrimesTT, a, 1, s); });
     }
     if (use_split(ctx, n)) return enqueue_primes_split(ctx, n, d_tt, flip, d_state, d_list, list_cap, d_count, s);
-    rc = enqueue_reduce_high(ctx, n, d_tt, flip, d_state, s);
+    const uint32_t *tf = nullptr;
+    rc = enqueue_reduce_high(ctx, n, d_tt, flip, d_state, s, &tf);
     if (rc != DQMC_OK) return rc;
-    return enqueue_extract_tiles(ctx, n, kLowReduceCount, d_state, d_list, list_cap, d_count, s);
+    return enqueue_extract_tiles(ctx, n, kLowReduceCount, d_state, d_list, list_cap, d_count, s, tf);
 }
 
 int dqmc_primes_noalloc(int n, const uint32_t *d_tt, uint32_t *d_state, uint64_t *d_list, uint64_t list_cap,

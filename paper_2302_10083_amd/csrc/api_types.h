@@ -17,6 +17,13 @@ struct dqmc_ctx {
     uint32_t *slice_tt;  // sliced path: truth table of one slice (2^20 words)
     uint32_t *split_tt;  // top-digit split: truth table of one third (2^19 words)
     uint64_t *run;       // sliced path: running prime counts (2)
+    // row flags of the n = 24 passes (plan [6, 6]): the top group's pass
+    // writes flags_top, a transpose turns them into flags_low for the reduce
+    // of digits 13..18 (kFlagTopBlocks and 729 kFlagLowBlocks blocks of
+    // kFlagWords words)
+    uint32_t *flags_top;
+    uint32_t *flags_low;
+    uint32_t *flags_tile;  // the same as chunk flags of the final reduce (3^12 tiles of kMapWords words)
     void *batch_mem;     // dqmc_primes_batch: scratch for up to batch_cap jobs (grown on demand)
     uint32_t batch_cap;
     char err[512];

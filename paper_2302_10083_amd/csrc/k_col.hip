@@ -95,6 +95,10 @@ __attribute__((amdgpu_waves_per_eu(MODE == kColReduce && GW == 2 ? 5 : 1))) void
     constexpr int XR = (GW > 0 && !NEED_MERGE) ? (int)pow3(GW - 1) * CR * 64 : 1;
     constexpr int XSZ = XM > XR ? XM : XR;
     __shared__ uint32_t xch[XSZ];
+    // merge+reduce with row flags: the block's 729 row bits
+    constexpr bool WRITE_FLAGS = MODE == kColMergeReduce && GR == 4 && GW == 2;
+    __shared__ uint32_t fl[WRITE_FLAGS ? kFlagWords : 1];
+    if (WRITE_FLAGS && threadIdx.x < kFlagWords) fl[threadIdx.x] = 0u;  // ordered by the merge's barrier
 
     // grids stay below 2^32 workgroups: 32-bit division
     const uint32_t logical = (uint32_t)xcd_remap(blockIdx.x, a.nblocks), nlb = (uint32_t)a.nlb;
@@ -117,6 +121,7 @@ __attribute__((amdgpu_waves_per_eu(MODE == kColReduce && GW == 2 ? 5 : 1))) void
     uint32_t *rows = a.state + L * (uint64_t)CR * ((uint64_t)cw + (uint64_t)CW * o);
 
     uint32_t x[CR];
+    uint32_t live_pre[(CR + 31) / 32] = {};  // reduce mode with row flags: rows that may hold a bit
     bool cw_binary = true;
     if constexpr (GW > 0) {
         int c = cw;
@@ -184,19 +189,52 @@ __attribute__((amdgpu_waves_per_eu(MODE == kColReduce && GW == 2 ? 5 : 1))) void
             return;
         }
     } else {
+        // rows to load: all, or those the top group's pass flagged (the
+        // others are zero in memory)
+        uint32_t rf[3] = {~0u, ~0u, ~0u};
+        if constexpr (GR == 4 && GW == 2) {
+            if (a.flags != nullptr) {
+                const uint32_t *fb = a.flags + (uint64_t)logical * kFlagWords;
+                const uint32_t b0 = (uint32_t)(CR * cw), w0 = b0 / 32, sh = b0 % 32;
+                uint32_t w[4];
+                static_for<4>([&](auto ki) {
+                    constexpr uint32_t k = decltype(ki)::value;
+                    w[k] = w0 + k < kFlagWords ? fb[w0 + k] : 0u;
+                });
+                rf[0] = __builtin_amdgcn_alignbit(w[1], w[0], sh);
+                rf[1] = __builtin_amdgcn_alignbit(w[2], w[1], sh);
+                rf[2] = __builtin_amdgcn_alignbit(w[3], w[2], sh) & ((1u << (CR - 64)) - 1u);
+            }
+        }
         static_for<CR>([&](auto ci) { x[decltype(ci)::value] = 0u; });
         if (active) {
             global_u32 *row = (global_u32 *)rows;
             static_for<CR>([&](auto ci) {
-                x[decltype(ci)::value] = row_word(row, l4);
+                constexpr int c = decltype(ci)::value;
+                if ((rf[c / 32] >> (c % 32)) & 1u) x[c] = row_word(row, l4);
                 row = next_row(row, L);
             });
+        }
+        if constexpr (GR == 4 && GW == 2) {
+            // with flags, the rows that may hold a bit are the flagged ones
+            if (a.flags != nullptr) {
+                live_pre[0] = rf[0];
+                live_pre[1] = rf[1];
+                live_pre[2] = rf[2];
+            }
         }
     }
     // Reduce-only mode works in place and only clears bits: a row whose 64
     // words are all zero as loaded stays zero and is not stored again.
     uint32_t live[(CR + 31) / 32] = {};
-    if constexpr (!NEED_MERGE) {
+    bool have_live = false;
+    if constexpr (!NEED_MERGE && GR == 4 && GW == 2) {
+        if (a.flags != nullptr) {
+            static_for<(CR + 31) / 32>([&](auto ki) { live[decltype(ki)::value] = live_pre[decltype(ki)::value]; });
+            have_live = true;
+        }
+    }
+    if (!NEED_MERGE && !have_live) {
         static_for<CR>([&](auto ci) {
             constexpr int c = decltype(ci)::value;
             // packed now (a scalar word): otherwise the 81 ballots stay
@@ -264,10 +302,111 @@ __attribute__((amdgpu_waves_per_eu(MODE == kColReduce && GW == 2 ? 5 : 1))) void
                 row = next_row(row, L);
             });
         }
+        if constexpr (WRITE_FLAGS) {
+            if (a.flags != nullptr) {
+                // a bit per row with a set bit: this wave's rows c + 81 cw (a
+                // bit per 32-word half would spare the reduce pass loads of
+                // odd slots, but its bookkeeping cost the top pass more)
+                uint32_t f[3] = {0u, 0u, 0u};
+                static_for<CR>([&](auto ci) {
+                    constexpr int c = decltype(ci)::value;
+                    f[c / 32] = __builtin_amdgcn_readfirstlane(f[c / 32] |
+                                                               (__ballot(x[c] != 0u) != 0 ? 1u << (c % 32) : 0u));
+                    asm volatile("" : "+s"(f[c / 32]));
+                });
+                for (uint32_t i = lane; i < (uint32_t)CR; i += 64) {
+                    const uint32_t fw = i < 32 ? f[0] : i < 64 ? f[1] : f[2];
+                    if ((fw >> (i % 32)) & 1u) {
+                        const uint32_t b = (uint32_t)(CR * cw) + i;
+                        atomicOr(&fl[b / 32], 1u << (b % 32));
+                    }
+                }
+                lds_barrier();
+                if (threadIdx.x < kFlagWords) a.flags[(uint64_t)logical * kFlagWords + threadIdx.x] = fl[threadIdx.x];
+            }
+        }
     }
 }
 
 int col_lanes_per_block(int gw) { return gw == 0 ? 256 : 64; }
+
+// Row flags of the top group's pass into the order of the reduce of digits
+// 13..18 (n = 24, both groups of six digits).  An item is (ob, lb, wc): the
+// reduce pass's outer combinations o = 32 ob .. 32 ob + 31, its column block
+// lb, and its rows c = 32 wc .. 32 wc + 31.  Lane i of the item's 32 reads the
+// top pass's flag word for row c = 32 wc + i (bits over o), ORed over the one
+// or two top blocks that hold words 64 lb .. 64 lb + 63 of slot c (slot c
+// starts at word 17504 c, half a top block in for odd c: a superset of the
+// rows that hold a bit); 32 ballots transpose the 32 x 32 bits, and lane j
+// writes the word of o = 32 ob + j (bits over c).  Two items per wavefront.
+constexpr uint64_t kFlagItems = (uint64_t)kFlagWords * kFlagLowBlocks * kFlagWords;
+
+__global__ __launch_bounds__(256) void flag_transpose_kernel(const uint32_t *top, uint32_t *low)
+{
+    const uint64_t item = ((uint64_t)blockIdx.x * 256 + threadIdx.x) / 32;
+    const uint32_t i = threadIdx.x % 32;
+    const bool valid = item < kFlagItems;
+    const uint32_t wc = (uint32_t)(item % kFlagWords), lb = (uint32_t)(item / kFlagWords % kFlagLowBlocks);
+    const uint32_t ob = (uint32_t)(item / (kFlagWords * kFlagLowBlocks));
+    const uint32_t c = 32 * wc + i;
+    uint32_t a = 0u;
+    if (valid && c < 729u) {
+        const uint64_t w = (uint64_t)kTileStride * c + 64ull * lb;  // the segment's first word in the top rows
+        const uint64_t b3 = w / 64;
+        a = top[b3 * kFlagWords + ob];
+        if (w % 64 != 0 && b3 + 1 < kFlagTopBlocks) a |= top[(b3 + 1) * kFlagWords + ob];
+    }
+    const bool hi = (threadIdx.x % 64) >= 32;
+    uint32_t out = 0u;
+    for (uint32_t j = 0; j < 32; ++j) {
+        const uint64_t m = __ballot((a >> j) & 1u);
+        const uint32_t half = hi ? (uint32_t)(m >> 32) : (uint32_t)m;
+        out = i == j ? half : out;
+    }
+    const uint32_t o = 32 * ob + i;
+    if (valid && o < 729u) low[((uint64_t)o * kFlagLowBlocks + lb) * kFlagWords + wc] = out;
+}
+
+// The reduce pass's row flags, block (o, lb) holding a bit per slot c, as
+// chunk flags of tile c + 729 o (bit lb).  An item is (o, cb, lw): slots
+// c = 32 cb .. 32 cb + 31 and chunks lb = 32 lw .. 32 lw + 31; lane i reads
+// the word of block (o, 32 lw + i), 32 ballots transpose, lane j writes word
+// lw of tile 32 cb + j + 729 o.  Two items per wavefront.
+constexpr uint64_t kTileFlagItems = 729ull * kFlagWords * kMapWords;
+
+__global__ __launch_bounds__(256) void tile_flags_kernel(const uint32_t *low, uint32_t *tiles)
+{
+    const uint64_t item = ((uint64_t)blockIdx.x * 256 + threadIdx.x) / 32;
+    const uint32_t i = threadIdx.x % 32;
+    const bool valid = item < kTileFlagItems;
+    const uint32_t lw = (uint32_t)(item % kMapWords), cb = (uint32_t)(item / kMapWords % kFlagWords);
+    const uint32_t o = (uint32_t)(item / (kMapWords * kFlagWords));
+    const uint32_t lb = 32 * lw + i;
+    const uint32_t a = (valid && lb < kFlagLowBlocks) ? low[((uint64_t)o * kFlagLowBlocks + lb) * kFlagWords + cb] : 0u;
+    const bool hi = (threadIdx.x % 64) >= 32;
+    uint32_t out = 0u;
+    for (uint32_t j = 0; j < 32; ++j) {
+        const uint64_t m = __ballot((a >> j) & 1u);
+        const uint32_t half = hi ? (uint32_t)(m >> 32) : (uint32_t)m;
+        out = i == j ? half : out;
+    }
+    const uint32_t c = 32 * cb + i;
+    if (valid && c < 729u) tiles[((uint64_t)o * 729 + c) * kMapWords + lw] = out;
+}
+
+hipError_t launch_tile_flags(const uint32_t *low, uint32_t *tiles, hipStream_t s)
+{
+    const uint64_t threads = kTileFlagItems * 32;
+    hipLaunchKernelGGL(tile_flags_kernel, dim3((uint32_t)((threads + 255) / 256)), dim3(256), 0, s, low, tiles);
+    return hipGetLastError();
+}
+
+hipError_t launch_flag_transpose(const uint32_t *top, uint32_t *low, hipStream_t s)
+{
+    const uint64_t threads = kFlagItems * 32;
+    hipLaunchKernelGGL(flag_transpose_kernel, dim3((uint32_t)((threads + 255) / 256)), dim3(256), 0, s, top, low);
+    return hipGetLastError();
+}
 
 // Dynamic LDS of the merge and merge+reduce passes with two wave digits: one
 // workgroup per CU (n = 24: the top group's merge 14.1 -> 9.0 ms, the first

@@ -84,6 +84,32 @@ __global__ __launch_bounds__(low_threads<MODE>()) __attribute__((amdgpu_waves_pe
         const uint32_t *src = a.state + tile * a.ts;
         if constexpr (MODE == kLowReduceCount) {
             // always a full tile here (n > 12)
+            if (a.tile_flags != nullptr) {
+                // kFlaggedTiles consecutive tiles per workgroup; each
+                // wavefront loads the flag words of all of them first (scalar
+                // loads), so only the first tile waits for its flags
+                const uint64_t first = tile * kFlaggedTiles;
+                const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+                const uint32_t k0 = 24 * wv / 32, k1 = (24 * wv + 23) / 32;
+                uint32_t f0[kFlaggedTiles], f1[kFlaggedTiles];
+                static_for<kFlaggedTiles>([&](auto ki) {
+                    constexpr int k = decltype(ki)::value;
+                    const bool in = first + k < a.ntiles;
+                    const uint32_t *fw = a.tile_flags + (first + k) * kMapWords;
+                    f0[k] = in && k0 < (uint32_t)kMapWords ? fw[k0] : 0u;
+                    f1[k] = in && k1 < (uint32_t)kMapWords ? fw[k1] : 0u;
+                });
+                static_for<kFlaggedTiles>([&](auto ki) {
+                    constexpr int k = decltype(ki)::value;
+                    const uint64_t tk = first + k;
+                    if (tk < a.ntiles) {
+                        if (k > 0) __syncthreads();  // the LDS tile and `red` are reused
+                        reduce_full_tile<true>(t, a.state + tk * a.ts, a.counts + tk, a.chunkmap + tk * kMapWords, red,
+                                               a.tile_flags + tk * kMapWords, f0[k], f1[k]);
+                    }
+                });
+                return;
+            }
             reduce_full_tile<true>(t, a.state + tile * a.ts, a.counts + tile, a.chunkmap + tile * kMapWords, red);
             return;
         } else {
@@ -130,9 +156,12 @@ hipError_t launch_low(int mode, const LowArgs &a, uint64_t nblocks, hipStream_t 
     case kLowPrimesTT:
         hipLaunchKernelGGL(low_kernel<kLowPrimesTT>, grid, dim3(low_threads<kLowPrimesTT>()), lds, s, a);
         break;
-    case kLowReduceCount:
-        hipLaunchKernelGGL(low_kernel<kLowReduceCount>, grid, dim3(low_threads<kLowReduceCount>()), lds, s, a);
+    case kLowReduceCount: {
+        // with chunk flags, kFlaggedTiles tiles per workgroup
+        const dim3 g(a.tile_flags != nullptr ? (uint32_t)((nblocks + kFlaggedTiles - 1) / kFlaggedTiles) : grid.x);
+        hipLaunchKernelGGL(low_kernel<kLowReduceCount>, g, dim3(low_threads<kLowReduceCount>()), lds, s, a);
         break;
+    }
     case kLowCount:
         hipLaunchKernelGGL(low_kernel<kLowCount>, grid, dim3(low_threads<kLowCount>()), lds, s, a);
         break;

@@ -44,9 +44,14 @@ struct LowArgs {
     int n;
     int lw;             // block digits inside a tile (tw = 8 * 3^lw)
     uint32_t flip;      // XOR applied to the truth-table words (~0u: complement)
+    // final reduce (n > 12): per tile, kMapWords words marking the 64-word
+    // chunks that may hold a set bit (the others are zero in the state), or
+    // nullptr
+    const uint32_t *tile_flags;
 };
 
 constexpr int kLowThreads = 256;
+constexpr int kFlaggedTiles = 4;  // tiles per workgroup of the final reduce with chunk flags
 
 hipError_t low_setup();
 
@@ -86,7 +91,30 @@ struct ColArgs {
     uint64_t nouter;     // outer (above the group) combinations launched
     uint64_t nblocks;    // nlb * nouter
     int outer_binary;    // 1: outer index enumerates binary digit combos
+    // Row flags (col_kernel<4, 2> only; nullptr: none).  The merge+reduce
+    // mode writes, per column block, a bit per row of its 729 (set: the row's
+    // 64 words hold a set bit after the pass), kFlagWords words per block.
+    // The reduce mode reads kFlagWords words per block in its own row order
+    // (launch_flag_transpose) and loads and stores only the flagged rows.
+    uint32_t *flags;
 };
+
+// Row flags from the top group's merge+reduce (digits 19..24) to the reduce
+// of digits 13..18 at n = 24 (plan [6, 6]): both passes have 729 rows per
+// column block.  The top pass's block b (words 64 b .. 64 b + 63 of a row,
+// rows L3 = 729 kTileStride words apart) is the 64-word segment of each of
+// its rows; the reduce pass's block (lb, o) covers words 64 lb .. of the
+// slots c (rows kTileStride words apart) of the 729 slots above o.
+constexpr uint32_t kFlagWords = 23;                    // 729 bits
+constexpr uint64_t kFlagTopBlocks = (729ull * kTileStride + 63) / 64;  // 199382
+constexpr uint64_t kFlagLowBlocks = (kTileStride + 63) / 64;          // 274 per slot
+// Bit o of word c / 32 of block (o, lb) of the reduce pass = bit o of the
+// top pass's block(s) holding words 64 lb .. 64 lb + 63 of slot c.
+hipError_t launch_flag_transpose(const uint32_t *top, uint32_t *low, hipStream_t s);
+// The reduce pass's row flags (rows that may hold a bit as it loads them, a
+// superset of what it leaves) as chunk flags of the n = 24 tiles: bit k of
+// word k / 32 of tile c + 729 o = bit c of the reduce pass's block (o, k).
+hipError_t launch_tile_flags(const uint32_t *low, uint32_t *tiles, hipStream_t s);
 
 hipError_t col_setup();    // also runs chunk_setup
 hipError_t chunk_setup();  // occupancy caps of the chunked column kernel

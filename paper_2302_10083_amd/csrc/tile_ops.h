@@ -346,9 +346,11 @@ __device__ __forceinline__ void reduce_run_to_lds(uint32_t *t, const TileRun &r,
 }
 
 // Reduce of digit 6 across the three blocks of run q into the LDS tile, the
-// chunk flags of the run as loaded, and the run's blocks that are non-zero
-// after it appended to `blist` (length *nlist).  Every thread of the
-// workgroup calls it (ballots); threads without a run pass has_run = false.
+// chunk flags of the run as loaded (unless MARK is false: given), and the
+// run's blocks that are non-zero after it appended to `blist` (length
+// *nlist).  Every thread of the workgroup calls it (ballots); threads without
+// a run pass has_run = false.
+template <bool MARK>
 __device__ __forceinline__ void run_digit6_to_lds(uint32_t *t, const TileRun &r, uint32_t q, bool has_run,
                                                   uint32_t *innz, uint16_t *blist, uint32_t *nlist)
 {
@@ -356,7 +358,7 @@ __device__ __forceinline__ void run_digit6_to_lds(uint32_t *t, const TileRun &r,
     if (has_run) {
         uint32_t b0[kBlockWords], b1[kBlockWords], b2[kBlockWords];
         unpack_run(r, b0, b1, b2);
-        mark_run_chunks(b0, b1, b2, q, innz);
+        if constexpr (MARK) mark_run_chunks(b0, b1, b2, q, innz);
         uint32_t o0 = 0, o1 = 0, o2 = 0;
         static_for<kBlockWords>([&](auto wi) {
             constexpr int w = decltype(wi)::value;
@@ -397,9 +399,16 @@ __device__ __forceinline__ void run_digit6_to_lds(uint32_t *t, const TileRun &r,
 // list that needs kBlockListBytes of LDS after the padded tile; and the stores of
 // chunks that were zero as loaded are left out (see last_round_to_hbm).  On
 // the denser small tiles of a batch both cost more than they save.
+// With SPARSE, `flags` (kMapWords words, or nullptr) marks the chunks that
+// may hold a set bit: the others are zero in HBM, so their runs are not
+// loaded, and the flags stand for the chunks that were non-zero as loaded.
+// f0, f1 are the words 24 w / 32 and (24 w + 23) / 32 of the flags for the
+// calling wavefront w (its 64 runs cover chunks 24 w .. 24 w + 23), loaded
+// ahead by the caller.
 template <bool SPARSE>
 __device__ __forceinline__ void reduce_full_tile(uint32_t *t, uint32_t *tile, uint32_t *count, uint32_t *map,
-                                                 uint32_t *red)
+                                                 uint32_t *red, const uint32_t *flags = nullptr, uint32_t f0 = 0u,
+                                                 uint32_t f1 = 0u)
 {
     uint32_t *innz = red + kMapWords + 1;
     if (threadIdx.x < kRedWords) red[threadIdx.x] = 0;
@@ -407,10 +416,25 @@ __device__ __forceinline__ void reduce_full_tile(uint32_t *t, uint32_t *tile, ui
     if constexpr (SPARSE) {
         uint16_t *blist = reinterpret_cast<uint16_t *>(t + kPaddedTileWords);
         uint32_t *nlist = red + kRedWords - 1;
-        __syncthreads();  // flags and list length zeroed before they are set
         TileRun r;
-        if (q < kTileTriples) load_run(r, tile, q);
-        run_digit6_to_lds(t, r, q, q < kTileTriples, innz, blist, nlist);
+        if (flags != nullptr) {
+            // The LDS copy of the flags serves the last round's store
+            // decisions.
+            const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+            const uint32_t k0 = 24 * wv / 32;
+            const uint32_t c0 = 24 * q / kChunkWords, c1 = (24 * q + 23) / kChunkWords;
+            const uint32_t g0 = c0 / 32 == k0 ? f0 : f1, g1 = c1 / 32 == k0 ? f0 : f1;
+            const bool need = q < kTileTriples && (((g0 >> (c0 % 32)) | (g1 >> (c1 % 32))) & 1u);
+            if (need) load_run(r, tile, q);
+            else static_for<6>([&](auto ki) { r.u[decltype(ki)::value] = make_uint4(0u, 0u, 0u, 0u); });
+            if (threadIdx.x < (uint32_t)kMapWords) innz[threadIdx.x] = flags[threadIdx.x];
+            __syncthreads();  // list length zeroed
+            run_digit6_to_lds<false>(t, r, q, q < kTileTriples, innz, blist, nlist);
+        } else {
+            __syncthreads();  // flags and list length zeroed before they are set
+            if (q < kTileTriples) load_run(r, tile, q);
+            run_digit6_to_lds<true>(t, r, q, q < kTileTriples, innz, blist, nlist);
+        }
         __syncthreads();
         const uint32_t nb = *nlist;
         for (uint32_t i = threadIdx.x; i < nb; i += blockDim.x) {
