@@ -273,3 +273,49 @@ def test_relabel_equivariance_full_list(n, flags):
     finally:
         del state
         torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("kind", ["bern0.5", "bern0.9", "dnf300"])
+def test_row_flags_equal_flag_free_plan_n24(kind):
+    """At n = 24 the default plan [6, 6] passes row flags from the top group's
+    pass to the reduce of digits 13..18 and chunk flags to the final reduce;
+    the plan [4, 4, 4] runs without them.  Both give the same bitmap, count
+    and list, on functions of three densities."""
+    import torch
+
+    from paper_2302_10083_amd import dqmc
+
+    n = 24
+    ctx = context()
+    rng_seed = {"bern0.5": 2401, "bern0.9": 2402, "dnf300": 2403}[kind]
+    if kind.startswith("bern"):
+        tt = inputs.bernoulli(n, float(kind[4:]), rng_seed)
+    else:
+        tt = inputs.make({"n": n, "kind": "dnf", "terms": 300, "wlo": 4, "whi": 12, "seed": rng_seed})
+    ttd = ctx.tt_to_device(tt)
+    state = ctx.new_state(n)
+    count = torch.zeros(1, dtype=torch.int64, device=ctx.torch_device)
+    h = torch.zeros(1, dtype=torch.int64, device=ctx.torch_device)
+    results = []
+    try:
+        for plan in ([], [4, 4, 4]):
+            dqmc.dqmc_set_plan(ctx.ctx, n, plan)
+            assert dqmc.dqmc_get_plan(ctx.ctx, n) == (plan or [6, 6])
+            dqmc.dqmc_primes(ctx.ctx, n, ttd, state, None, 0, count)
+            dqmc.dqmc_hash_words(ctx.ctx, state, state.numel(), h)
+            torch.cuda.synchronize()
+            c = int(count.item())
+            lst = torch.empty(max(c, 1), dtype=torch.int64, device=ctx.torch_device)
+            dqmc.dqmc_extract(ctx.ctx, n, state, lst, c, count)
+            hl = torch.zeros(1, dtype=torch.int64, device=ctx.torch_device)
+            dqmc.dqmc_hash_words(ctx.ctx, lst, 2 * c, hl)
+            torch.cuda.synchronize()
+            results.append((c, int(h.item()), int(hl.item())))
+            log("n=24 %s plan %s: %d primes" % (kind, plan or "[6, 6]", c))
+            del lst
+            state.fill_(0x7F7F7F7F)  # the second plan must overwrite everything it reads
+    finally:
+        dqmc.dqmc_set_plan(ctx.ctx, n, [])
+    assert results[0] == results[1]
+    del state
+    torch.cuda.empty_cache()
