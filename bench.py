@@ -585,14 +585,29 @@ def main():
                                                    lbpp=r["list_bytes_per_prime"]))
         p["ms"] += r["ms"]
         p["k"] += 1
+    # With the row and chunk flags (n = 24, plan [6, 6]) the reduce of digits
+    # 13..18 and the final reduce move data-dependent bytes: the rows and runs
+    # the flags select, counted from the flags of the last step.  Their dense
+    # model (every word read and written) is kept as dense_model_GB.
+    units = dqmc.dqmc_flag_units(ctx.ctx) if n == 24 else {"used": False}
+    ntiles = 3 ** max(n - 12, 0)
+    flagged = {}
+    if units["used"]:
+        flag_bytes = 4.0 * 729 * 274 * 23
+        flagged["col_reduce_g13_6"] = 2.0 * units["reduce13_rows_bytes"] + flag_bytes
+        flagged["low_reduce_count"] = (units["final_runs_bytes"] + units["final_store_bytes"]
+                                       + ntiles * 4.0 * (2 * 9 + 1))  # flags, chunk map, count
     pass_rows = []
     total_bytes = 0.0
     for name, p in passes.items():
         ms = p["ms"] / p["k"]
-        b = p["model_bytes"] + p["lbpp"] * nprimes
+        dense = p["model_bytes"] + p["lbpp"] * nprimes
+        b = flagged.get(name, dense)
         total_bytes += b
-        pass_rows.append(dict(name=name, ms=round(ms, 4), model_GB=round(b / 1e9, 3),
-                              GBps=round(b / (ms / 1e3) / 1e9, 1)))
+        row = dict(name=name, ms=round(ms, 4), model_GB=round(b / 1e9, 3), GBps=round(b / (ms / 1e3) / 1e9, 1))
+        if name in flagged:
+            row["dense_model_GB"] = round(dense / 1e9, 3)
+        pass_rows.append(row)
     dom = max(pass_rows, key=lambda r: r["ms"])
     dom_bytes = dom["model_GB"] * 1e9
     achieved = dom_bytes / (dom["ms"] / 1e3) / 1e9
@@ -616,16 +631,16 @@ def main():
         "hbm_GBps_model": total_bytes / (ms_step / 1e3) / 1e9,
         "hbm_frac_model": total_bytes / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBPS,
         "model_bytes_per_step": total_bytes,
+        "flag_units": units,
         "wall_s_timed": wall,
         "passes": pass_rows,
         "plan": {"groups": dqmc.dqmc_get_plan(ctx.ctx, n), "passes_per_step": len(pass_rows),
                  "split_top_digit": dqmc.dqmc_get_split(ctx.ctx, n),
                  "autotune_trials": [["split" if t["split"] else t["sizes"], round(t["ms"], 3)]
                                      for t in plan_trials]},
-        # achieved: the pass's model bytes (reads and writes of every word) per
-        # second; the in-place reduces skip the stores of segments that were
-        # zero as loaded, so the counter traffic can be below the model, and
-        # traffic_GBps is the measured HBM rate
+        # achieved: the pass's model bytes per second (for the flagged passes
+        # the bytes their flags select, else every word the plan reads and
+        # writes); traffic: HBM bytes by rocprofv3 counters for these sources
         "roofline": {"bound": "hbm", "kernel": dom["name"], "achieved": achieved, "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
                      "traffic": traffic, "model_bytes_per_launch": dom_bytes,

@@ -265,6 +265,7 @@ int enqueue_reduce_high(dqmc_ctx *ctx, int n, const uint32_t *tt, uint32_t flip,
     if (rc != DQMC_OK) return rc;
     const std::vector<Group> gs = groups_of(plan_sizes(ctx, n));
     const bool flags = use_row_flags(ctx, n, gs);
+    if (n == 24) ctx->flags_used = flags && tile_flags != nullptr;
     if (flags) {
         // 18 MB read, 18 MB written
         rc = run_pass(ctx, s, "flag_transpose", n, 8.0 * 729 * kFlagLowBlocks * kFlagWords, 0,
@@ -509,6 +510,7 @@ int dqmc_create(int device, dqmc_ctx **out)
     c->flags_top = nullptr;
     c->flags_low = nullptr;
     c->flags_tile = nullptr;
+    c->flags_used = false;
     c->batch_mem = nullptr;
     c->batch_cap = 0;
     c->err[0] = 0;
@@ -978,6 +980,23 @@ int dqmc_profile_read(dqmc_ctx *ctx, dqmc_pass_record *out, int cap)
     }
     ctx->nrec = 0;
     return k;
+}
+
+int dqmc_flag_units(dqmc_ctx *ctx, uint64_t *h_units)
+{
+    if (ctx == nullptr || h_units == nullptr) return DQMC_EINVAL;
+    for (int i = 0; i < 4; ++i) h_units[i] = 0;
+    if (!ctx->flags_used) return DQMC_OK;
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, DQMC_EDEVICE, "%s", "hipSetDevice failed");
+    // three counters in the scan scratch (free between calls)
+    unsigned long long *d = (unsigned long long *)ctx->sums;
+    DQMC_HIP(ctx, hipMemsetAsync(d, 0, 3 * sizeof(unsigned long long), nullptr));
+    DQMC_HIP(ctx, launch_flag_units(ctx->flags_low, ctx->flags_tile, d, nullptr));
+    unsigned long long hu[3];
+    DQMC_HIP(ctx, hipMemcpy(hu, d, sizeof(hu), hipMemcpyDeviceToHost));
+    for (int i = 0; i < 3; ++i) h_units[i] = hu[i];
+    h_units[3] = 1;
+    return DQMC_OK;
 }
 
 }  // extern "C"

@@ -401,6 +401,54 @@ hipError_t launch_tile_flags(const uint32_t *low, uint32_t *tiles, hipStream_t s
     return hipGetLastError();
 }
 
+// Bytes of the flagged passes, from the flags: rows of the reduce of digits
+// 13..18 (256 bytes, 128 in the last column block, whose upper 32 lanes lie
+// past the slot), and per tile the runs and wavefront row segments of the
+// final reduce that touch a flagged chunk (the same tests as the kernels).
+__global__ __launch_bounds__(256) void flag_units_kernel(const uint32_t *low, const uint32_t *tiles,
+                                                         unsigned long long *units)
+{
+    constexpr uint64_t nlow = 729ull * kFlagLowBlocks * kFlagWords;
+    constexpr uint64_t ntiles = 531441;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    unsigned long long rows = 0, runs = 0, stores = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nlow; i += stride) {
+        const uint32_t lb = (uint32_t)(i / kFlagWords % kFlagLowBlocks);
+        rows += (unsigned long long)__popc(low[i]) * (lb + 1 == kFlagLowBlocks ? 128u : 256u);
+    }
+    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < ntiles; t += stride) {
+        uint32_t f[kMapWords];
+        static_for<kMapWords>([&](auto ki) { f[decltype(ki)::value] = tiles[t * kMapWords + decltype(ki)::value]; });
+        auto bit = [&](uint32_t c) {
+            uint32_t w = 0;
+            static_for<kMapWords>([&](auto ki) { w = c / 32 == (uint32_t)decltype(ki)::value ? f[decltype(ki)::value] : w; });
+            return (w >> (c % 32)) & 1u;
+        };
+        for (uint32_t q = 0; q < 729; ++q) runs += (bit(24 * q / 64) | bit((24 * q + 23) / 64)) ? 96u : 0u;
+        for (uint32_t q0 = 0; q0 < 648; q0 += 64) {
+            const uint32_t qn = (648 - q0 < 64 ? 648 - q0 : 64) - 1;
+            for (uint32_t k = 0; k < 27; ++k) {
+                const uint32_t w0 = q0 + 648 * k;
+                stores += (bit(w0 / 64) | bit((w0 + qn) / 64)) ? 4u * (qn + 1) : 0u;
+            }
+        }
+    }
+    rows = wave_sum(rows);
+    runs = wave_sum(runs);
+    stores = wave_sum(stores);
+    if (lane_id() == 0) {
+        atomicAdd(&units[0], rows);
+        atomicAdd(&units[1], runs);
+        atomicAdd(&units[2], stores);
+    }
+}
+
+hipError_t launch_flag_units(const uint32_t *low, const uint32_t *tiles, unsigned long long *units, hipStream_t s)
+{
+    hipLaunchKernelGGL(flag_units_kernel, dim3(2048), dim3(256), 0, s, low, tiles, units);
+    return hipGetLastError();
+}
+
 hipError_t launch_flag_transpose(const uint32_t *top, uint32_t *low, hipStream_t s)
 {
     const uint64_t threads = kFlagItems * 32;

@@ -115,6 +115,9 @@ hipError_t launch_flag_transpose(const uint32_t *top, uint32_t *low, hipStream_t
 // superset of what it leaves) as chunk flags of the n = 24 tiles: bit k of
 // word k / 32 of tile c + 729 o = bit c of the reduce pass's block (o, k).
 hipError_t launch_tile_flags(const uint32_t *low, uint32_t *tiles, hipStream_t s);
+// Bytes the flagged passes move (see dqmc_flag_units) into units[0..2]
+// (device, zeroed by the caller).
+hipError_t launch_flag_units(const uint32_t *low, const uint32_t *tiles, unsigned long long *units, hipStream_t s);
 
 hipError_t col_setup();    // also runs chunk_setup
 hipError_t chunk_setup();  // occupancy caps of the chunked column kernel

@@ -401,7 +401,7 @@ __device__ __forceinline__ void run_digit6_to_lds(uint32_t *t, const TileRun &r,
 // the denser small tiles of a batch both cost more than they save.
 // With SPARSE, `flags` (kMapWords words, or nullptr) marks the chunks that
 // may hold a set bit: the others are zero in HBM, so their runs are not
-// loaded, and the flags stand for the chunks that were non-zero as loaded.
+// loaded.
 // f0, f1 are the words 24 w / 32 and (24 w + 23) / 32 of the flags for the
 // calling wavefront w (its 64 runs cover chunks 24 w .. 24 w + 23), loaded
 // ahead by the caller.
@@ -418,8 +418,6 @@ __device__ __forceinline__ void reduce_full_tile(uint32_t *t, uint32_t *tile, ui
         uint32_t *nlist = red + kRedWords - 1;
         TileRun r;
         if (flags != nullptr) {
-            // The LDS copy of the flags serves the last round's store
-            // decisions.
             const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
             const uint32_t k0 = 24 * wv / 32;
             const uint32_t c0 = 24 * q / kChunkWords, c1 = (24 * q + 23) / kChunkWords;
@@ -427,9 +425,10 @@ __device__ __forceinline__ void reduce_full_tile(uint32_t *t, uint32_t *tile, ui
             const bool need = q < kTileTriples && (((g0 >> (c0 % 32)) | (g1 >> (c1 % 32))) & 1u);
             if (need) load_run(r, tile, q);
             else static_for<6>([&](auto ki) { r.u[decltype(ki)::value] = make_uint4(0u, 0u, 0u, 0u); });
-            if (threadIdx.x < (uint32_t)kMapWords) innz[threadIdx.x] = flags[threadIdx.x];
-            __syncthreads();  // list length zeroed
-            run_digit6_to_lds<false>(t, r, q, q < kTileTriples, innz, blist, nlist);
+            __syncthreads();  // flags and list length zeroed before they are set
+            // the chunks non-zero as loaded (a subset of the flagged ones):
+            // the last round stores only those
+            run_digit6_to_lds<true>(t, r, q, q < kTileTriples, innz, blist, nlist);
         } else {
             __syncthreads();  // flags and list length zeroed before they are set
             if (q < kTileTriples) load_run(r, tile, q);

@@ -143,6 +143,7 @@ def load():
             "dqmc_set_split": (i32, [vp, i32, i32]),
             "dqmc_get_split": (i32, [vp, i32]),
             "dqmc_tune_save": (i32, [vp, ctypes.c_char_p]),
+            "dqmc_flag_units": (i32, [vp, ctypes.POINTER(ctypes.c_uint64)]),
             "dqmc_tune_load": (i32, [vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int32)]),
             "dqmc_profile_read": (i32, [vp, ctypes.POINTER(dqmc_pass_record), i32]),
             "dqmc_batch_autotune": (i32, [vp, ctypes.c_int32, vp, ctypes.POINTER(dqmc_batch_trial), ctypes.c_int32,
@@ -592,6 +593,14 @@ def dqmc_set_split(ctx, n: int, mode: int) -> None:
 
 def dqmc_get_split(ctx, n: int) -> bool:
     return load().dqmc_get_split(ctx, n) == 1
+
+
+def dqmc_flag_units(ctx) -> dict:
+    """Bytes of the data-dependent passes of the last flagged n = 24 call."""
+    u = (ctypes.c_uint64 * 4)()
+    _check(ctx, load().dqmc_flag_units(ctx, u))
+    return {"reduce13_rows_bytes": int(u[0]), "final_runs_bytes": int(u[1]), "final_store_bytes": int(u[2]),
+            "used": bool(u[3])}
 
 
 def dqmc_tune_save(ctx, path: str) -> None:
