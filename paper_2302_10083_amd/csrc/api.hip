@@ -195,7 +195,13 @@ int enqueue_merge(dqmc_ctx *ctx, int n, const uint32_t *tt, uint32_t flip, uint3
         const bool top = j + 1 == gs.size();
         const int mode = (top && fuse_top_reduce) ? kColMergeReduce : kColMerge;
         ColArgs c = col_args(state, n, gs[j], true);
-        if (mode == kColMergeReduce && use_row_flags(ctx, n, gs)) c.flags = ctx->flags_top;
+        if (mode == kColMergeReduce && use_row_flags(ctx, n, gs)) {
+            // slot-aligned blocks (the reduce pass's), so the flags carry over exactly
+            c.flags = ctx->flags_top;
+            c.slot_blocks = (uint32_t)kFlagLowBlocks;
+            c.nlb = kFlagTopBlocks;  // n = 24: no outer digits
+            c.nblocks = c.nlb * c.nouter;
+        }
         const int od = n - (gs[j].g0 + gs[j].size() - 1);
         const double fo = std::pow(2.0 / 3.0, od), fg = std::pow(2.0 / 3.0, gs[j].size());
         const double bytes = mode == kColMerge ? S * fo * (fg + (1.0 - fg)) : S * fo * (fg + 1.0);

@@ -114,8 +114,15 @@ __attribute__((amdgpu_waves_per_eu(MODE == kColReduce && GW == 2 ? 5 : 1))) void
     const int cw = GW == 0 ? 0 : __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64));
     const uint32_t lane = GW == 0 ? threadIdx.x : (threadIdx.x & 63);
     const uint64_t L = a.L;
-    const uint64_t l64 = (uint64_t)lb * LANES + lane;
-    const bool active = l64 < L;
+    uint64_t l64 = (uint64_t)lb * LANES + lane;
+    bool active = l64 < L;
+    if constexpr (GR == 4 && GW == 2) {
+        if (a.slot_blocks != 0) {  // blocks cut per tile slot
+            const uint32_t w = (lb % a.slot_blocks) * LANES + lane;
+            l64 = (uint64_t)kTileStride * (lb / a.slot_blocks) + w;
+            active = w < kTileStride;
+        }
+    }
     const uint32_t l = (uint32_t)l64;  // L < 2^32: plans keep g0 <= 24
     const uint32_t l4 = 4 * l;          // byte offset in a row (rows of the lanes' blocks are below 2^32 bytes)
     uint32_t *rows = a.state + L * (uint64_t)CR * ((uint64_t)cw + (uint64_t)CW * o);
@@ -334,11 +341,9 @@ int col_lanes_per_block(int gw) { return gw == 0 ? 256 : 64; }
 // 13..18 (n = 24, both groups of six digits).  An item is (ob, lb, wc): the
 // reduce pass's outer combinations o = 32 ob .. 32 ob + 31, its column block
 // lb, and its rows c = 32 wc .. 32 wc + 31.  Lane i of the item's 32 reads the
-// top pass's flag word for row c = 32 wc + i (bits over o), ORed over the one
-// or two top blocks that hold words 64 lb .. 64 lb + 63 of slot c (slot c
-// starts at word 17504 c, half a top block in for odd c: a superset of the
-// rows that hold a bit); 32 ballots transpose the 32 x 32 bits, and lane j
-// writes the word of o = 32 ob + j (bits over c).  Two items per wavefront.
+// top pass's flag word of its block (c, lb) for c = 32 wc + i (bits over o);
+// 32 ballots transpose the 32 x 32 bits, and lane j writes the word of
+// o = 32 ob + j (bits over c).  Two items per wavefront.
 constexpr uint64_t kFlagItems = (uint64_t)kFlagWords * kFlagLowBlocks * kFlagWords;
 
 __global__ __launch_bounds__(256) void flag_transpose_kernel(const uint32_t *top, uint32_t *low)
@@ -350,12 +355,7 @@ __global__ __launch_bounds__(256) void flag_transpose_kernel(const uint32_t *top
     const uint32_t ob = (uint32_t)(item / (kFlagWords * kFlagLowBlocks));
     const uint32_t c = 32 * wc + i;
     uint32_t a = 0u;
-    if (valid && c < 729u) {
-        const uint64_t w = (uint64_t)kTileStride * c + 64ull * lb;  // the segment's first word in the top rows
-        const uint64_t b3 = w / 64;
-        a = top[b3 * kFlagWords + ob];
-        if (w % 64 != 0 && b3 + 1 < kFlagTopBlocks) a |= top[(b3 + 1) * kFlagWords + ob];
-    }
+    if (valid && c < 729u) a = top[((uint64_t)c * kFlagLowBlocks + lb) * kFlagWords + ob];
     const bool hi = (threadIdx.x % 64) >= 32;
     uint32_t out = 0u;
     for (uint32_t j = 0; j < 32; ++j) {

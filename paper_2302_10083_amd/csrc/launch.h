@@ -91,9 +91,16 @@ struct ColArgs {
     uint64_t nouter;     // outer (above the group) combinations launched
     uint64_t nblocks;    // nlb * nouter
     int outer_binary;    // 1: outer index enumerates binary digit combos
+    // Column blocks cut per tile slot (col_kernel<4, 2> only): 0, or the
+    // blocks per slot (kFlagLowBlocks): block lb covers words 64 (lb mod
+    // slot_blocks) .. of slot lb / slot_blocks of the rows, the last one of a
+    // slot half full.
+    uint32_t slot_blocks;
     // Row flags (col_kernel<4, 2> only; nullptr: none).  The merge+reduce
     // mode writes, per column block, a bit per row of its 729 (set: the row's
-    // 64 words hold a set bit after the pass), kFlagWords words per block.
+    // words of the block hold a set bit after the pass), kFlagWords words per
+    // block; it runs with slot_blocks set, so that its blocks are those of
+    // the reduce pass.
     // The reduce mode reads kFlagWords words per block in its own row order
     // (launch_flag_transpose) and loads and stores only the flagged rows.
     uint32_t *flags;
@@ -101,15 +108,14 @@ struct ColArgs {
 
 // Row flags from the top group's merge+reduce (digits 19..24) to the reduce
 // of digits 13..18 at n = 24 (plan [6, 6]): both passes have 729 rows per
-// column block.  The top pass's block b (words 64 b .. 64 b + 63 of a row,
-// rows L3 = 729 kTileStride words apart) is the 64-word segment of each of
-// its rows; the reduce pass's block (lb, o) covers words 64 lb .. of the
-// slots c (rows kTileStride words apart) of the 729 slots above o.
-constexpr uint32_t kFlagWords = 23;                    // 729 bits
-constexpr uint64_t kFlagTopBlocks = (729ull * kTileStride + 63) / 64;  // 199382
+// column block.  The top pass's block (c, lb) (slot-aligned: words 64 lb ..
+// 64 lb + 63 of slot c, in each of its rows 729 kTileStride words apart) is
+// the reduce pass's block (lb, o) in its row c for every o.
+constexpr uint32_t kFlagWords = 23;                                   // 729 bits
 constexpr uint64_t kFlagLowBlocks = (kTileStride + 63) / 64;          // 274 per slot
+constexpr uint64_t kFlagTopBlocks = 729ull * kFlagLowBlocks;          // 199746
 // Bit o of word c / 32 of block (o, lb) of the reduce pass = bit o of the
-// top pass's block(s) holding words 64 lb .. 64 lb + 63 of slot c.
+// top pass's block (c, lb).
 hipError_t launch_flag_transpose(const uint32_t *top, uint32_t *low, hipStream_t s);
 // The reduce pass's row flags (rows that may hold a bit as it loads them, a
 // superset of what it leaves) as chunk flags of the n = 24 tiles: bit k of
