@@ -38,29 +38,53 @@ __device__ __forceinline__ uint32_t binary_cover(int cw)
     return cover;
 }
 
+// The binary wave combinations in `cover` (a non-empty set of 2^s of them) as
+// K LDS word offsets of their first exchange row (plus the lane), listed
+// cyclically when fewer than K: AND being idempotent, a wavefront then reads
+// K rows per register row at offsets fixed for the whole pass, with no
+// per-row test of the cover (which the compiler turns into a branch and a
+// wait for each LDS read).
+template <int K, int BW>
+__device__ __forceinline__ void cover_bases(uint32_t cover, uint32_t stride, uint32_t lane, uint32_t (&va)[K])
+{
+    const uint32_t m = (uint32_t)__builtin_popcount(cover);  // a power of two
+    static_for<K>([&](auto ki) {
+        const uint32_t want = (uint32_t)decltype(ki)::value & (m - 1u);
+        uint32_t pick = 0, seen = 0;
+        for (int b = 0; b < BW; ++b) {
+            const bool on = (cover >> b) & 1u;
+            pick = (on && seen == want) ? (uint32_t)b : pick;
+            seen += on ? 1u : 0u;
+        }
+        va[decltype(ki)::value] = pick * stride + lane;
+    });
+}
+
 // x &= ~M(w) on all 3^GR register rows, where w is the wave combination whose
 // covered binary waves are `cover`: its binary rows are the AND of theirs (in
 // xch, as the merge step left them) and its other rows follow by register
 // merges.  Built one third of the top register digit at a time (top digit 0,
 // 1, then * = the AND of the two) to hold 2 * 3^(GR-1) extra registers
-// instead of 3^GR.
+// instead of 3^GR.  w differs from this wave in one binary digit, so it
+// covers at most 2^(GW-1) binary waves.
 template <int GR, int GW>
 __device__ __forceinline__ void reduce_by_sibling(uint32_t (&x)[pow3(GR)], const uint32_t *xch, uint32_t cover,
                                                   uint32_t lane)
 {
     constexpr int CL = (int)pow3(GR - 1);
     constexpr int BR = 1 << GR, BL = 1 << (GR - 1);
+    constexpr int K = 1 << (GW - 1);
+    uint32_t va[K];
+    cover_bases<K, 1 << GW>(cover, BR * 64, lane, va);
     uint32_t y0[CL], y1[CL];
     static_for<CL>([&](auto ci) {
         constexpr int c = decltype(ci)::value;
         if constexpr (all_binary(c, GR - 1)) {
             uint32_t a0 = ~0u, a1 = ~0u;
-            for (int b = 0; b < (1 << GW); ++b) {
-                if ((cover >> b) & 1u) {
-                    a0 &= xch[(b * BR + bin_index(c, GR - 1)) * 64 + lane];
-                    a1 &= xch[(b * BR + BL + bin_index(c, GR - 1)) * 64 + lane];
-                }
-            }
+            static_for<K>([&](auto ki) {
+                a0 &= xch[va[decltype(ki)::value] + bin_index(c, GR - 1) * 64];
+                a1 &= xch[va[decltype(ki)::value] + (BL + bin_index(c, GR - 1)) * 64];
+            });
             y0[c] = a0;
             y1[c] = a1;
         }
@@ -162,13 +186,13 @@ __attribute__((amdgpu_waves_per_eu(MODE == kColReduce && GW == 2 ? 5 : 1))) void
             __syncthreads();
             if (!cw_binary) {
                 // AND over the binary wave combinations covered by cw
-                const uint32_t cover = binary_cover<GW>(cw);
+                uint32_t va[BW];
+                cover_bases<BW, BW>(binary_cover<GW>(cw), BR * 64, lane, va);
                 static_for<CR>([&](auto ci) {
                     constexpr int c = decltype(ci)::value;
                     if constexpr (all_binary(c, GR)) {
                         uint32_t acc = ~0u;
-                        for (int b = 0; b < BW; ++b)
-                            if ((cover >> b) & 1u) acc &= xch[(b * BR + bin_index(c, GR)) * 64 + lane];
+                        static_for<BW>([&](auto ki) { acc &= xch[va[decltype(ki)::value] + bin_index(c, GR) * 64]; });
                         x[c] = acc;
                     }
                 });
