@@ -85,29 +85,17 @@ __global__ __launch_bounds__(low_threads<MODE>()) __attribute__((amdgpu_waves_pe
         if constexpr (MODE == kLowReduceCount) {
             // always a full tile here (n > 12)
             if (a.tile_flags != nullptr) {
-                // kFlaggedTiles consecutive tiles per workgroup; each
-                // wavefront loads the flag words of all of them first (scalar
-                // loads), so only the first tile waits for its flags
-                const uint64_t first = tile * kFlaggedTiles;
+                // one tile per workgroup (more, with the flags of all read
+                // first, was slower: a tile's run loads then wait for the
+                // previous tile's stores, vmcnt retiring in order)
+                const uint32_t *fw = a.tile_flags + tile * kMapWords;
+                // the flag words of this wavefront's 64 runs (chunks 24 w .. 24 w + 23)
                 const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
                 const uint32_t k0 = 24 * wv / 32, k1 = (24 * wv + 23) / 32;
-                uint32_t f0[kFlaggedTiles], f1[kFlaggedTiles];
-                static_for<kFlaggedTiles>([&](auto ki) {
-                    constexpr int k = decltype(ki)::value;
-                    const bool in = first + k < a.ntiles;
-                    const uint32_t *fw = a.tile_flags + (first + k) * kMapWords;
-                    f0[k] = in && k0 < (uint32_t)kMapWords ? fw[k0] : 0u;
-                    f1[k] = in && k1 < (uint32_t)kMapWords ? fw[k1] : 0u;
-                });
-                static_for<kFlaggedTiles>([&](auto ki) {
-                    constexpr int k = decltype(ki)::value;
-                    const uint64_t tk = first + k;
-                    if (tk < a.ntiles) {
-                        if (k > 0) __syncthreads();  // the LDS tile and `red` are reused
-                        reduce_full_tile<true>(t, a.state + tk * a.ts, a.counts + tk, a.chunkmap + tk * kMapWords, red,
-                                               a.tile_flags + tk * kMapWords, f0[k], f1[k]);
-                    }
-                });
+                const uint32_t f0 = k0 < (uint32_t)kMapWords ? fw[k0] : 0u;
+                const uint32_t f1 = k1 < (uint32_t)kMapWords ? fw[k1] : 0u;
+                reduce_full_tile<true>(t, a.state + tile * a.ts, a.counts + tile, a.chunkmap + tile * kMapWords, red,
+                                       fw, f0, f1);
                 return;
             }
             reduce_full_tile<true>(t, a.state + tile * a.ts, a.counts + tile, a.chunkmap + tile * kMapWords, red);
@@ -156,12 +144,9 @@ hipError_t launch_low(int mode, const LowArgs &a, uint64_t nblocks, hipStream_t 
     case kLowPrimesTT:
         hipLaunchKernelGGL(low_kernel<kLowPrimesTT>, grid, dim3(low_threads<kLowPrimesTT>()), lds, s, a);
         break;
-    case kLowReduceCount: {
-        // with chunk flags, kFlaggedTiles tiles per workgroup
-        const dim3 g(a.tile_flags != nullptr ? (uint32_t)((nblocks + kFlaggedTiles - 1) / kFlaggedTiles) : grid.x);
-        hipLaunchKernelGGL(low_kernel<kLowReduceCount>, g, dim3(low_threads<kLowReduceCount>()), lds, s, a);
+    case kLowReduceCount:
+        hipLaunchKernelGGL(low_kernel<kLowReduceCount>, grid, dim3(low_threads<kLowReduceCount>()), lds, s, a);
         break;
-    }
     case kLowCount:
         hipLaunchKernelGGL(low_kernel<kLowCount>, grid, dim3(low_threads<kLowCount>()), lds, s, a);
         break;

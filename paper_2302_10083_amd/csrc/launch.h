@@ -51,7 +51,6 @@ struct LowArgs {
 };
 
 constexpr int kLowThreads = 256;
-constexpr int kFlaggedTiles = 4;  // tiles per workgroup of the final reduce with chunk flags
 
 hipError_t low_setup();
 

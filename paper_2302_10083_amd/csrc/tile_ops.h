@@ -194,26 +194,20 @@ constexpr int kRawBufferWord3 = 0x00020000;
 // in LDS): thread q owns column q, reduces it, and writes it to HBM (the prime
 // bitmap); consecutive threads write consecutive words.  It also builds the
 // tile summary in `red` (zeroed before): red[0] = set bits, red[1..] = map of
-// the non-zero 64-word chunks.  The tile is reduced in place in HBM and a
-// Reduce only clears bits, so a wavefront's 64-word store is skipped when
-// every 64-word chunk it overlaps was zero as loaded (`innz`): those words are
-// zero already.
+// the non-zero 64-word chunks.
 // A wavefront's words of row k are q0 + 648k .. q0 + 648k + 63 (q0 a multiple
 // of 64), so they start at 8 (k mod 8) inside a chunk and lie in chunks c(k)
-// and c(k) + 1.  Everything per row is wave-uniform: the store decisions are
-// taken once per wavefront (lane k decides row k, one ballot), the stores are
-// raw buffer stores with the row offset in a scalar register, and the chunk
-// map is gathered as two bits per row in scalar registers (work only for rows
-// with a set bit), written at the end by lane k for row k.
-template <bool SKIP_ZERO>
-__device__ __forceinline__ void last_round_to_hbm(uint32_t *t, uint32_t *dst, uint32_t *red, const uint32_t *innz)
+// and c(k) + 1.  Everything per row is wave-uniform: the stores are raw buffer
+// stores with the row offset in a scalar register, and the chunk map is
+// gathered as two bits per row in scalar registers (work only for rows with a
+// set bit), written at the end by lane k for row k.
+__device__ __forceinline__ void last_round_to_hbm(uint32_t *t, uint32_t *dst, uint32_t *red)
 {
     constexpr uint32_t S = kRowWords;  // 648
     const uint32_t q = threadIdx.x, lane = lane_id();
     const uint32_t q0 = __builtin_amdgcn_readfirstlane(q & ~63u);  // the wavefront's first column
     if (q0 >= S) return;                                         // wave-uniform
     const bool mine = q < S;                                     // the last wavefront holds 8 columns
-    const uint32_t qn = (S - q0 < 64 ? S - q0 : 64) - 1;         // its last column, relative
     uint32_t x[27], any = 0;
     // lanes past the last column read column q0's words and are zeroed
     const uint32_t qc = mine ? q : q0;
@@ -221,15 +215,9 @@ __device__ __forceinline__ void last_round_to_hbm(uint32_t *t, uint32_t *dst, ui
     if (q0 + 64 > S) static_for<27>([&](auto ci) { x[decltype(ci)::value] = mine ? x[decltype(ci)::value] : 0u; });
     static_for<27>([&](auto ci) { any |= x[decltype(ci)::value]; });
     if (__ballot(any != 0u) != 0) reg_reduce<3>(x);  // zero columns stay zero
-    // row lk = lane (lanes 0..26): its chunks, and whether it is stored
+    // row lk = lane (lanes 0..26): its first chunk
     const uint32_t lk = lane < 27u ? lane : 0u;
     const uint32_t ck = (q0 + lk * S) / kChunkWords;
-    uint32_t rows = ~0u;  // bit k: store row k
-    if constexpr (SKIP_ZERO) {
-        const uint32_t ce = (q0 + lk * S + qn) / kChunkWords;
-        const uint32_t f = (innz[ck / 32] >> (ck % 32)) | (innz[ce / 32] >> (ce % 32));
-        rows = (uint32_t)__ballot(lane < 27u && (f & 1u) != 0u);
-    }
     // the tile's words in HBM as a raw buffer: row k at scalar offset 2592 k;
     // lanes past the last column get an offset beyond the tile, so their
     // stores are dropped by the buffer's range check
@@ -241,7 +229,7 @@ __device__ __forceinline__ void last_round_to_hbm(uint32_t *t, uint32_t *dst, ui
         constexpr uint32_t k = decltype(ci)::value;
         constexpr uint32_t split = 64 - 8 * (k % 8);  // lanes below it are in chunk c(k)
         constexpr uint64_t lo = split >= 64 ? ~0ull : (1ull << (split & 63u)) - 1ull;
-        if ((rows >> k) & 1u) __builtin_amdgcn_raw_buffer_store_b32(x[k], rs, voff, (int)(4 * k * S), 0);
+        __builtin_amdgcn_raw_buffer_store_b32(x[k], rs, voff, (int)(4 * k * S), 0);
         c += __popc(x[k]);
         const uint64_t m = __ballot(x[k] != 0u);
         if (m != 0) {
@@ -310,6 +298,96 @@ __device__ __forceinline__ void put_block(uint32_t *t, uint32_t blk, const uint3
     uint4 *dst = reinterpret_cast<uint4 *>(t + padded_word(kBlockWords * blk));
     dst[0] = make_uint4(b[0], b[1], b[2], b[3]);
     dst[1] = make_uint4(b[4], b[5], b[6], b[7]);
+}
+
+// Block blk of a padded LDS tile, into registers.
+__device__ __forceinline__ void get_block(const uint32_t *t, uint32_t blk, uint32_t (&b)[kBlockWords])
+{
+    const uint4 *src = reinterpret_cast<const uint4 *>(t + padded_word(kBlockWords * blk));
+    const uint4 lo = src[0], hi = src[1];
+    b[0] = lo.x; b[1] = lo.y; b[2] = lo.z; b[3] = lo.w;
+    b[4] = hi.x; b[5] = hi.y; b[6] = hi.z; b[7] = hi.w;
+}
+
+// Blocks per thread in the block-list reduce: 768 threads cover the 2187
+// blocks of a tile in three.
+constexpr int kListSlots = 3;
+
+// Reduce of digits 1..5 and 7..12 on the blocks of the list (those non-zero
+// after digit 6; the others stay zero) as one step (reading 7 of the design
+// notes: a group of dimensions reduced at once, against the values the
+// previous groups left, gives the same primes as one dimension after
+// another): block b keeps its in-block reduce (Sec. 4.2, digits 1..5) less
+// what its * neighbours along digits 7..12 hold, all read as digit 6 left
+// them.  Reads and writes are split by a barrier; every thread calls it.
+__device__ __forceinline__ void reduce_block_list(uint32_t *t, const uint16_t *blist, uint32_t nb)
+{
+    uint32_t res[kListSlots][kBlockWords];
+    uint32_t blk[kListSlots];
+    static_for<kListSlots>([&](auto si) {
+        constexpr int sl = decltype(si)::value;
+        const uint32_t i = threadIdx.x + sl * blockDim.x;
+        blk[sl] = i < nb ? (uint32_t)blist[i] : 0u;
+        if (i < nb) {
+            uint32_t v[kBlockWords], kill[kBlockWords] = {};
+            get_block(t, blk[sl], v);
+            uint32_t rest = blk[sl] / 3;  // digits 7..12 of the block index
+            static_for<6>([&](auto di) {
+                constexpr uint32_t p = (uint32_t)pow3(decltype(di)::value + 1);
+                const uint32_t d = rest % 3;
+                rest /= 3;
+                if (d != 2u) {
+                    uint32_t u[kBlockWords];
+                    get_block(t, blk[sl] + (2u - d) * p, u);
+                    static_for<kBlockWords>([&](auto wi) { kill[decltype(wi)::value] |= u[decltype(wi)::value]; });
+                }
+            });
+            block_reduce(v);
+            static_for<kBlockWords>([&](auto wi) {
+                constexpr int w = decltype(wi)::value;
+                res[sl][w] = v[w] & ~kill[w];
+            });
+        }
+    });
+    lds_barrier();  // every read of the digit-6 values is done
+    static_for<kListSlots>([&](auto si) {
+        constexpr int sl = decltype(si)::value;
+        if (threadIdx.x + sl * blockDim.x < nb) put_block(t, blk[sl], res[sl]);
+    });
+}
+
+// The tile's chunks that were non-zero as loaded (`innz`), stored from the
+// padded LDS tile to HBM at dst (the other chunks were zero there and stay
+// zero), with the tile summary in red: red[0] += set bits, red[1 + k / 32]
+// bit k for the chunks non-zero now.  Wavefront w takes chunks 23 w .. 23 w +
+// 22 (12 wavefronts); lane j holds word j of a chunk, so each store is one
+// 256-byte segment.
+__device__ __forceinline__ void store_marked_chunks(const uint32_t *t, uint32_t *dst, uint32_t *red,
+                                                    const uint32_t *innz)
+{
+    constexpr uint32_t kPer = (kTileChunks + 11) / 12;  // 23
+    const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x / 64), lane = lane_id();
+    const uint32_t k0 = wv * kPer;
+    if (k0 >= (uint32_t)kTileChunks) return;
+    const uint32_t a0 = __builtin_amdgcn_readfirstlane(innz[k0 / 32]);
+    const uint32_t a1 = k0 / 32 + 1 < (uint32_t)kMapWords ? __builtin_amdgcn_readfirstlane(innz[k0 / 32 + 1]) : 0u;
+    const uint32_t nk = (uint32_t)kTileChunks - k0 < kPer ? (uint32_t)kTileChunks - k0 : kPer;
+    // bit i: chunk k0 + i is marked
+    uint32_t bits = (uint32_t)((((uint64_t)a1 << 32) | a0) >> (k0 % 32)) & ((1u << nk) - 1u);
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(dst, 0, (int)(kTileWords * 4), kRawBufferWord3);
+    uint32_t c = 0;
+    while (bits != 0u) {
+        const uint32_t k = k0 + (uint32_t)__builtin_ctz(bits);
+        bits &= bits - 1u;
+        const uint32_t w = k * kChunkWords + lane;
+        const bool in = w < kTileWords;  // the last chunk holds 24 words
+        const uint32_t v = in ? t[padded_word(w)] : 0u;
+        c += __popc(v);
+        if (__ballot(v != 0u) != 0 && lane == 0) atomicOr(&red[1 + k / 32], 1u << (k % 32));
+        __builtin_amdgcn_raw_buffer_store_b32(v, rs, in ? (int)(4 * w) : 0x40000000, 0, 0);
+    }
+    c = wave_sum32(c);
+    if (lane == 0 && c != 0) atomicAdd(&red[0], c);
 }
 
 // Reduce of digit 6 across the three blocks of run q and of digits 1..5
@@ -388,18 +466,19 @@ __device__ __forceinline__ void run_digit6_to_lds(uint32_t *t, const TileRun &r,
 
 // Final Reduce of a full tile in HBM (kTileWords words at `tile`, 16-byte
 // aligned; 768 threads; kReduceTileBytes of LDS at t, rows padded as
-// described at kRowStride): thread q < 729 loads run q; digit 6 and digits 1..5
-// are reduced on the way into LDS, digits 7..9 in LDS, digits 10..12 in the
-// last round straight back to HBM (the prime bitmap).  It also writes the
-// tile summary: *count = its set bits, map[0..kMapWords) = its non-zero
-// 64-word chunks.  `red` is kRedWords words of LDS.
+// described at kRowStride): thread q < 729 loads run q and digit 6 is reduced
+// on the way into LDS.  It also writes the tile summary: *count = its set
+// bits, map[0..kMapWords) = its non-zero 64-word chunks.  `red` is kRedWords
+// words of LDS.
+// Without SPARSE (the denser small tiles of a batch) digits 1..5 are reduced
+// on the way in too, digits 7..9 in LDS, and digits 10..12 in the last round
+// straight back to HBM, over every word of the tile.
 // SPARSE is for a single large function, whose tiles are mostly zero by this
-// pass: the in-block reduce of digits 1..5 runs only on the blocks that are
-// non-zero after digit 6 (a Reduce leaves a zero block zero), taken from a
-// list that needs kBlockListBytes of LDS after the padded tile; and the stores of
-// chunks that were zero as loaded are left out (see last_round_to_hbm).  On
-// the denser small tiles of a batch both cost more than they save.
-// With SPARSE, `flags` (kMapWords words, or nullptr) marks the chunks that
+// pass.  The blocks non-zero after digit 6 are listed (kBlockListBytes of LDS
+// after the padded tile); each gets digits 1..5 and 7..12 in one step
+// (reduce_block_list), and only the chunks non-zero as loaded are stored
+// (store_marked_chunks): a Reduce only clears bits, so the others are zero in
+// HBM already.  `flags` (kMapWords words, or nullptr) marks the chunks that
 // may hold a set bit: the others are zero in HBM, so their runs are not
 // loaded.
 // f0, f1 are the words 24 w / 32 and (24 w + 23) / 32 of the flags for the
@@ -427,7 +506,7 @@ __device__ __forceinline__ void reduce_full_tile(uint32_t *t, uint32_t *tile, ui
             else static_for<6>([&](auto ki) { r.u[decltype(ki)::value] = make_uint4(0u, 0u, 0u, 0u); });
             __syncthreads();  // flags and list length zeroed before they are set
             // the chunks non-zero as loaded (a subset of the flagged ones):
-            // the last round stores only those
+            // only those are stored
             run_digit6_to_lds<true>(t, r, q, q < kTileTriples, innz, blist, nlist);
         } else {
             __syncthreads();  // flags and list length zeroed before they are set
@@ -435,15 +514,13 @@ __device__ __forceinline__ void reduce_full_tile(uint32_t *t, uint32_t *tile, ui
             run_digit6_to_lds<true>(t, r, q, q < kTileTriples, innz, blist, nlist);
         }
         __syncthreads();
-        const uint32_t nb = *nlist;
-        for (uint32_t i = threadIdx.x; i < nb; i += blockDim.x) {
-            const uint32_t blk = blist[i];
-            const uint4 *src = reinterpret_cast<const uint4 *>(t + padded_word(kBlockWords * blk));
-            const uint4 lo = src[0], hi = src[1];
-            uint32_t v[kBlockWords] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
-            block_reduce(v);
-            put_block(t, blk, v);
-        }
+        reduce_block_list(t, blist, *nlist);
+        __syncthreads();
+        store_marked_chunks(t, tile, red, innz);
+        __syncthreads();
+        if (threadIdx.x == 0) *count = red[0];
+        if (threadIdx.x < kMapWords) map[threadIdx.x] = red[1 + threadIdx.x];
+        return;
     } else {
         if (q < kTileTriples) {
             TileRun r;
@@ -469,7 +546,7 @@ __device__ __forceinline__ void reduce_full_tile(uint32_t *t, uint32_t *tile, ui
         });
     }
     __syncthreads();
-    last_round_to_hbm<SPARSE>(t, tile, red, innz);  // digits 10..12
+    last_round_to_hbm(t, tile, red);  // digits 10..12
     __syncthreads();
     if (threadIdx.x == 0) *count = red[0];
     if (threadIdx.x < kMapWords) map[threadIdx.x] = red[1 + threadIdx.x];
