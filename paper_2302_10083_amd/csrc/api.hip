@@ -226,9 +226,12 @@ int enqueue_summary(dqmc_ctx *ctx, int n, int mode, uint32_t *state, hipStream_t
     a.chunkmap += tile0 * kMapWords;
     const double S = state_bytes(n);
     const bool reduce = mode == kLowReduceCount;
+    // with chunk flags: the compact kernel, then the tiles it deferred
+    const bool compact = reduce && tile_flags != nullptr && ctx->deferred != nullptr && n > kLowDigits;
+    if (compact) a.deferred = ctx->deferred;
     return run_pass(ctx, s, reduce ? "low_reduce_count" : "low_count", n,
                     (reduce ? 2 * S : S) + a.ntiles * 4.0 * (1 + kMapWords), 0,
-                    [&] { return launch_low(mode, a, a.ntiles, s); });
+                    [&] { return compact ? launch_low_compact(a, s) : launch_low(mode, a, a.ntiles, s); });
 }
 
 // Scan of the tile counts (starting at *base when base is given) and the
@@ -292,7 +295,7 @@ int enqueue_reduce_high(dqmc_ctx *ctx, int n, const uint32_t *tt, uint32_t flip,
         // the reduce pass's row flags as chunk flags of the tiles (18 MB
         // read, 19 MB written)
         rc = run_pass(ctx, s, "tile_flags", n, 4.0 * 729 * kFlagLowBlocks * kFlagWords + 4.0 * pow3(12) * kMapWords,
-                      0, [&] { return launch_tile_flags(ctx->flags_low, ctx->flags_tile, s); });
+                      0, [&] { return launch_tile_flags(ctx->flags_low, ctx->flags_tile, ctx->deferred, s); });
         if (rc != DQMC_OK) return rc;
         *tile_flags = ctx->flags_tile;
     }
@@ -516,6 +519,7 @@ int dqmc_create(int device, dqmc_ctx **out)
     c->flags_top = nullptr;
     c->flags_low = nullptr;
     c->flags_tile = nullptr;
+    c->deferred = nullptr;
     c->flags_used = false;
     c->batch_mem = nullptr;
     c->batch_cap = 0;
@@ -536,7 +540,8 @@ int dqmc_create(int device, dqmc_ctx **out)
         hipMalloc((void **)&c->run, 2 * sizeof(uint64_t)) != hipSuccess ||
         hipMalloc((void **)&c->flags_top, kFlagTopBlocks * kFlagWords * sizeof(uint32_t)) != hipSuccess ||
         hipMalloc((void **)&c->flags_low, 729 * kFlagLowBlocks * kFlagWords * sizeof(uint32_t)) != hipSuccess ||
-        hipMalloc((void **)&c->flags_tile, pow3(12) * kMapWords * sizeof(uint32_t)) != hipSuccess) {
+        hipMalloc((void **)&c->flags_tile, pow3(12) * kMapWords * sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc((void **)&c->deferred, (pow3(12) + 1) * sizeof(uint32_t)) != hipSuccess) {
         dqmc_destroy(c);
         return DQMC_ENOMEM;
     }
@@ -560,6 +565,7 @@ void dqmc_destroy(dqmc_ctx *ctx)
     if (ctx->flags_top) (void)hipFree(ctx->flags_top);
     if (ctx->flags_low) (void)hipFree(ctx->flags_low);
     if (ctx->flags_tile) (void)hipFree(ctx->flags_tile);
+    if (ctx->deferred) (void)hipFree(ctx->deferred);
     if (ctx->batch_mem) (void)hipFree(ctx->batch_mem);
     delete ctx;
 }

@@ -24,6 +24,7 @@ struct dqmc_ctx {
     uint32_t *flags_top;
     uint32_t *flags_low;
     uint32_t *flags_tile;  // the same as chunk flags of the final reduce (3^12 tiles of kMapWords words)
+    uint32_t *deferred;    // final reduce: count and list of the tiles the compact kernel left (3^12 + 1 words)
     bool flags_used;       // the last n = 24 computation wrote them
     void *batch_mem;     // dqmc_primes_batch: scratch for up to batch_cap jobs (grown on demand)
     uint32_t batch_cap;

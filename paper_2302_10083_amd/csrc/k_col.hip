@@ -398,8 +398,10 @@ __global__ __launch_bounds__(256) void flag_transpose_kernel(const uint32_t *top
 // lw of tile 32 cb + j + 729 o.  Two items per wavefront.
 constexpr uint64_t kTileFlagItems = 729ull * kFlagWords * kMapWords;
 
-__global__ __launch_bounds__(256) void tile_flags_kernel(const uint32_t *low, uint32_t *tiles)
+__global__ __launch_bounds__(256) void tile_flags_kernel(const uint32_t *low, uint32_t *tiles, uint32_t *deferred)
 {
+    // the final reduce's list of deferred tiles starts empty
+    if (deferred != nullptr && blockIdx.x == 0 && threadIdx.x == 0) deferred[0] = 0u;
     const uint64_t item = ((uint64_t)blockIdx.x * 256 + threadIdx.x) / 32;
     const uint32_t i = threadIdx.x % 32;
     const bool valid = item < kTileFlagItems;
@@ -418,10 +420,11 @@ __global__ __launch_bounds__(256) void tile_flags_kernel(const uint32_t *low, ui
     if (valid && c < 729u) tiles[((uint64_t)o * 729 + c) * kMapWords + lw] = out;
 }
 
-hipError_t launch_tile_flags(const uint32_t *low, uint32_t *tiles, hipStream_t s)
+hipError_t launch_tile_flags(const uint32_t *low, uint32_t *tiles, uint32_t *deferred, hipStream_t s)
 {
     const uint64_t threads = kTileFlagItems * 32;
-    hipLaunchKernelGGL(tile_flags_kernel, dim3((uint32_t)((threads + 255) / 256)), dim3(256), 0, s, low, tiles);
+    hipLaunchKernelGGL(tile_flags_kernel, dim3((uint32_t)((threads + 255) / 256)), dim3(256), 0, s, low, tiles,
+                       deferred);
     return hipGetLastError();
 }
 

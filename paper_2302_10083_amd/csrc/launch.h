@@ -48,6 +48,10 @@ struct LowArgs {
     // chunks that may hold a set bit (the others are zero in the state), or
     // nullptr
     const uint32_t *tile_flags;
+    // final reduce with chunk flags: tiles left to the full-tile kernel, count
+    // at [0] and tile indices from [1] (written by the compact kernel, read by
+    // the full-tile kernel; nullptr otherwise)
+    uint32_t *deferred;
 };
 
 constexpr int kLowThreads = 256;
@@ -68,6 +72,10 @@ hipError_t launch_list(int n, const uint32_t *state, uint32_t tw, uint32_t ts, u
                        const uint32_t *chunkmap, const uint64_t *offs, uint64_t *list, uint64_t cap, hipStream_t s,
                        uint64_t rho0 = 0);
 hipError_t launch_low(int mode, const LowArgs &a, uint64_t nblocks, hipStream_t s);
+// Final reduce of full tiles with chunk flags (a.tile_flags and a.deferred
+// set): the compact kernel on every tile, then the full-tile kernel on the
+// tiles it deferred (more non-zero blocks than its LDS holds).
+hipError_t launch_low_compact(const LowArgs &a, hipStream_t s);
 
 // High-digit groups: one pass applies Merge and/or Reduce for a group of
 // consecutive digits g0 .. g0+GR+GW-1 (g0 >= 13) with GR digits held in
@@ -119,7 +127,7 @@ hipError_t launch_flag_transpose(const uint32_t *top, uint32_t *low, hipStream_t
 // The reduce pass's row flags (rows that may hold a bit as it loads them, a
 // superset of what it leaves) as chunk flags of the n = 24 tiles: bit k of
 // word k / 32 of tile c + 729 o = bit c of the reduce pass's block (o, k).
-hipError_t launch_tile_flags(const uint32_t *low, uint32_t *tiles, hipStream_t s);
+hipError_t launch_tile_flags(const uint32_t *low, uint32_t *tiles, uint32_t *deferred, hipStream_t s);
 // Bytes the flagged passes move (see dqmc_flag_units) into units[0..2]
 // (device, zeroed by the caller).
 hipError_t launch_flag_units(const uint32_t *low, const uint32_t *tiles, unsigned long long *units, hipStream_t s);
