@@ -494,12 +494,12 @@ int dqmc_profile_read(dqmc_ctx *ctx, dqmc_pass_record *out, int cap);
  * used row and chunk flags (the default plan [6, 6]): the reduce of digits
  * 13..18 loads and stores only the row segments flagged by the top group's
  * pass, and the final reduce loads only the runs of three blocks that touch a
- * flagged 64-word chunk, and stores only wavefront row segments that touch a
- * chunk it found non-zero (a subset of the flagged ones).
+ * flagged 64-word chunk, and stores only the chunks it found non-zero as
+ * loaded (a subset of the flagged ones).
  * h_units (host, 4 entries): [0] bytes of the rows the reduce of digits 13..18
  * loads (it stores the same rows), [1] bytes of the runs the final reduce
- * loads, [2] bytes of the row segments that touch a flagged chunk (a bound on
- * the final reduce's stores), [3] 1 if the last n = 24
+ * loads, [2] bytes of the flagged chunks (a bound on the final reduce's
+ * stores), [3] 1 if the last n = 24
  * computation used the flags (else all 0).  Waits for the context's default
  * stream work it enqueues; call after the computation has finished.  Errors:
  * DQMC_EINVAL (NULL), DQMC_EDEVICE. */

@@ -430,8 +430,8 @@ hipError_t launch_tile_flags(const uint32_t *low, uint32_t *tiles, uint32_t *def
 
 // Bytes of the flagged passes, from the flags: rows of the reduce of digits
 // 13..18 (256 bytes, 128 in the last column block, whose upper 32 lanes lie
-// past the slot), and per tile the runs and wavefront row segments of the
-// final reduce that touch a flagged chunk (the same tests as the kernels).
+// past the slot), and per tile the runs of the final reduce that touch a
+// flagged chunk (the same test as the kernels) and the flagged chunks.
 __global__ __launch_bounds__(256) void flag_units_kernel(const uint32_t *low, const uint32_t *tiles,
                                                          unsigned long long *units)
 {
@@ -452,13 +452,10 @@ __global__ __launch_bounds__(256) void flag_units_kernel(const uint32_t *low, co
             return (w >> (c % 32)) & 1u;
         };
         for (uint32_t q = 0; q < 729; ++q) runs += (bit(24 * q / 64) | bit((24 * q + 23) / 64)) ? 96u : 0u;
-        for (uint32_t q0 = 0; q0 < 648; q0 += 64) {
-            const uint32_t qn = (648 - q0 < 64 ? 648 - q0 : 64) - 1;
-            for (uint32_t k = 0; k < 27; ++k) {
-                const uint32_t w0 = q0 + 648 * k;
-                stores += (bit(w0 / 64) | bit((w0 + qn) / 64)) ? 4u * (qn + 1) : 0u;
-            }
-        }
+        // the final reduce stores the chunks non-zero as loaded, a subset of
+        // the flagged ones (the last chunk holds 24 words)
+        for (uint32_t k = 0; k < (uint32_t)kTileChunks; ++k)
+            stores += bit(k) ? (k + 1 == (uint32_t)kTileChunks ? 96u : 256u) : 0u;
     }
     rows = wave_sum(rows);
     runs = wave_sum(runs);
