@@ -342,10 +342,10 @@ void batch_reduce_kernel(const dqmc_job *jobs, BatchScratch s)
     const uint32_t nitems = hl[kHSegSize + kSegReduce];
     if (blockIdx.x >= nitems) return;
     extern __shared__ __align__(16) uint32_t t[];
-    __shared__ uint32_t red[kRedWords];  // the chunk flags and list length are unused here
+    __shared__ uint32_t red[kRedWords];
     const Item it = decode(hl, kSegReduce, blockIdx.x);
     const uint32_t tile = first_tile(hl, it) + it.idx;
-    reduce_full_tile<false>(t, jobs[s.order[it.pos]].state + (uint64_t)it.idx * kSlot, s.counts + tile,
+    reduce_full_tile(t, jobs[s.order[it.pos]].state + (uint64_t)it.idx * kSlot, s.counts + tile,
                             s.chunkmap + (uint64_t)tile * kMapWords, red);
 }
 
@@ -439,7 +439,7 @@ hipError_t batch_setup()
                                 (int)col_cap_pad(1));
     if (e != hipSuccess) return e;
     return hipFuncSetAttribute((const void *)batch_reduce_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)kReduceTileBytes);
+                               (int)(kReduceTileBytes + kBlockListBytes));
 }
 
 hipError_t launch_batch(void *jobs, uint32_t njobs, const BatchScratch &s, int col_cap, int mode, hipStream_t st,
@@ -469,7 +469,7 @@ hipError_t launch_batch(void *jobs, uint32_t njobs, const BatchScratch &s, int c
     hipLaunchKernelGGL(batch_plan_kernel, dim3(1), dim3(kPlanThreads), 0, st, j, njobs, s, e);
     hipLaunchKernelGGL(batch_tt_kernel, g(first), dim3(kBatchThreads), lds, st, j, s, mode == 0 ? 1 : 0);
     hipLaunchKernelGGL(batch_col_kernel, g(ncol), dim3(kColThreads), col_cap_pad(col_cap), st, j, s);
-    hipLaunchKernelGGL(batch_reduce_kernel, g(ntiles), dim3(kBatchThreads), kReduceTileBytes, st, j, s);
+    hipLaunchKernelGGL(batch_reduce_kernel, g(ntiles), dim3(kBatchThreads), kReduceTileBytes + kBlockListBytes, st, j, s);
     hipLaunchKernelGGL(batch_scan_kernel, dim3(ncu), dim3(256), 0, st, j, s);
     hipLaunchKernelGGL(batch_list_kernel, g((ntiles + 3) / 4), dim3(256), 0, st, j, s);
     return hipGetLastError();

@@ -94,11 +94,11 @@ __global__ __launch_bounds__(low_threads<MODE>()) __attribute__((amdgpu_waves_pe
                 const uint32_t k0 = 24 * wv / 32, k1 = (24 * wv + 23) / 32;
                 const uint32_t f0 = k0 < (uint32_t)kMapWords ? fw[k0] : 0u;
                 const uint32_t f1 = k1 < (uint32_t)kMapWords ? fw[k1] : 0u;
-                reduce_full_tile<true>(t, a.state + tile * a.ts, a.counts + tile, a.chunkmap + tile * kMapWords, red,
+                reduce_full_tile(t, a.state + tile * a.ts, a.counts + tile, a.chunkmap + tile * kMapWords, red,
                                        fw, f0, f1);
                 return;
             }
-            reduce_full_tile<true>(t, a.state + tile * a.ts, a.counts + tile, a.chunkmap + tile * kMapWords, red);
+            reduce_full_tile(t, a.state + tile * a.ts, a.counts + tile, a.chunkmap + tile * kMapWords, red);
             return;
         } else {
             load_tile<THREADS>(t, src, a.tw);
@@ -110,7 +110,7 @@ __global__ __launch_bounds__(low_threads<MODE>()) __attribute__((amdgpu_waves_pe
 
 static size_t low_lds_bytes(int mode, uint32_t tw)
 {
-    // the final reduce holds the tile with padded rows, then the list of its
+    // the final reduce holds the tile, then the list of its
     // non-zero blocks
     return mode == kLowReduceCount ? (size_t)kReduceTileBytes + kBlockListBytes : (size_t)tw * 4;
 }
@@ -132,7 +132,7 @@ __global__ __launch_bounds__(768) __attribute__((amdgpu_waves_per_eu(6))) void l
         const uint32_t k0 = 24 * wv / 32, k1 = (24 * wv + 23) / 32;
         const uint32_t f0 = k0 < (uint32_t)kMapWords ? fw[k0] : 0u;
         const uint32_t f1 = k1 < (uint32_t)kMapWords ? fw[k1] : 0u;
-        reduce_full_tile<true>(dyn, a.state + tl * a.ts, a.counts + tl, a.chunkmap + tl * kMapWords, red, fw, f0, f1);
+        reduce_full_tile(dyn, a.state + tl * a.ts, a.counts + tl, a.chunkmap + tl * kMapWords, red, fw, f0, f1);
     }
 }
 

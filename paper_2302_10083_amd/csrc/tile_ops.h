@@ -18,20 +18,10 @@ constexpr uint32_t kTileTriples = kTileBlocks / 3;  // 729 runs of digit 6 = 0, 
 // LDS words of a tile's reduce bookkeeping: set-bit count, map of non-zero
 // chunks, map of chunks non-zero as loaded, length of the non-zero block list
 constexpr uint32_t kRedWords = 2 * kMapWords + 2;
-// LDS layout of a full tile in the final reduce: its 27 rows of 648 words
-// (one value of digits 10..12 each) lie kRowStride words apart.  The round of
-// digits 7..9 has thread q read column q at words 648 (q / 24) + q % 24 + 24 c
-// (c < 27); with rows 664 (= 24 mod 32) words apart those words lie in bank
-// q + 24 c mod 32, so every 32 consecutive threads hit 32 different banks
-// (648 = 8 mod 32 would pair them two to a bank).
-constexpr uint32_t kRowWords = kTileWords / 27;                  // 648
-constexpr uint32_t kRowStride = kRowWords + 16;                 // 664
-constexpr uint32_t kPaddedTileWords = 27 * kRowStride;          // 17928
-__device__ __forceinline__ uint32_t padded_word(uint32_t w) { return w + 16 * (w / kRowWords); }
-// LDS bytes after the padded tile for the list of its non-zero blocks (uint16)
+// LDS of the final reduce of a full tile: its kTileWords words in order, then
+// the list of its non-zero blocks (uint16).
 constexpr uint32_t kBlockListBytes = (kTileBlocks * 2 + 15) / 16 * 16;
-// LDS bytes of the final reduce of a full tile (SPARSE adds the block list)
-constexpr uint32_t kReduceTileBytes = kPaddedTileWords * 4;
+constexpr uint32_t kReduceTileBytes = kTileWords * 4;
 
 // Apply Merge (MERGE) or Reduce to the K tile digits of every column of the
 // tile, the first of them at word stride s.
@@ -190,60 +180,6 @@ __device__ __forceinline__ void load_tile(uint32_t *t, const uint32_t *src, uint
 // (32 bit) in bits 15..18, every other field 0.
 constexpr int kRawBufferWord3 = 0x00020000;
 
-// Last Reduce round of a full tile (digits 10..12, rows of 648 words, padded
-// in LDS): thread q owns column q, reduces it, and writes it to HBM (the prime
-// bitmap); consecutive threads write consecutive words.  It also builds the
-// tile summary in `red` (zeroed before): red[0] = set bits, red[1..] = map of
-// the non-zero 64-word chunks.
-// A wavefront's words of row k are q0 + 648k .. q0 + 648k + 63 (q0 a multiple
-// of 64), so they start at 8 (k mod 8) inside a chunk and lie in chunks c(k)
-// and c(k) + 1.  Everything per row is wave-uniform: the stores are raw buffer
-// stores with the row offset in a scalar register, and the chunk map is
-// gathered as two bits per row in scalar registers (work only for rows with a
-// set bit), written at the end by lane k for row k.
-__device__ __forceinline__ void last_round_to_hbm(uint32_t *t, uint32_t *dst, uint32_t *red)
-{
-    constexpr uint32_t S = kRowWords;  // 648
-    const uint32_t q = threadIdx.x, lane = lane_id();
-    const uint32_t q0 = __builtin_amdgcn_readfirstlane(q & ~63u);  // the wavefront's first column
-    if (q0 >= S) return;                                         // wave-uniform
-    const bool mine = q < S;                                     // the last wavefront holds 8 columns
-    uint32_t x[27], any = 0;
-    // lanes past the last column read column q0's words and are zeroed
-    const uint32_t qc = mine ? q : q0;
-    static_for<27>([&](auto ci) { x[decltype(ci)::value] = t[qc + decltype(ci)::value * kRowStride]; });
-    if (q0 + 64 > S) static_for<27>([&](auto ci) { x[decltype(ci)::value] = mine ? x[decltype(ci)::value] : 0u; });
-    static_for<27>([&](auto ci) { any |= x[decltype(ci)::value]; });
-    if (__ballot(any != 0u) != 0) reg_reduce<3>(x);  // zero columns stay zero
-    // row lk = lane (lanes 0..26): its first chunk
-    const uint32_t lk = lane < 27u ? lane : 0u;
-    const uint32_t ck = (q0 + lk * S) / kChunkWords;
-    // the tile's words in HBM as a raw buffer: row k at scalar offset 2592 k;
-    // lanes past the last column get an offset beyond the tile, so their
-    // stores are dropped by the buffer's range check
-    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(dst, 0, (int)(kTileWords * 4), kRawBufferWord3);
-    const int voff = mine ? (int)(4 * q) : 0x40000000;
-    uint64_t nzc = 0;  // bit 2k: chunk c(k) holds a set bit; bit 2k + 1: chunk c(k) + 1
-    uint32_t c = 0;
-    static_for<27>([&](auto ci) {
-        constexpr uint32_t k = decltype(ci)::value;
-        constexpr uint32_t split = 64 - 8 * (k % 8);  // lanes below it are in chunk c(k)
-        constexpr uint64_t lo = split >= 64 ? ~0ull : (1ull << (split & 63u)) - 1ull;
-        __builtin_amdgcn_raw_buffer_store_b32(x[k], rs, voff, (int)(4 * k * S), 0);
-        c += __popc(x[k]);
-        const uint64_t m = __ballot(x[k] != 0u);
-        if (m != 0) {
-            nzc |= ((m & lo) != 0 ? 1ull : 0ull) << (2 * k);
-            nzc |= ((m & ~lo) != 0 ? 1ull : 0ull) << (2 * k + 1);
-        }
-    });
-    const uint32_t two = (uint32_t)(nzc >> (2 * lk)) & 3u;
-    if (lane < 27u && (two & 1u)) atomicOr(&red[1 + ck / 32], 1u << (ck % 32));
-    if (lane < 27u && (two & 2u)) atomicOr(&red[1 + (ck + 1) / 32], 1u << ((ck + 1) % 32));
-    c = wave_sum32(c);
-    if (lane == 0 && c != 0) atomicAdd(&red[0], c);
-}
-
 // Run q of a full tile (q < 729): its three blocks with digit 6 = 0, 1, *,
 // 96 contiguous bytes of the tile in HBM (16-byte aligned).
 struct TileRun {
@@ -292,18 +228,18 @@ __device__ __forceinline__ void mark_run_chunks(const uint32_t (&b0)[kBlockWords
     if (in1 != 0u) atomicOr(&innz[(c0 + 1) / 32], 1u << ((c0 + 1) % 32));
 }
 
-// Block blk of a padded LDS tile.
+// Block blk of an LDS tile.
 __device__ __forceinline__ void put_block(uint32_t *t, uint32_t blk, const uint32_t (&b)[kBlockWords])
 {
-    uint4 *dst = reinterpret_cast<uint4 *>(t + padded_word(kBlockWords * blk));
+    uint4 *dst = reinterpret_cast<uint4 *>(t + kBlockWords * blk);
     dst[0] = make_uint4(b[0], b[1], b[2], b[3]);
     dst[1] = make_uint4(b[4], b[5], b[6], b[7]);
 }
 
-// Block blk of a padded LDS tile, into registers.
+// Block blk of an LDS tile, into registers.
 __device__ __forceinline__ void get_block(const uint32_t *t, uint32_t blk, uint32_t (&b)[kBlockWords])
 {
-    const uint4 *src = reinterpret_cast<const uint4 *>(t + padded_word(kBlockWords * blk));
+    const uint4 *src = reinterpret_cast<const uint4 *>(t + kBlockWords * blk);
     const uint4 lo = src[0], hi = src[1];
     b[0] = lo.x; b[1] = lo.y; b[2] = lo.z; b[3] = lo.w;
     b[4] = hi.x; b[5] = hi.y; b[6] = hi.z; b[7] = hi.w;
@@ -357,7 +293,7 @@ __device__ __forceinline__ void reduce_block_list(uint32_t *t, const uint16_t *b
 }
 
 // The tile's chunks that were non-zero as loaded (`innz`), stored from the
-// padded LDS tile to HBM at dst (the other chunks were zero there and stay
+// LDS tile to HBM at dst (the other chunks were zero there and stay
 // zero), with the tile summary in red: red[0] += set bits, red[1 + k / 32]
 // bit k for the chunks non-zero now.  Wavefront w takes chunks 23 w .. 23 w +
 // 22 (12 wavefronts); lane j holds word j of a chunk, so each store is one
@@ -381,46 +317,13 @@ __device__ __forceinline__ void store_marked_chunks(const uint32_t *t, uint32_t 
         bits &= bits - 1u;
         const uint32_t w = k * kChunkWords + lane;
         const bool in = w < kTileWords;  // the last chunk holds 24 words
-        const uint32_t v = in ? t[padded_word(w)] : 0u;
+        const uint32_t v = in ? t[w] : 0u;
         c += __popc(v);
         if (__ballot(v != 0u) != 0 && lane == 0) atomicOr(&red[1 + k / 32], 1u << (k % 32));
         __builtin_amdgcn_raw_buffer_store_b32(v, rs, in ? (int)(4 * w) : 0x40000000, 0, 0);
     }
     c = wave_sum32(c);
     if (lane == 0 && c != 0) atomicAdd(&red[0], c);
-}
-
-// Reduce of digit 6 across the three blocks of run q and of digits 1..5
-// inside each block, into blocks 3q .. 3q+2 of the padded LDS tile.  Digit 6 comes
-// first (the order of the reduced dimensions is free): the blocks with digit
-// 6 = 0 or 1 lose what the * block holds.  A wavefront whose runs are all
-// zero skips the arithmetic.
-__device__ __forceinline__ void reduce_run_to_lds(uint32_t *t, const TileRun &r, uint32_t q)
-{
-    uint32_t b0[kBlockWords], b1[kBlockWords], b2[kBlockWords];
-    unpack_run(r, b0, b1, b2);
-    uint32_t any = 0;
-    static_for<kBlockWords>([&](auto wi) {
-        constexpr int w = decltype(wi)::value;
-        any |= b0[w] | b1[w] | b2[w];
-    });
-    if (__ballot(any != 0u) != 0) {
-        static_for<kBlockWords>([&](auto wi) {
-            constexpr int w = decltype(wi)::value;
-            b0[w] &= ~b2[w];
-            b1[w] &= ~b2[w];
-        });
-        block_reduce(b0);
-        put_block(t, 3 * q, b0);
-        block_reduce(b1);
-        put_block(t, 3 * q + 1, b1);
-        block_reduce(b2);
-        put_block(t, 3 * q + 2, b2);
-    } else {
-        put_block(t, 3 * q, b0);
-        put_block(t, 3 * q + 1, b1);
-        put_block(t, 3 * q + 2, b2);
-    }
 }
 
 // Reduce of digit 6 across the three blocks of run q into the LDS tile, the
@@ -465,26 +368,19 @@ __device__ __forceinline__ void run_digit6_to_lds(uint32_t *t, const TileRun &r,
 }
 
 // Final Reduce of a full tile in HBM (kTileWords words at `tile`, 16-byte
-// aligned; 768 threads; kReduceTileBytes of LDS at t, rows padded as
-// described at kRowStride): thread q < 729 loads run q and digit 6 is reduced
-// on the way into LDS.  It also writes the tile summary: *count = its set
-// bits, map[0..kMapWords) = its non-zero 64-word chunks.  `red` is kRedWords
-// words of LDS.
-// Without SPARSE (the denser small tiles of a batch) digits 1..5 are reduced
-// on the way in too, digits 7..9 in LDS, and digits 10..12 in the last round
-// straight back to HBM, over every word of the tile.
-// SPARSE is for a single large function, whose tiles are mostly zero by this
-// pass.  The blocks non-zero after digit 6 are listed (kBlockListBytes of LDS
-// after the padded tile); each gets digits 1..5 and 7..12 in one step
-// (reduce_block_list), and only the chunks non-zero as loaded are stored
-// (store_marked_chunks): a Reduce only clears bits, so the others are zero in
-// HBM already.  `flags` (kMapWords words, or nullptr) marks the chunks that
-// may hold a set bit: the others are zero in HBM, so their runs are not
-// loaded.
-// f0, f1 are the words 24 w / 32 and (24 w + 23) / 32 of the flags for the
-// calling wavefront w (its 64 runs cover chunks 24 w .. 24 w + 23), loaded
-// ahead by the caller.
-template <bool SPARSE>
+// aligned; 768 threads; kReduceTileBytes + kBlockListBytes of LDS at t):
+// thread q < 729 loads run q and digit 6
+// is reduced on the way into LDS.  The blocks non-zero after it are listed;
+// each gets digits 1..5 and 7..12 in one step (reduce_block_list), and only
+// the chunks non-zero as loaded are stored (store_marked_chunks): a Reduce
+// only clears bits, so the others are zero in HBM already.  It also writes
+// the tile summary: *count = its set bits, map[0..kMapWords) = its non-zero
+// 64-word chunks.  `red` is kRedWords words of LDS.
+// `flags` (kMapWords words, or nullptr) marks the chunks that may hold a set
+// bit: the others are zero in HBM, so their runs are not loaded.  f0, f1 are
+// the words 24 w / 32 and (24 w + 23) / 32 of the flags for the calling
+// wavefront w (its 64 runs cover chunks 24 w .. 24 w + 23), loaded ahead by
+// the caller.
 __device__ __forceinline__ void reduce_full_tile(uint32_t *t, uint32_t *tile, uint32_t *count, uint32_t *map,
                                                  uint32_t *red, const uint32_t *flags = nullptr, uint32_t f0 = 0u,
                                                  uint32_t f1 = 0u)
@@ -492,61 +388,30 @@ __device__ __forceinline__ void reduce_full_tile(uint32_t *t, uint32_t *tile, ui
     uint32_t *innz = red + kMapWords + 1;
     if (threadIdx.x < kRedWords) red[threadIdx.x] = 0;
     const uint32_t q = threadIdx.x;
-    if constexpr (SPARSE) {
-        uint16_t *blist = reinterpret_cast<uint16_t *>(t + kPaddedTileWords);
-        uint32_t *nlist = red + kRedWords - 1;
-        TileRun r;
-        if (flags != nullptr) {
-            const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
-            const uint32_t k0 = 24 * wv / 32;
-            const uint32_t c0 = 24 * q / kChunkWords, c1 = (24 * q + 23) / kChunkWords;
-            const uint32_t g0 = c0 / 32 == k0 ? f0 : f1, g1 = c1 / 32 == k0 ? f0 : f1;
-            const bool need = q < kTileTriples && (((g0 >> (c0 % 32)) | (g1 >> (c1 % 32))) & 1u);
-            if (need) load_run(r, tile, q);
-            else static_for<6>([&](auto ki) { r.u[decltype(ki)::value] = make_uint4(0u, 0u, 0u, 0u); });
-            __syncthreads();  // flags and list length zeroed before they are set
-            // the chunks non-zero as loaded (a subset of the flagged ones):
-            // only those are stored
-            run_digit6_to_lds<true>(t, r, q, q < kTileTriples, innz, blist, nlist);
-        } else {
-            __syncthreads();  // flags and list length zeroed before they are set
-            if (q < kTileTriples) load_run(r, tile, q);
-            run_digit6_to_lds<true>(t, r, q, q < kTileTriples, innz, blist, nlist);
-        }
-        __syncthreads();
-        reduce_block_list(t, blist, *nlist);
-        __syncthreads();
-        store_marked_chunks(t, tile, red, innz);
-        __syncthreads();
-        if (threadIdx.x == 0) *count = red[0];
-        if (threadIdx.x < kMapWords) map[threadIdx.x] = red[1 + threadIdx.x];
-        return;
+    uint16_t *blist = reinterpret_cast<uint16_t *>(t + kTileWords);
+    uint32_t *nlist = red + kRedWords - 1;
+    TileRun r;
+    if (flags != nullptr) {
+        const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+        const uint32_t k0 = 24 * wv / 32;
+        const uint32_t c0 = 24 * q / kChunkWords, c1 = (24 * q + 23) / kChunkWords;
+        const uint32_t g0 = c0 / 32 == k0 ? f0 : f1, g1 = c1 / 32 == k0 ? f0 : f1;
+        const bool need = q < kTileTriples && (((g0 >> (c0 % 32)) | (g1 >> (c1 % 32))) & 1u);
+        if (need) load_run(r, tile, q);
+        else static_for<6>([&](auto ki) { r.u[decltype(ki)::value] = make_uint4(0u, 0u, 0u, 0u); });
+        __syncthreads();  // flags and list length zeroed before they are set
+        // the chunks non-zero as loaded (a subset of the flagged ones):
+        // only those are stored
+        run_digit6_to_lds<true>(t, r, q, q < kTileTriples, innz, blist, nlist);
     } else {
-        if (q < kTileTriples) {
-            TileRun r;
-            load_run(r, tile, q);
-            reduce_run_to_lds(t, r, q);
-        }
+        __syncthreads();  // flags and list length zeroed before they are set
+        if (q < kTileTriples) load_run(r, tile, q);
+        run_digit6_to_lds<true>(t, r, q, q < kTileTriples, innz, blist, nlist);
     }
     __syncthreads();
-    // digits 7..9: column q < 648 of the padded tile (see kRowStride)
-    for (uint32_t q = threadIdx.x; q < kRowWords; q += blockDim.x) {
-        uint32_t *col = t + (q / 24) * kRowStride + q % 24;
-        uint32_t x[27], any = 0;
-        static_for<27>([&](auto ci) {
-            constexpr int c = decltype(ci)::value;
-            x[c] = col[24 * c];
-            any |= x[c];
-        });
-        if (__ballot(any != 0u) == 0) continue;  // zero columns stay zero
-        reg_reduce<3>(x);
-        static_for<26>([&](auto ci) {
-            constexpr int c = decltype(ci)::value;
-            col[24 * c] = x[c];
-        });
-    }
+    reduce_block_list(t, blist, *nlist);
     __syncthreads();
-    last_round_to_hbm(t, tile, red);  // digits 10..12
+    store_marked_chunks(t, tile, red, innz);
     __syncthreads();
     if (threadIdx.x == 0) *count = red[0];
     if (threadIdx.x < kMapWords) map[threadIdx.x] = red[1 + threadIdx.x];
