@@ -466,6 +466,54 @@ def test_sibling_form_of_the_reduce(n, kind, seed):
     assert by_sib.any() and (M & ~by_sib).any()
 
 
+@pytest.mark.parametrize("n,kind,seed", [(6, 0.8, 1), (7, "dnf", 2), (8, 0.9, 3), (9, "dnf", 4)])
+def test_reduce_in_staged_one_step_groups(n, kind, seed):
+    """Reading 7 as the final tile reduce uses it: the dimensions split into
+    groups taken one after another, each group reduced in one step from the
+    values the previous groups left (x loses its bit when S(x[i <- *]) is set
+    for some i of the group with x_i binary), give the primes; checked on the
+    kernels' order (top digits first, then the digit above the in-block ones,
+    then the in-block digits with the rest in one step) and on random
+    orderings and partitions."""
+    if kind == "dnf":
+        tt = inputs.dnf(n, 8, 1, 4, 9400 + seed)
+    else:
+        tt = inputs.bernoulli(n, kind, 9400 + seed)
+    M = np.zeros(3**n, dtype=bool)
+    M[sorted(oracle.bitmap_to_set(n, oracle.enum_M(n, tt)))] = True
+    _, O, _ = oracle.primes(n, tt)
+    want = oracle.bitmap_to_set(n, O)
+    rho = np.arange(3**n, dtype=np.int64)
+    p3 = 3 ** np.arange(n, dtype=np.int64)
+    digs = (rho[:, None] // p3[None, :]) % 3
+
+    def staged(groups):
+        S = M.copy()
+        for g in groups:
+            kill = np.zeros_like(S)
+            for i in g:
+                s = rho[digs[:, i] != 2]
+                kill[s] |= S[s + (2 - digs[s, i]) * p3[i]]
+            S &= ~kill
+        return set(np.flatnonzero(S).tolist())
+
+    # the kernels' order scaled down (0-based digits): the top group, the group
+    # below it, one digit lo, then the digits under lo with those between lo
+    # and the lower group in one step
+    lo = (n - 4) // 2
+    kernels = [[n - 2, n - 1], [n - 4, n - 3], [lo], list(range(lo)) + list(range(lo + 1, n - 4))]
+    assert sorted(d for g in kernels for d in g) == list(range(n))
+    assert staged(kernels) == want
+    rng = random.Random(9400 + seed)
+    for _ in range(6):
+        order = list(range(n))
+        rng.shuffle(order)
+        cuts = sorted(rng.sample(range(1, n), rng.randint(0, n - 1)))
+        groups = [order[a:b] for a, b in zip([0] + cuts, cuts + [n])]
+        assert staged(groups) == want, groups
+    assert want and len(want) < int(M.sum())
+
+
 # ----------------------------------------------------------------------------
 # the ranged ("streaming") O sweep and the block digests built on it
 
