@@ -39,8 +39,7 @@ template <int MODE>
 __host__ __device__ constexpr int low_threads()
 {
     // the tile passes over HBM-resident states use one run of three blocks
-    // per thread on the way in (729 runs in a full tile) and one 27-word
-    // column per thread in the LDS rounds (648 columns)
+    // per thread on the way in (729 runs in a full tile)
     return (MODE == kLowReduceCount || MODE == kLowCount) ? 768 : kLowThreads;
 }
 
