@@ -319,3 +319,51 @@ def test_row_flags_equal_flag_free_plan_n24(kind):
     assert results[0] == results[1]
     del state
     torch.cuda.empty_cache()
+
+
+def test_flag_units_bound_the_flagged_passes():
+    """dqmc_flag_units after the flagged n = 24 call (c3 recipe): every figure
+    is a whole number of rows, runs or chunks within its dense bound; the
+    chunks the final bitmap holds a bit in (counted from the state) are within
+    both the final reduce's store bound and the rows the reduce of digits
+    13..18 was given (a chunk of a tile is a row segment of that pass); a
+    flag-free plan reports nothing."""
+    import torch
+
+    from paper_2302_10083_amd import dqmc
+
+    n, tiles, stride = 24, 3**12, 17504
+    ctx = context()
+    ttd = ctx.tt_to_device(inputs.config("c3_n24_dnf2000_noise"))
+    state = ctx.new_state(n)
+    count = torch.zeros(1, dtype=torch.int64, device=ctx.torch_device)
+    try:
+        dqmc.dqmc_primes(ctx.ctx, n, ttd, state, None, 0, count)
+        torch.cuda.synchronize()
+        u = dqmc.dqmc_flag_units(ctx.ctx)
+        assert u["used"]
+        rows, runs, stores = u["reduce13_rows_bytes"], u["final_runs_bytes"], u["final_store_bytes"]
+        assert rows % 128 == 0 and 0 < rows <= 729 * 729 * (273 * 256 + 128)
+        assert runs % 96 == 0 and 0 < runs <= tiles * 729 * 96
+        assert stores % 32 == 0 and 0 < stores <= tiles * (273 * 256 + 96)
+        # chunks of the final bitmap with a set bit: 273 of 64 words and one of 24 per tile
+        S = state.view(tiles, stride)
+        full = last = 0
+        for t0 in range(0, tiles, 1 << 15):
+            blk = S[t0:t0 + (1 << 15)]
+            full += int(blk[:, :273 * 64].reshape(-1, 273, 64).ne(0).any(dim=2).sum())
+            last += int(blk[:, 273 * 64:17496].ne(0).any(dim=1).sum())
+        log("flag units: rows %.2f GB, runs %.2f GB, store bound %.2f GB; %d + %d non-zero chunks"
+            % (rows / 1e9, runs / 1e9, stores / 1e9, full, last))
+        assert full + last > 0
+        assert 256 * full + 96 * last <= stores
+        assert 256 * full + 128 * last <= rows
+        dqmc.dqmc_set_plan(ctx.ctx, n, [4, 4, 4])
+        dqmc.dqmc_primes(ctx.ctx, n, ttd, state, None, 0, count)
+        torch.cuda.synchronize()
+        u = dqmc.dqmc_flag_units(ctx.ctx)
+        assert not u["used"] and u["reduce13_rows_bytes"] == u["final_runs_bytes"] == u["final_store_bytes"] == 0
+    finally:
+        dqmc.dqmc_set_plan(ctx.ctx, n, [])
+        del state
+        torch.cuda.empty_cache()
