@@ -378,6 +378,7 @@ __global__ __launch_bounds__(256) void batch_list_kernel(const dqmc_job *jobs, B
     const uint32_t nitems = hl[kHSegSize + kSegList];
     if (blockIdx.x * 4 >= nitems) return;
     __shared__ uint16_t nzs[4][kTileChunks];
+    __shared__ uint64_t stage[4][kListStage];
     const uint32_t wv = threadIdx.x / 64, i = blockIdx.x * 4 + wv;
     if (i >= nitems) return;
     const Item it = decode(hl, kSegList, i);
@@ -388,7 +389,7 @@ __global__ __launch_bounds__(256) void batch_list_kernel(const dqmc_job *jobs, B
     const uint64_t cap = j.list != nullptr ? j.list_cap : 0;
     if (c == 0 || off >= cap) return;
     list_tile(j.state + (uint64_t)it.idx * kSlot, kTileL, (uint64_t)it.idx * kTileL, off,
-              s.chunkmap + (uint64_t)tile * kMapWords, j.list, cap, nzs[wv]);
+              s.chunkmap + (uint64_t)tile * kMapWords, j.list, cap, nzs[wv], stage[wv]);
 }
 
 uint64_t batch_scratch_bytes(uint32_t cap)

@@ -124,6 +124,7 @@ __global__ __launch_bounds__(kListThreads) void list_kernel(ListArgs a)
 {
     constexpr int NW = kListThreads / 64;
     __shared__ uint16_t nzs[NW][kTileChunks];
+    __shared__ uint64_t stage[NW][kListStage];
     const uint32_t wv = threadIdx.x / 64;
     const uint64_t nwaves = (uint64_t)gridDim.x * NW;
     for (uint64_t tile = (uint64_t)blockIdx.x * NW + wv; tile < a.ntiles; tile += nwaves) {
@@ -131,7 +132,7 @@ __global__ __launch_bounds__(kListThreads) void list_kernel(ListArgs a)
         const uint64_t off = a.offs[tile];
         if (c == 0 || off >= a.cap) continue;
         list_tile(a.state + tile * a.ts, a.tw, tile * a.tw, off, a.chunkmap + tile * kMapWords, a.list, a.cap, nzs[wv],
-                  a.rho0);
+                  stage[wv], a.rho0);
     }
 }
 

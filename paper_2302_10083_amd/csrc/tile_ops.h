@@ -417,18 +417,25 @@ __device__ __forceinline__ void reduce_full_tile(uint32_t *t, uint32_t *tile, ui
     if (threadIdx.x < kMapWords) map[threadIdx.x] = red[1 + threadIdx.x];
 }
 
+// Entries of a wavefront's list staging buffer in LDS (see list_tile).
+constexpr uint32_t kListStage = 512;
+
 // Ordered list of the set bits of one tile of a bitmap in HBM, by one
 // wavefront: the tile's non-zero chunks (bit k of map = chunk k, from the
 // tile summary) are listed in order, and taken sixteen at a time: lane l
 // holds words 16 (l mod 4) .. 16 (l mod 4) + 15 of the (l / 4)-th chunk of
 // the batch, so lane order is word order.  One wave scan of the lanes' bit
-// counts places every lane's bits, which it writes in order at `off` plus the
-// running count as cube indices rho0 + rho_of_word(wbase + word) + bit
-// (wbase a multiple of 8).  Entries at or past cap are dropped.  nz holds
-// kTileChunks entries private to the wave.
+// counts places every lane's bits, as cube indices rho0 +
+// rho_of_word(wbase + word) + bit (wbase a multiple of 8), at `off` plus the
+// running count.  They go through `stage` (kListStage entries private to the
+// wave) in list order, so that the wave writes the batch's entries to HBM as
+// consecutive 8-byte words (lanes writing their own bits would scatter every
+// store over up to 64 lines); a batch's entries past kListStage are written
+// directly.  Entries at or past cap are dropped.  nz holds kTileChunks
+// entries private to the wave.
 __device__ __forceinline__ void list_tile(const uint32_t *src, uint32_t tw, uint64_t wbase, uint64_t off,
                                           const uint32_t *map, uint64_t *list, uint64_t cap, uint16_t *nz,
-                                          uint64_t rho0 = 0)
+                                          uint64_t *stage, uint64_t rho0 = 0)
 {
     constexpr int kSpan = 16;  // words per lane
     const uint32_t lane = lane_id();
@@ -473,19 +480,29 @@ __device__ __forceinline__ void list_tile(const uint32_t *src, uint32_t tw, uint
         uint32_t cnt = 0;
         static_for<kSpan>([&](auto ji) { cnt += __popc(v[decltype(ji)::value]); });
         const uint32_t incl = wave_inclusive_scan32(cnt);
-        uint64_t p = run + (incl - cnt);
+        const uint32_t nb = __shfl(incl, 63, 64);  // the batch's entries
+        uint32_t at = incl - cnt;                   // this lane's first, in the batch
         const uint64_t rb = rho0 + rho_of_word(wbase + w0);  // w0 is a multiple of 8
         static_for<kSpan>([&](auto ji) {
             constexpr int j = decltype(ji)::value;
             uint32_t x = v[j];
             const uint64_t rj = rb + (uint64_t)(kBlockCubes * (j / 8) + 32 * (j % 8));
-            while (x != 0u && p < cap) {
+            while (x != 0u) {
                 const uint32_t b = __builtin_ctz(x);
                 x &= x - 1u;
-                list[p++] = rj + b;
+                if (at < kListStage) stage[at] = rj + b;
+                else if (run + at < cap) list[run + at] = rj + b;
+                ++at;
             }
         });
-        run += __shfl(incl, 63, 64);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        const uint32_t ns = nb < kListStage ? nb : kListStage;
+        for (uint32_t i = lane; i < ns; i += 64)
+            if (run + i < cap) list[run + i] = stage[i];
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();  // the stage is rewritten by the next batch
+        run += nb;
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();  // nz is reused by the wave's next tile
